@@ -1,0 +1,110 @@
+"""CPU oracle for butterfly counting and tip decomposition.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg use this package to check and time the GPU path.  The
+product library never imports it.
+
+* ``count(g)``            per-vertex butterfly counts of both sides + total
+                          (plain 2-hop definition, notation table of the paper)
+* ``bup(g, side)``        tip numbers by sequential bottom-up peeling (Alg. 2)
+* ``support_in(g, side, member, query)``
+                          f_x(S) for sampled vertices, for property checks
+* ``brute``               exponential brute force for tiny graphs
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tip_oracle.cpp")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with the host C++ compiler; returns the .so path."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC",
+                               _SRC, "-o", tmp])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load(path: str | None = None):
+    global _lib
+    with _lock:
+        if path is not None:
+            lib = ctypes.CDLL(path)
+        elif _lib is None:
+            lib = _lib = ctypes.CDLL(build())
+        else:
+            return _lib
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    p = ctypes.c_void_p
+    lib.oracle_count.argtypes = [i32, i32, i64, p, p, p, p, p]
+    lib.oracle_count.restype = ctypes.c_int
+    lib.oracle_bup.argtypes = [i32, i32, i64, p, p, i32, p, p, p]
+    lib.oracle_bup.restype = ctypes.c_int
+    lib.oracle_support_in.argtypes = [i32, i32, i64, p, p, i32, p, p, i64, p]
+    lib.oracle_support_in.restype = ctypes.c_int
+    return lib
+
+
+def _ptr(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _edges(g):
+    eu = np.ascontiguousarray(g.eu, dtype=np.int32)
+    ev = np.ascontiguousarray(g.ev, dtype=np.int32)
+    return eu, ev
+
+
+def count(g, lib=None):
+    """Returns (bfly_u int64[n_u], bfly_v int64[n_v], total int)."""
+    lib = lib or _load()
+    eu, ev = _edges(g)
+    bu = np.zeros(g.n_u, np.int64)
+    bv = np.zeros(g.n_v, np.int64)
+    tot = np.zeros(1, np.int64)
+    rc = lib.oracle_count(g.n_u, g.n_v, g.m, _ptr(eu), _ptr(ev), _ptr(bu), _ptr(bv), _ptr(tot))
+    if rc != 0:
+        raise ValueError("oracle_count: invalid graph")
+    return bu, bv, int(tot[0])
+
+
+def bup(g, side: int = 0, lib=None):
+    """Returns (theta int64[n_side], peel order int32[n_side], wedges int)."""
+    lib = lib or _load()
+    eu, ev = _edges(g)
+    n = g.n_u if side == 0 else g.n_v
+    theta = np.zeros(n, np.int64)
+    order = np.zeros(n, np.int32)
+    wedges = np.zeros(1, np.int64)
+    rc = lib.oracle_bup(g.n_u, g.n_v, g.m, _ptr(eu), _ptr(ev), side, _ptr(theta),
+                        _ptr(order), _ptr(wedges))
+    if rc != 0:
+        raise ValueError("oracle_bup: invalid graph or side")
+    return theta, order, int(wedges[0])
+
+
+def support_in(g, side: int, member: np.ndarray, query: np.ndarray, lib=None) -> np.ndarray:
+    """f_x(S) for each x in ``query``; ``member`` is a 0/1 mask of S."""
+    lib = lib or _load()
+    eu, ev = _edges(g)
+    member = np.ascontiguousarray(member, dtype=np.uint8)
+    query = np.ascontiguousarray(query, dtype=np.int32)
+    out = np.zeros(query.shape[0], np.int64)
+    rc = lib.oracle_support_in(g.n_u, g.n_v, g.m, _ptr(eu), _ptr(ev), side, _ptr(member),
+                               _ptr(query), query.shape[0], _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle_support_in: invalid argument")
+    return out
