@@ -1,0 +1,136 @@
+/*
+ * tip.h -- C ABI of libtip: butterfly counting and tip decomposition of
+ * bipartite graphs on an AMD Instinct MI355X (gfx950).
+ *
+ * Method: Lakhotia, Kannan, Prasanna, De Rose, "RECEIPT: REfine CoarsE-grained
+ * IndePendent Tasks for Parallel Tip decomposition of Bipartite Graphs"
+ * (arXiv 2010.08695).
+ *
+ * Conventions shared by every call
+ *   - A graph is given as a COO edge list: edge i joins U vertex eu[i] and V
+ *     vertex ev[i]; ids are 0-based, eu[i] < n_u, ev[i] < n_v.  Duplicate
+ *     edges are merged (the method is defined on simple graphs).  Isolated
+ *     vertices are allowed and get count 0 and tip number 0.
+ *   - All counts and tip numbers are exact signed 64-bit integers.
+ *   - The caller owns every buffer.  Host-pointer calls copy their inputs to
+ *     the device, allocate and free their own device memory and return after
+ *     the results are in the caller's host buffers.
+ *   - Every call returns a tip_status.  Nothing throws across the ABI.  On an
+ *     error the output buffers are unspecified and tip_last_error() describes
+ *     the failure.  Argument errors (TIP_EINVAL) are detected on the host
+ *     before any device work and leave the outputs untouched.
+ *   - Calls may be made concurrently from several host threads; each call
+ *     uses its own device memory and stream.
+ */
+#ifndef TIP_H
+#define TIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tip_status;
+enum {
+    TIP_OK = 0,
+    TIP_EINVAL = -1,    /* NULL required pointer, id out of range, bad side, negative or too large size */
+    TIP_ENOMEM = -2,    /* device or host allocation failed, or the workspace is too small */
+    TIP_EDEVICE = -3,   /* a HIP runtime error; tip_last_error() holds the HIP message */
+    TIP_EOVERFLOW = -4, /* counts could exceed INT64_MAX (checked before counting) */
+    TIP_EBUSY = -5      /* reserved */
+};
+
+/* The vertex side to decompose.  The paper decomposes one side at a time
+ * (Background section); deciding V is deciding U of the transposed graph. */
+typedef enum { TIP_SIDE_U = 0, TIP_SIDE_V = 1 } tip_side;
+
+/* Host COO edge list.  m <= 2^31 - 1. */
+typedef struct {
+    int32_t n_u, n_v;
+    int64_t m;
+    const int32_t* eu; /* [m] U ids */
+    const int32_t* ev; /* [m] V ids */
+} tip_edges;
+
+/* Options.  Zero-initialised means defaults. */
+typedef struct {
+    int32_t P;       /* number of tip-number ranges of the coarse-grained step
+                        (Alg. 3); 0 = 150, the value the paper's experiments
+                        settle on; at most 65535 */
+    int32_t flags;   /* reserved, must be 0 */
+    int32_t tune[8]; /* reserved, must be 0 */
+} tip_opts;
+
+/* Work and time accounting of one decomposition (NULL = not wanted). */
+typedef struct {
+    int64_t wedges_count; /* wedges traversed by per-vertex counting (Alg. 1) */
+    int64_t wedges_cd;    /* wedges traversed by coarse-grained peeling (Alg. 3) */
+    int64_t wedges_fd;    /* wedges traversed by fine-grained peeling (Alg. 4) */
+    int64_t pair_updates; /* support decrements applied (distinct peeled/live pairs) */
+    int64_t rounds;       /* coarse-grained peeling iterations (synchronisation rounds) */
+    int64_t subsets;      /* vertex subsets created (P, plus 1 if vertices were left over) */
+    int64_t fd_levels;    /* peeling levels run by the fine-grained step */
+    int64_t spills;       /* repeat keys that did not fit in LDS (kept in HBM) */
+    int64_t skipped;      /* peeled vertices with no butterfly left (no update needed) */
+    int64_t m_unique;     /* edges after duplicate merging */
+    double t_ingest_ms, t_count_ms, t_cd_ms, t_fd_ms, t_total_ms; /* device time per phase */
+} tip_stats;
+
+/* Per-vertex butterfly counts of both sides (Alg. 1, Section 2.1) and the
+ * total number of butterflies.  bfly_u [n_u], bfly_v [n_v] and total may each
+ * be NULL.  Sum of bfly_u = sum of bfly_v = 2 * total. */
+tip_status tip_count_butterflies(const tip_edges* g, int64_t* bfly_u, int64_t* bfly_v, int64_t* total);
+
+/* Tip numbers of every vertex of `side` (Def. 1; RECEIPT: Alg. 3 then Alg. 4).
+ * theta has n_u (side U) or n_v (side V) entries.  opt and st may be NULL. */
+tip_status tip_decompose(const tip_edges* g, int32_t side, int64_t* theta, const tip_opts* opt, tip_stats* st);
+
+/* tip_decompose plus the coarse-grained state (Alg. 3 outputs), for checking:
+ *   subset       [n_side]  index i of the range R_i = [bounds[i], bounds[i+1])
+ *                          holding the vertex's tip number, or NULL
+ *   init_support [n_side]  support of the vertex when its subset's range
+ *                          began (the support-initialisation vector), or NULL
+ *   bounds       [P + 2]   range bounds; bounds[0] = 0, the last used bound of
+ *                          a left-over subset is INT64_MAX, or NULL
+ *   n_subsets              number of subsets created, or NULL */
+tip_status tip_decompose_ex(const tip_edges* g, int32_t side, int64_t* theta, const tip_opts* opt,
+                            tip_stats* st, int32_t* subset, int64_t* init_support, int64_t* bounds,
+                            int32_t* n_subsets);
+
+/* Decomposes n independent graphs: graph k's side sides[k] into thetas[k].
+ * st may be NULL or point to n entries. */
+tip_status tip_decompose_batch(int32_t n, const tip_edges* gs, const int32_t* sides, int64_t* const* thetas,
+                               const tip_opts* opt, tip_stats* st);
+
+/* Device-memory bytes tip_decompose_async needs for a graph of this size
+ * (m counted before duplicate merging). */
+tip_status tip_workspace_size(int32_t n_u, int32_t n_v, int64_t m, int32_t side, const tip_opts* opt,
+                              size_t* bytes);
+
+/* Device-resident variant for callers that keep graphs on the GPU.
+ *   d_eu, d_ev  device COO arrays [m]
+ *   d_theta     device output [n_u or n_v]
+ *   d_workspace device buffer of ws_bytes >= tip_workspace_size(...)
+ *   stream      a hipStream_t (NULL = the default stream)
+ * Uses no device memory besides the workspace and the outputs and issues all
+ * work on `stream`.  The call returns once the decomposition is complete (the
+ * coarse-grained step reads a few control words back between peeling rounds).
+ * Id range errors are detected on the device and reported as TIP_EINVAL. */
+tip_status tip_decompose_async(const int32_t* d_eu, const int32_t* d_ev, int32_t n_u, int32_t n_v, int64_t m,
+                               int32_t side, int64_t* d_theta, void* d_workspace, size_t ws_bytes, void* stream,
+                               const tip_opts* opt, tip_stats* st);
+
+/* Message of the last failed call on this thread ("" if none).  Valid until
+ * the next tip_* call on this thread. */
+const char* tip_last_error(void);
+
+/* Number of HIP devices visible to the library (0 if none). */
+int32_t tip_device_count(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TIP_H */

@@ -1,0 +1,608 @@
+// C ABI of libtip (include/tip.h): argument checks, workspace planning and the
+// host-side orchestration of counting, coarse-grained and fine-grained
+// decomposition.  All arithmetic runs in the HIP kernels; the host only
+// sequences launches and reads a small control block between CD rounds.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/tip.h"
+#include "tip_ingest.h"
+#include "tip_kernels.h"
+
+namespace tip {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string& msg) { g_err = msg; }
+const char* last_error() { return g_err.c_str(); }
+
+namespace {
+
+constexpr int kDefaultP = 150;
+constexpr int kMaxP = 65535;
+
+struct Work {
+    IngestBuffers ib;
+    DevGraph g;
+    GraphAux aux;
+    CountBuffers cb;
+    PeelBuffers pb;
+    FdBuffers fb;
+    Ctl* ctl = nullptr;
+    SpillArena spill;
+    int64_t* total = nullptr;
+    double* ovf = nullptr;
+};
+
+int resident_workgroups() {
+    static std::mutex mu;
+    static int cached_dev = -1, cached = 0;
+    int dev = 0;
+    TIP_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev != cached_dev) {
+        int cus = 0;
+        TIP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        cached = std::max(1, cus) * big_kernel_occupancy();
+        cached_dev = dev;
+    }
+    return cached;
+}
+
+// Allocates every buffer of one decomposition from the arena (or, with a
+// null arena base, only sums the sizes).
+void plan(Arena& ar, int32_t n_a, int32_t n_b, int64_t m, int32_t P, int slots, Work& w) {
+    const int32_t S = P + 1;
+    const int64_t na = std::max<int32_t>(n_a, 1), nb = std::max<int32_t>(n_b, 1), mm = std::max<int64_t>(m, 1);
+    ingest_alloc(ar, n_a, n_b, m, w.ib);
+    graph_alloc(ar, n_a, n_b, m, w.g, w.aux);
+    w.cb.bfly_a = ar.take<int64_t>(na);
+    w.cb.bfly_b = ar.take<int64_t>(nb);
+    w.cb.work = ar.take<int64_t>(na + nb);
+    w.cb.items_small = ar.take<int32_t>(na + nb);
+    w.cb.items_big = ar.take<int32_t>(na + nb);
+    w.pb.supp = w.cb.bfly_a;
+    w.pb.wprox = ar.take<int64_t>(na);
+    w.pb.state = ar.take<int32_t>(na);
+    w.pb.init = ar.take<int64_t>(na);
+    for (int i = 0; i < 2; ++i) w.pb.live[i] = ar.take<int32_t>(na);
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) w.pb.front[i][j] = ar.take<int32_t>(na);
+    w.pb.sel_hist = ar.take<int64_t>(256);
+    w.fb.fd_vert = ar.take<int32_t>(na);
+    w.fb.fd_pos = ar.take<int32_t>(na);
+    w.fb.sub_off = ar.take<int64_t>(S + 1);
+    w.fb.sub_cnt = ar.take<int64_t>(S + 1);
+    w.fb.pkeys = ar.take<uint64_t>(mm);
+    w.fb.pcsc = ar.take<int32_t>(mm);
+    w.fb.fd_beg = ar.take<int64_t>(mm);
+    w.fb.fd_len = ar.take<int32_t>(mm);
+    w.fb.task_w = ar.take<int64_t>(S);
+    w.fb.order = ar.take<int32_t>(S);
+    w.fb.supp_fd = ar.take<int64_t>(na);
+    w.fb.alive = ar.take<int32_t>(na);
+    for (int i = 0; i < 3; ++i) w.fb.lst[i] = ar.take<int32_t>(na);
+    w.fb.theta = ar.take<int64_t>(na);
+    w.ctl = ar.take<Ctl>(1);
+    w.total = ar.take<int64_t>(2);
+    w.ovf = ar.take<double>(8);
+    const int64_t keys = std::max<int64_t>(std::max(na, nb), 1);
+    w.spill.stride = std::min<int64_t>(kBmBits, (keys + 63) & ~int64_t(63));
+    w.spill.slots = slots;
+    w.spill.dense = ar.take<int32_t>(w.spill.stride * slots);
+    w.spill.list = ar.take<int32_t>(w.spill.stride * slots);
+}
+
+// Pinned host mirror of the control block, one per host thread.
+Ctl* host_ctl() {
+    thread_local Ctl* h = nullptr;
+    if (!h) {
+        void* p = nullptr;
+        TIP_HIP_TRY(hipHostMalloc(&p, sizeof(Ctl), hipHostMallocDefault));
+        h = static_cast<Ctl*>(p);
+    }
+    return h;
+}
+
+const Ctl& read_ctl(const Work& w, hipStream_t s) {
+    Ctl* h = host_ctl();
+    TIP_HIP_TRY(hipMemcpyAsync(h, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    TIP_HIP_TRY(hipStreamSynchronize(s));
+    return *h;
+}
+
+struct Events {
+    hipEvent_t e[6] = {};
+    Events() {
+        for (auto& x : e) TIP_HIP_TRY(hipEventCreate(&x));
+    }
+    ~Events() {
+        for (auto& x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+    double ms(int a, int b) const {
+        float t = 0;
+        if (hipEventElapsedTime(&t, e[a], e[b]) != hipSuccess) return 0.0;
+        return t;
+    }
+};
+
+__global__ void k_overflow_terms(const int32_t* deg_a, int32_t n_a, const int32_t* deg_b, int32_t n_b, double* out) {
+    // out[0] = sum C(d_a, 2), out[1] = sum C(d_b, 2), out[2] = max d_a, out[3] = max d_b
+    double sa = 0, sb = 0;
+    int32_t ma = 0, mb = 0;
+    for (int64_t i = threadIdx.x; i < n_a; i += blockDim.x) {
+        const double d = deg_a[i];
+        sa += d * (d - 1) * 0.5;
+        ma = max(ma, deg_a[i]);
+    }
+    for (int64_t i = threadIdx.x; i < n_b; i += blockDim.x) {
+        const double d = deg_b[i];
+        sb += d * (d - 1) * 0.5;
+        mb = max(mb, deg_b[i]);
+    }
+    __shared__ double r0[1024], r1[1024];
+    __shared__ int32_t r2[1024], r3[1024];
+    r0[threadIdx.x] = sa;
+    r1[threadIdx.x] = sb;
+    r2[threadIdx.x] = ma;
+    r3[threadIdx.x] = mb;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0, b = 0;
+        int32_t x = 0, y = 0;
+        for (int i = 0; i < (int)blockDim.x; ++i) {
+            a += r0[i];
+            b += r1[i];
+            x = max(x, r2[i]);
+            y = max(y, r3[i]);
+        }
+        out[0] = a;
+        out[1] = b;
+        out[2] = x;
+        out[3] = y;
+    }
+}
+
+__global__ void k_sum_i64(const int64_t* a, int32_t n, int64_t* out) {
+    __shared__ unsigned long long r[1024];
+    unsigned long long s = 0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += (unsigned long long)a[i];
+    r[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < (int)blockDim.x; ++i) t += r[i];
+        out[0] = (int64_t)t;
+    }
+}
+
+// Butterfly-count bound: every butterfly is a pair of neighbours of one of
+// its U vertices plus another common neighbour of that pair, counted from
+// both U vertices, so B <= 1/2 * sum_u C(d_u, 2) * (max d_V - 1); likewise
+// from V.  Every per-vertex count and every per-side sum is at most 2B.
+bool counts_may_overflow(Work& w, hipStream_t s) {
+    k_overflow_terms<<<1, 1024, 0, s>>>(w.aux.deg_a, w.g.n_a, w.aux.deg_b, w.g.n_b, w.ovf);
+    TIP_HIP_TRY(hipGetLastError());
+    double h[4];
+    TIP_HIP_TRY(hipMemcpyAsync(h, w.ovf, sizeof(h), hipMemcpyDeviceToHost, s));
+    TIP_HIP_TRY(hipStreamSynchronize(s));
+    const double ba = 0.5 * h[0] * std::max(0.0, h[3] - 1.0);
+    const double bb = 0.5 * h[1] * std::max(0.0, h[2] - 1.0);
+    const double bound = std::min(ba, bb);
+    return 2.0 * bound * 1.0001 >= 9.2e18;
+}
+
+struct RunOut {
+    int64_t* theta = nullptr;      // device, by original id
+    int64_t* bfly_a = nullptr;     // device, by original id (count mode)
+    int64_t* bfly_b = nullptr;
+    int32_t* subset = nullptr;     // device, by original id (optional)
+    int64_t* init = nullptr;       // device, by original id (optional)
+    std::vector<int64_t>* bounds = nullptr;
+    int32_t* n_subsets = nullptr;
+};
+
+__global__ void k_scatter_i32(const int32_t* by_rank, const int32_t* orig, int32_t n, int32_t* out) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+        out[orig[r]] = by_rank[r];
+}
+
+// Ingest + count (+ CD + FD when decomposing).  Returns TIP_OK or an error
+// status (EINVAL for out-of-range ids found on the device).
+tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int32_t n_b, int64_t m, bool a_is_u,
+               int32_t P, bool decompose, RunOut& out, tip_stats* st, hipStream_t s) {
+    Events ev;
+    TIP_HIP_TRY(hipEventRecord(ev.e[0], s));
+    TIP_HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s));
+    if (!ingest(d_a, d_b, n_a, n_b, m, a_is_u, w.ib, w.g, w.aux, s)) {
+        set_error("an edge endpoint id is out of range");
+        return TIP_EINVAL;
+    }
+    if (counts_may_overflow(w, s)) {
+        set_error("butterfly counts of this graph could exceed INT64_MAX");
+        return TIP_EOVERFLOW;
+    }
+    TIP_HIP_TRY(hipEventRecord(ev.e[1], s));
+    const DevGraph& g = w.g;
+    const int big_grid = w.spill.slots;
+
+    // Per-vertex butterfly counting (Alg. 1).
+    launch_count(g, w.cb, w.ctl, w.spill, big_grid, s);
+    TIP_HIP_TRY(hipEventRecord(ev.e[2], s));
+
+    int64_t rounds = 0;
+    int32_t S = 0;
+    if (!decompose) {
+        if (out.bfly_a) launch_scatter_i64(w.cb.bfly_a, g.a_orig, n_a, out.bfly_a, s);
+        if (out.bfly_b) launch_scatter_i64(w.cb.bfly_b, g.b_orig, n_b, out.bfly_b, s);
+        TIP_HIP_TRY(hipEventRecord(ev.e[3], s));
+        TIP_HIP_TRY(hipEventRecord(ev.e[4], s));
+    } else {
+        // Coarse-grained decomposition (Alg. 3).
+        PeelBuffers& pb = w.pb;
+        launch_wproxy(g, w.aux.deg_b, pb.wprox, s);
+        fill_i32(pb.state, kLive, n_a, s);
+        iota_i32(pb.live[0], n_a, s);
+        int cur_live = 0;
+        int32_t n_live = n_a;
+        double scale = 1.0;
+        int64_t lo = 0;
+        std::vector<int64_t> bounds{0};
+        int32_t label = 0;
+        for (; label < P && n_live > 0; ++label) {
+            launch_range_start(pb, cur_live, n_live, w.ctl, s);
+            const Ctl& c0 = read_ctl(w, s);
+            n_live = c0.n_live_next;
+            cur_live ^= 1;
+            if (n_live == 0) break;
+            const uint64_t max_supp = c0.max_supp;
+            const long long w_rem = c0.w_rem;
+            // adaptive target: remaining wedges over remaining subsets,
+            // scaled by how far the previous subset overshot its target
+            double tgt_d = std::ceil(scale * (double)w_rem / (double)(P - label));
+            int64_t tgt = tgt_d < 1.0 ? 1 : (int64_t)tgt_d;
+            int64_t hi;
+            if (max_supp == 0) {
+                hi = 1;
+            } else {
+                launch_select(pb, cur_live, n_live, max_supp, tgt, w.ctl, s);
+                const Ctl& c1 = read_ctl(w, s);
+                hi = c1.sel_found ? (int64_t)c1.sel_prefix + 1 : (int64_t)max_supp + 1;
+            }
+            bounds.push_back(hi);
+            int cur_front = 0;
+            launch_frontier_init(pb, cur_live, n_live, hi, label, cur_front, w.ctl, s);
+            for (;;) {
+                const Ctl& c2 = read_ctl(w, s);
+                const int32_t ns = c2.n_front[0], nb = c2.n_front[1];
+                if (ns + nb == 0) break;
+                launch_peel_round(g, pb, cur_front, ns, nb, hi, w.ctl, w.spill, big_grid, s);
+                launch_round_end(pb, 1 - cur_front, n_live, 0, label, w.ctl, s);
+                cur_front ^= 1;
+                ++rounds;
+            }
+            const Ctl& c3 = read_ctl(w, s);
+            if (c3.w_range > 0) scale = std::min(1.0, (double)tgt / (double)c3.w_range);
+            lo = hi;
+        }
+        (void)lo;
+        // Vertices left after P ranges form one more subset.
+        launch_range_start(pb, cur_live, n_live, w.ctl, s);
+        const Ctl& c4 = read_ctl(w, s);
+        n_live = c4.n_live_next;
+        cur_live ^= 1;
+        if (n_live > 0) {
+            launch_assign_live(pb, cur_live, n_live, label, s);
+            bounds.push_back(INT64_MAX);
+            S = label + 1;
+        } else {
+            S = label;
+        }
+        TIP_HIP_TRY(hipEventRecord(ev.e[3], s));
+        // Fine-grained decomposition (Alg. 4).
+        if (S > 0) {
+            launch_fd(g, pb, w.fb, S, w.ctl, w.spill, big_grid, w.ib.keys2, w.ib.vals2, w.ib.hist, w.ib.scan_tmp,
+                      w.ib.keys, w.ib.vals, s);
+        }
+        TIP_HIP_TRY(hipEventRecord(ev.e[4], s));
+        launch_scatter_i64(w.fb.theta, g.a_orig, n_a, out.theta, s);
+        if (out.subset && n_a > 0) {
+            k_scatter_i32<<<(n_a + 255) / 256, 256, 0, s>>>(pb.state, g.a_orig, n_a, out.subset);
+            TIP_HIP_TRY(hipGetLastError());
+        }
+        if (out.init) launch_scatter_i64(pb.init, g.a_orig, n_a, out.init, s);
+        if (out.bounds) *out.bounds = bounds;
+        if (out.n_subsets) *out.n_subsets = S;
+    }
+    TIP_HIP_TRY(hipEventRecord(ev.e[5], s));
+    const Ctl& cf = read_ctl(w, s);
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->wedges_count = (int64_t)cf.wedges_count;
+        st->wedges_cd = (int64_t)cf.wedges_cd;
+        st->wedges_fd = (int64_t)cf.wedges_fd;
+        st->pair_updates = (int64_t)cf.pair_updates;
+        st->rounds = rounds;
+        st->subsets = S;
+        st->fd_levels = (int64_t)cf.fd_levels;
+        st->spills = (int64_t)cf.spills;
+        st->skipped = (int64_t)cf.skipped;
+        st->m_unique = g.m;
+        st->t_ingest_ms = ev.ms(0, 1);
+        st->t_count_ms = ev.ms(1, 2);
+        st->t_cd_ms = ev.ms(2, 3);
+        st->t_fd_ms = ev.ms(3, 4);
+        st->t_total_ms = ev.ms(0, 5);
+    }
+    return TIP_OK;
+}
+
+struct DeviceBuffer {
+    void* p = nullptr;
+    ~DeviceBuffer() {
+        if (p) (void)hipFree(p);
+    }
+    void alloc(size_t bytes) {
+        if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            throw AllocFailure("hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        }
+    }
+};
+
+struct StreamHolder {
+    hipStream_t s = nullptr;
+    StreamHolder() { TIP_HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)); }
+    ~StreamHolder() {
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
+
+void check_edges(const tip_edges* g) {
+    if (!g) throw InvalidArg("graph is NULL");
+    if (g->n_u < 0 || g->n_v < 0) throw InvalidArg("negative vertex count");
+    if (g->m < 0) throw InvalidArg("negative edge count");
+    if (g->m > INT32_MAX) throw InvalidArg("more than 2^31-1 edges");
+    if (g->m > 0 && (!g->eu || !g->ev)) throw InvalidArg("edge arrays are NULL");
+    for (int64_t i = 0; i < g->m; ++i) {
+        if ((uint32_t)g->eu[i] >= (uint32_t)g->n_u || (uint32_t)g->ev[i] >= (uint32_t)g->n_v)
+            throw InvalidArg("edge " + std::to_string(i) + " has an endpoint id out of range");
+    }
+}
+
+int32_t check_opts(const tip_opts* opt) {
+    if (!opt) return kDefaultP;
+    if (opt->P < 0 || opt->P > kMaxP) throw InvalidArg("P must be in [0, 65535]");
+    if (opt->flags != 0) throw InvalidArg("flags must be 0");
+    for (int i = 0; i < 8; ++i)
+        if (opt->tune[i] != 0) throw InvalidArg("tune must be all 0");
+    return opt->P == 0 ? kDefaultP : opt->P;
+}
+
+template <class F>
+tip_status guard(F&& f) {
+    try {
+        g_err.clear();
+        return f();
+    } catch (const InvalidArg& e) {
+        set_error(e.msg);
+        return TIP_EINVAL;
+    } catch (const AllocFailure& e) {
+        set_error(e.msg);
+        return TIP_ENOMEM;
+    } catch (const HipFailure& e) {
+        set_error(e.msg);
+        return TIP_EDEVICE;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return TIP_ENOMEM;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return TIP_EDEVICE;
+    }
+}
+
+// Host-pointer decomposition of one graph (side already validated).
+tip_status decompose_host(const tip_edges* g, int32_t side, int64_t* theta, int32_t P, tip_stats* st,
+                          int32_t* subset, int64_t* init, int64_t* bounds, int32_t* n_subsets) {
+    const bool a_is_u = side == TIP_SIDE_U;
+    const int32_t n_a = a_is_u ? g->n_u : g->n_v;
+    const int32_t n_b = a_is_u ? g->n_v : g->n_u;
+    const int64_t m = g->m;
+    StreamHolder sh;
+    Work w;
+    const int slots = resident_workgroups();
+    Arena sizer;
+    plan(sizer, n_a, n_b, m, P, slots, w);
+    const size_t extra = sizeof(int32_t) * (2 * (size_t)std::max<int64_t>(m, 1)) +
+                         (sizeof(int64_t) * 2 + sizeof(int32_t)) * (size_t)std::max<int32_t>(n_a, 1) + 4096;
+    DeviceBuffer buf;
+    buf.alloc(sizer.off + extra);
+    Arena ar{static_cast<char*>(buf.p), sizer.off + extra, 0};
+    plan(ar, n_a, n_b, m, P, slots, w);
+    int32_t* d_a = ar.take<int32_t>(std::max<int64_t>(m, 1));
+    int32_t* d_b = ar.take<int32_t>(std::max<int64_t>(m, 1));
+    int64_t* d_theta = ar.take<int64_t>(std::max<int32_t>(n_a, 1));
+    int64_t* d_init = ar.take<int64_t>(std::max<int32_t>(n_a, 1));
+    int32_t* d_sub = ar.take<int32_t>(std::max<int32_t>(n_a, 1));
+    const hipStream_t s = sh.s;
+    TIP_HIP_TRY(hipMemsetAsync(w.spill.dense, 0, sizeof(int32_t) * w.spill.stride * w.spill.slots, s));
+    if (m > 0) {
+        TIP_HIP_TRY(hipMemcpyAsync(d_a, a_is_u ? g->eu : g->ev, sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+        TIP_HIP_TRY(hipMemcpyAsync(d_b, a_is_u ? g->ev : g->eu, sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+    }
+    RunOut out;
+    out.theta = d_theta;
+    out.subset = subset ? d_sub : nullptr;
+    out.init = init ? d_init : nullptr;
+    std::vector<int64_t> bvec;
+    out.bounds = &bvec;
+    int32_t ns = 0;
+    out.n_subsets = &ns;
+    const tip_status rc = run(w, d_a, d_b, n_a, n_b, m, a_is_u, P, true, out, st, s);
+    if (rc != TIP_OK) return rc;
+    if (n_a > 0) {
+        TIP_HIP_TRY(hipMemcpyAsync(theta, d_theta, sizeof(int64_t) * n_a, hipMemcpyDeviceToHost, s));
+        if (subset) TIP_HIP_TRY(hipMemcpyAsync(subset, d_sub, sizeof(int32_t) * n_a, hipMemcpyDeviceToHost, s));
+        if (init) TIP_HIP_TRY(hipMemcpyAsync(init, d_init, sizeof(int64_t) * n_a, hipMemcpyDeviceToHost, s));
+    }
+    TIP_HIP_TRY(hipStreamSynchronize(s));
+    if (bounds) {
+        for (size_t i = 0; i < bvec.size(); ++i) bounds[i] = bvec[i];
+    }
+    if (n_subsets) *n_subsets = ns;
+    return TIP_OK;
+}
+
+}  // namespace
+}  // namespace tip
+
+using namespace tip;
+
+extern "C" {
+
+const char* tip_last_error(void) { return tip::last_error(); }
+
+int32_t tip_device_count(void) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+tip_status tip_count_butterflies(const tip_edges* g, int64_t* bfly_u, int64_t* bfly_v, int64_t* total) {
+    return guard([&]() -> tip_status {
+        check_edges(g);
+        const int32_t n_a = g->n_u, n_b = g->n_v;
+        const int64_t m = g->m;
+        StreamHolder sh;
+        Work w;
+        const int slots = resident_workgroups();
+        Arena sizer;
+        plan(sizer, n_a, n_b, m, 1, slots, w);
+        const size_t extra = sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(m, 1) +
+                             sizeof(int64_t) * ((size_t)std::max(n_a, 1) + std::max(n_b, 1)) + 4096;
+        DeviceBuffer buf;
+        buf.alloc(sizer.off + extra);
+        Arena ar{static_cast<char*>(buf.p), sizer.off + extra, 0};
+        plan(ar, n_a, n_b, m, 1, slots, w);
+        int32_t* d_a = ar.take<int32_t>(std::max<int64_t>(m, 1));
+        int32_t* d_b = ar.take<int32_t>(std::max<int64_t>(m, 1));
+        int64_t* d_bu = ar.take<int64_t>(std::max(n_a, 1));
+        int64_t* d_bv = ar.take<int64_t>(std::max(n_b, 1));
+        const hipStream_t s = sh.s;
+        TIP_HIP_TRY(hipMemsetAsync(w.spill.dense, 0, sizeof(int32_t) * w.spill.stride * w.spill.slots, s));
+        if (m > 0) {
+            TIP_HIP_TRY(hipMemcpyAsync(d_a, g->eu, sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+            TIP_HIP_TRY(hipMemcpyAsync(d_b, g->ev, sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+        }
+        RunOut out;
+        out.bfly_a = d_bu;
+        out.bfly_b = d_bv;
+        const tip_status rc = run(w, d_a, d_b, n_a, n_b, m, true, 1, false, out, nullptr, s);
+        if (rc != TIP_OK) return rc;
+        if (total) {
+            k_sum_i64<<<1, 1024, 0, s>>>(w.cb.bfly_a, n_a, w.total);
+            TIP_HIP_TRY(hipGetLastError());
+        }
+        int64_t tot2 = 0;
+        if (bfly_u && n_a > 0)
+            TIP_HIP_TRY(hipMemcpyAsync(bfly_u, d_bu, sizeof(int64_t) * n_a, hipMemcpyDeviceToHost, s));
+        if (bfly_v && n_b > 0)
+            TIP_HIP_TRY(hipMemcpyAsync(bfly_v, d_bv, sizeof(int64_t) * n_b, hipMemcpyDeviceToHost, s));
+        if (total) TIP_HIP_TRY(hipMemcpyAsync(&tot2, w.total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        TIP_HIP_TRY(hipStreamSynchronize(s));
+        if (total) *total = tot2 / 2;
+        return TIP_OK;
+    });
+}
+
+tip_status tip_decompose_ex(const tip_edges* g, int32_t side, int64_t* theta, const tip_opts* opt, tip_stats* st,
+                            int32_t* subset, int64_t* init_support, int64_t* bounds, int32_t* n_subsets) {
+    return guard([&]() -> tip_status {
+        check_edges(g);
+        if (side != TIP_SIDE_U && side != TIP_SIDE_V) throw InvalidArg("side must be 0 (U) or 1 (V)");
+        const int32_t P = check_opts(opt);
+        const int32_t n_side = side == TIP_SIDE_U ? g->n_u : g->n_v;
+        if (n_side > 0 && !theta) throw InvalidArg("theta is NULL");
+        return decompose_host(g, side, theta, P, st, subset, init_support, bounds, n_subsets);
+    });
+}
+
+tip_status tip_decompose(const tip_edges* g, int32_t side, int64_t* theta, const tip_opts* opt, tip_stats* st) {
+    return tip_decompose_ex(g, side, theta, opt, st, nullptr, nullptr, nullptr, nullptr);
+}
+
+tip_status tip_decompose_batch(int32_t n, const tip_edges* gs, const int32_t* sides, int64_t* const* thetas,
+                               const tip_opts* opt, tip_stats* st) {
+    return guard([&]() -> tip_status {
+        if (n < 0) throw InvalidArg("negative batch size");
+        if (n > 0 && (!gs || !sides || !thetas)) throw InvalidArg("batch arrays are NULL");
+        const int32_t P = check_opts(opt);
+        for (int32_t k = 0; k < n; ++k) {
+            check_edges(&gs[k]);
+            if (sides[k] != TIP_SIDE_U && sides[k] != TIP_SIDE_V) throw InvalidArg("side must be 0 or 1");
+            const int32_t n_side = sides[k] == TIP_SIDE_U ? gs[k].n_u : gs[k].n_v;
+            if (n_side > 0 && !thetas[k]) throw InvalidArg("theta is NULL");
+        }
+        for (int32_t k = 0; k < n; ++k) {
+            const tip_status rc = decompose_host(&gs[k], sides[k], thetas[k], P, st ? &st[k] : nullptr, nullptr,
+                                                 nullptr, nullptr, nullptr);
+            if (rc != TIP_OK) return rc;
+        }
+        return TIP_OK;
+    });
+}
+
+tip_status tip_workspace_size(int32_t n_u, int32_t n_v, int64_t m, int32_t side, const tip_opts* opt,
+                              size_t* bytes) {
+    return guard([&]() -> tip_status {
+        if (!bytes) throw InvalidArg("bytes is NULL");
+        if (n_u < 0 || n_v < 0 || m < 0 || m > INT32_MAX) throw InvalidArg("bad graph size");
+        if (side != TIP_SIDE_U && side != TIP_SIDE_V) throw InvalidArg("side must be 0 or 1");
+        const int32_t P = check_opts(opt);
+        const int32_t n_a = side == TIP_SIDE_U ? n_u : n_v, n_b = side == TIP_SIDE_U ? n_v : n_u;
+        Work w;
+        Arena sizer;
+        plan(sizer, n_a, n_b, m, P, resident_workgroups(), w);
+        *bytes = sizer.off + 256;
+        return TIP_OK;
+    });
+}
+
+tip_status tip_decompose_async(const int32_t* d_eu, const int32_t* d_ev, int32_t n_u, int32_t n_v, int64_t m,
+                               int32_t side, int64_t* d_theta, void* d_workspace, size_t ws_bytes, void* stream,
+                               const tip_opts* opt, tip_stats* st) {
+    return guard([&]() -> tip_status {
+        if (n_u < 0 || n_v < 0 || m < 0 || m > INT32_MAX) throw InvalidArg("bad graph size");
+        if (m > 0 && (!d_eu || !d_ev)) throw InvalidArg("edge arrays are NULL");
+        if (side != TIP_SIDE_U && side != TIP_SIDE_V) throw InvalidArg("side must be 0 or 1");
+        const int32_t P = check_opts(opt);
+        const bool a_is_u = side == TIP_SIDE_U;
+        const int32_t n_a = a_is_u ? n_u : n_v, n_b = a_is_u ? n_v : n_u;
+        if (n_a > 0 && !d_theta) throw InvalidArg("theta is NULL");
+        if (!d_workspace) throw InvalidArg("workspace is NULL");
+        Work w;
+        Arena sizer;
+        const int slots = resident_workgroups();
+        plan(sizer, n_a, n_b, m, P, slots, w);
+        if (ws_bytes < sizer.off) throw AllocFailure("workspace smaller than tip_workspace_size");
+        Arena ar{static_cast<char*>(d_workspace), ws_bytes, 0};
+        plan(ar, n_a, n_b, m, P, slots, w);
+        const hipStream_t s = static_cast<hipStream_t>(stream);
+        TIP_HIP_TRY(hipMemsetAsync(w.spill.dense, 0, sizeof(int32_t) * w.spill.stride * w.spill.slots, s));
+        RunOut out;
+        out.theta = d_theta;
+        return run(w, a_is_u ? d_eu : d_ev, a_is_u ? d_ev : d_eu, n_a, n_b, m, a_is_u, P, true, out, st, s);
+    });
+}
+
+}  // extern "C"

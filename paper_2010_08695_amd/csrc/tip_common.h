@@ -1,0 +1,114 @@
+// Internal declarations shared by the libtip translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+namespace tip {
+
+// ---------------------------------------------------------------------------
+// Tunables.  The bitmap covers BM_BITS keys per tile (one bit per same-side
+// vertex); the repeat table keeps keys seen at least twice.
+// ---------------------------------------------------------------------------
+constexpr int kWave = 64;
+constexpr int kBigThreads = 1024;          // threads of the workgroup-per-vertex kernels
+constexpr int kBmBits = 1 << 20;           // keys per bitmap tile (128 KiB of LDS)
+constexpr int kBmWords = kBmBits / 32;
+constexpr int kRepSlots = 2048;            // LDS repeat-table slots (16 KiB)
+constexpr int kRepProbe = 16;              // bounded probing before spilling to HBM
+constexpr int kGroup = 512;                // neighbour slices staged per pass
+constexpr int kSmallThreads = 256;         // threads of the wave-per-vertex kernels
+constexpr int kSmallSlots = 1024;          // per-wave hash slots (8 KiB)
+constexpr int64_t kSmallMaxWedges = 448;   // wave path handles <= this many wedges
+
+constexpr int32_t kLive = -1;              // subset id of a vertex not yet assigned
+
+// 64-bit hash-table slot: (key + 1) << 32 | count; 0 = empty.
+__host__ __device__ inline uint32_t hash32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+__host__ __device__ inline int64_t choose2(int64_t c) { return c * (c - 1) / 2; }
+
+// Device view of a canonical graph.  "A" is the side being decomposed (or the
+// first side when counting), "B" the other.  Vertex ids on each side are
+// local ranks by (degree descending, original id ascending); every list is
+// sorted ascending.
+struct DevGraph {
+    int32_t n_a = 0, n_b = 0;
+    int64_t m = 0;
+    int64_t* a_off = nullptr;   // [n_a+1]
+    int32_t* a_adj = nullptr;   // [m]  B ranks
+    int64_t* b_off = nullptr;   // [n_b+1]
+    int32_t* b_adj = nullptr;   // [m]  A ranks
+    int32_t* a_cut = nullptr;   // [n_a] leading entries of N_x with higher joint priority than x
+    int32_t* b_cut = nullptr;   // [n_b]
+    int32_t* a_rev = nullptr;   // [m]  position of the row vertex inside its neighbour's list
+    int32_t* b_rev = nullptr;   // [m]
+    int32_t* a_orig = nullptr;  // [n_a] rank -> original id
+    int32_t* b_orig = nullptr;  // [n_b]
+    int32_t* a_row = nullptr;   // [m]  row (A rank) of each CSR position
+    int32_t* b_row = nullptr;   // [m]  row (B rank) of each CSC position
+};
+
+// Per-workgroup spill buffers (HBM) for repeat keys that do not fit in LDS.
+// Workgroup b uses dense/list + b * stride; stride >= the largest tile of
+// keys any kernel uses on this graph.  `dense` is all zero between uses.
+struct SpillArena {
+    int32_t* dense = nullptr;    // [slots * stride] repeat counts
+    int32_t* list = nullptr;     // [slots * stride] spilled keys
+    int64_t stride = 0;
+    int32_t slots = 0;           // number of workgroup slots (= resident workgroups)
+};
+
+// Error reporting (thread-local message behind tip_last_error).
+void set_error(const std::string& msg);
+const char* last_error();
+
+#define TIP_HIP_TRY(expr)                                                        \
+    do {                                                                         \
+        hipError_t e_ = (expr);                                                  \
+        if (e_ != hipSuccess) {                                                  \
+            throw ::tip::HipFailure(std::string(#expr) + ": " + hipGetErrorString(e_)); \
+        }                                                                        \
+    } while (0)
+
+struct HipFailure {
+    std::string msg;
+    explicit HipFailure(std::string m) : msg(std::move(m)) {}
+};
+struct AllocFailure {
+    std::string msg;
+    explicit AllocFailure(std::string m) : msg(std::move(m)) {}
+};
+struct InvalidArg {
+    std::string msg;
+    explicit InvalidArg(std::string m) : msg(std::move(m)) {}
+};
+
+// ---------------------------------------------------------------------------
+// Launch wrappers implemented in the kernel translation units.
+// ---------------------------------------------------------------------------
+
+// util.hip
+void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+size_t scan_tmp_elems(int64_t n);
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of key.
+// Ping-pongs between the two buffers; on return the sorted data is in
+// (keys, vals).  tmp_keys/tmp_vals hold n entries; hist holds radix_hist_elems(n).
+void radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* tmp_keys, int32_t* tmp_vals,
+                      int64_t n, int bits, int64_t* hist, int64_t* scan_tmp, hipStream_t s);
+size_t radix_hist_elems(int64_t n);
+void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+void iota_i32(int32_t* p, int64_t n, hipStream_t s);
+
+}  // namespace tip

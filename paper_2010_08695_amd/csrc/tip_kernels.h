@@ -1,0 +1,93 @@
+// Internal: control block and launch wrappers of the decomposition kernels.
+#pragma once
+
+#include "agg.h"
+
+namespace tip {
+
+// Device-resident control block of one decomposition.
+struct Ctl {
+    int32_t n_live;         // live-list length (after the last compaction)
+    int32_t n_live_next;    // compaction output counter
+    int32_t n_front[2];     // current frontier sizes [wave bin, workgroup bin]
+    int32_t n_next[2];      // next frontier sizes
+    int32_t n_items[2];     // counting work items [wave bin, workgroup bin]
+    int32_t fd_head;        // fine-grained task queue head
+    int32_t sel_found;      // 0 once no support value reaches the target
+    int32_t pad[6];
+    unsigned long long max_supp;
+    long long w_rem;        // wedge proxy summed over live vertices
+    long long w_range;      // wedge proxy summed over the current subset
+    unsigned long long sel_prefix;
+    long long sel_cum;
+    long long sel_tgt;
+    long long hi;
+    unsigned long long wedges_count;
+    unsigned long long wedges_cd;
+    unsigned long long wedges_fd;
+    unsigned long long pair_updates;
+    unsigned long long spills;
+    unsigned long long skipped;
+    unsigned long long fd_levels;
+};
+
+struct CountBuffers {
+    int64_t* bfly_a;     // [n_a]
+    int64_t* bfly_b;     // [n_b]
+    int64_t* work;       // [n_a + n_b]
+    int32_t* items_small;
+    int32_t* items_big;
+};
+
+struct PeelBuffers {
+    int64_t* supp;       // [n_a] raw supports (= bfly_a)
+    int64_t* wprox;      // [n_a] wedges of u in the original graph
+    int32_t* state;      // [n_a] kLive or subset id
+    int64_t* init;       // [n_a] support at the start of u's range
+    int32_t* live[2];    // [n_a] live lists (ping-pong)
+    int32_t* front[2][2];  // [buffer][bin] frontier lists
+    int64_t* sel_hist;   // [256]
+};
+
+struct FdBuffers {
+    int32_t* fd_vert;    // [n_a] vertices grouped by subset, ascending rank inside
+    int32_t* fd_pos;     // [n_a]
+    int64_t* sub_off;    // [S + 1]
+    int64_t* sub_cnt;    // [S + 1]
+    uint64_t* pkeys;     // [m] partitioned CSC keys (row * S + subset)
+    int32_t* pcsc;       // [m] local ids
+    int64_t* fd_beg;     // [m] per CSR edge: slice begin in pcsc
+    int32_t* fd_len;     // [m]
+    int64_t* task_w;     // [S]
+    int32_t* order;      // [S]
+    int64_t* supp_fd;    // [n_a] by subset position
+    int32_t* alive;      // [n_a] by subset position
+    int32_t* lst[3];     // [n_a] live / next-live / peel lists by subset position
+    int64_t* theta;      // [n_a] by rank
+};
+
+// counting
+void launch_count(const DevGraph& g, CountBuffers& cb, Ctl* ctl, const SpillArena& spill, int big_grid,
+                  hipStream_t s);
+// CD
+void launch_wproxy(const DevGraph& g, const int32_t* deg_b_rank, int64_t* wprox, hipStream_t s);
+void launch_range_start(PeelBuffers& pb, int cur_live, int32_t n_live, Ctl* ctl, hipStream_t s);
+void launch_select(PeelBuffers& pb, int cur_live, int32_t n_live, uint64_t max_supp, int64_t tgt, Ctl* ctl,
+                   hipStream_t s);
+void launch_frontier_init(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi, int32_t label, int cur_front,
+                          Ctl* ctl, hipStream_t s);
+void launch_peel_round(const DevGraph& g, PeelBuffers& pb, int cur_front, int32_t n_small, int32_t n_big,
+                       int64_t hi, Ctl* ctl, const SpillArena& spill, int big_grid, hipStream_t s);
+void launch_round_end(PeelBuffers& pb, int next_front, int32_t n_small, int32_t n_big, int32_t label, Ctl* ctl,
+                      hipStream_t s);
+void launch_assign_live(PeelBuffers& pb, int cur_live, int32_t n_live, int32_t label, hipStream_t s);
+// FD
+void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl, const SpillArena& spill,
+               int big_grid, uint64_t* tmp_keys, int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp,
+               uint64_t* keys_scratch, int32_t* vals_scratch, hipStream_t s);
+// output
+void launch_scatter_i64(const int64_t* by_rank, const int32_t* orig, int32_t n, int64_t* out, hipStream_t s);
+
+int big_kernel_occupancy();  // resident workgroups per CU of the workgroup kernels
+
+}  // namespace tip

@@ -1,0 +1,231 @@
+"""ctypes binding of libtip (include/tip.h).
+
+Argument marshalling only: every step of counting and decomposition runs in
+the HIP kernels of libtip.so.  If the library has not been built, loading
+raises instead of falling back to anything else.
+
+Graph arguments are any object with ``n_u``, ``n_v``, ``eu``, ``ev``
+(e.g. ``graphgen.Graph``); ``eu``/``ev`` are int32 arrays of 0-based ids.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtip.so")
+
+TIP_OK, TIP_EINVAL, TIP_ENOMEM, TIP_EDEVICE, TIP_EOVERFLOW, TIP_EBUSY = 0, -1, -2, -3, -4, -5
+SIDE_U, SIDE_V = 0, 1
+STATUS_NAMES = {0: "TIP_OK", -1: "TIP_EINVAL", -2: "TIP_ENOMEM", -3: "TIP_EDEVICE",
+                -4: "TIP_EOVERFLOW", -5: "TIP_EBUSY"}
+
+# Every symbol declared in include/tip.h.
+EXPORTS = ["tip_count_butterflies", "tip_decompose", "tip_decompose_ex", "tip_decompose_batch",
+           "tip_workspace_size", "tip_decompose_async", "tip_last_error", "tip_device_count"]
+
+
+class TipError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class Edges(ctypes.Structure):
+    _fields_ = [("n_u", ctypes.c_int32), ("n_v", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("eu", ctypes.c_void_p), ("ev", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int32), ("flags", ctypes.c_int32), ("tune", ctypes.c_int32 * 8)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("wedges_count", "wedges_cd", "wedges_fd", "pair_updates", "rounds", "subsets",
+                 "fd_levels", "spills", "skipped", "m_unique")] + \
+               [(n, ctypes.c_double) for n in
+                ("t_ingest_ms", "t_count_ms", "t_cd_ms", "t_fd_ms", "t_total_ms")]
+
+    def to_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def _bind_hip_runtime():
+    # One HIP runtime per process: when PyTorch is installed, load it first so
+    # that libtip binds to the HIP runtime torch already uses (same soname)
+    # instead of a second copy that would make torch's device init fail.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Loads libtip.so; raises FileNotFoundError if it has not been built."""
+    global _lib
+    _bind_hip_runtime()
+    with _lock:
+        if _lib is not None and path is None:
+            return _lib
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise FileNotFoundError(
+                f"{p} is missing: build it with `python -m paper_2010_08695_amd.build` "
+                "(there is no fallback implementation)")
+        lib = ctypes.CDLL(p)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        lib.tip_count_butterflies.argtypes = [ctypes.POINTER(Edges), vp, vp, vp]
+        lib.tip_decompose.argtypes = [ctypes.POINTER(Edges), i32, vp, ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
+        lib.tip_decompose_ex.argtypes = [ctypes.POINTER(Edges), i32, vp, ctypes.POINTER(Opts),
+                                         ctypes.POINTER(Stats), vp, vp, vp, vp]
+        lib.tip_decompose_batch.argtypes = [i32, ctypes.POINTER(Edges), vp, vp, ctypes.POINTER(Opts),
+                                            ctypes.POINTER(Stats)]
+        lib.tip_workspace_size.argtypes = [i32, i32, i64, i32, ctypes.POINTER(Opts),
+                                           ctypes.POINTER(ctypes.c_size_t)]
+        lib.tip_decompose_async.argtypes = [vp, vp, i32, i32, i64, i32, vp, vp, ctypes.c_size_t, vp,
+                                            ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
+        for name in EXPORTS[:6]:
+            getattr(lib, name).restype = ctypes.c_int32
+        lib.tip_last_error.argtypes = []
+        lib.tip_last_error.restype = ctypes.c_char_p
+        lib.tip_device_count.argtypes = []
+        lib.tip_device_count.restype = ctypes.c_int32
+        if path is None:
+            _lib = lib
+        return lib
+
+
+def device_available() -> bool:
+    return load().tip_device_count() > 0
+
+
+def _check(lib, rc: int):
+    if rc != TIP_OK:
+        raise TipError(rc, (lib.tip_last_error() or b"").decode())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _edges(g) -> tuple[Edges, tuple]:
+    eu = np.ascontiguousarray(g.eu, dtype=np.int32)
+    ev = np.ascontiguousarray(g.ev, dtype=np.int32)
+    if eu.shape != ev.shape:
+        raise ValueError("eu and ev differ in length")
+    e = Edges(int(g.n_u), int(g.n_v), int(eu.shape[0]), _ptr(eu), _ptr(ev))
+    return e, (eu, ev)
+
+
+def _opts(P: int = 0) -> Opts:
+    o = Opts()
+    o.P = int(P)
+    return o
+
+
+def count_butterflies(g):
+    """Per-vertex butterfly counts: (bfly_u int64[n_u], bfly_v int64[n_v], total)."""
+    lib = load()
+    e, keep = _edges(g)
+    bu = np.zeros(g.n_u, np.int64)
+    bv = np.zeros(g.n_v, np.int64)
+    tot = np.zeros(1, np.int64)
+    _check(lib, lib.tip_count_butterflies(ctypes.byref(e), _ptr(bu), _ptr(bv), _ptr(tot)))
+    return bu, bv, int(tot[0])
+
+
+def decompose(g, side: int = SIDE_U, P: int = 0, with_stats: bool = False):
+    """Tip numbers int64[n_side] of ``side``; with_stats adds a stats dict."""
+    lib = load()
+    e, keep = _edges(g)
+    n = g.n_u if side == SIDE_U else g.n_v
+    theta = np.zeros(max(n, 0), np.int64)
+    st = Stats()
+    o = _opts(P)
+    _check(lib, lib.tip_decompose(ctypes.byref(e), int(side), _ptr(theta), ctypes.byref(o), ctypes.byref(st)))
+    return (theta, st.to_dict()) if with_stats else theta
+
+
+def decompose_ex(g, side: int = SIDE_U, P: int = 0) -> dict:
+    """Tip numbers plus the coarse-grained state (subsets, initial supports, bounds)."""
+    lib = load()
+    e, keep = _edges(g)
+    n = g.n_u if side == SIDE_U else g.n_v
+    Pe = P if P > 0 else 150
+    theta = np.zeros(n, np.int64)
+    subset = np.zeros(n, np.int32)
+    init = np.zeros(n, np.int64)
+    bounds = np.zeros(Pe + 2, np.int64)
+    ns = np.zeros(1, np.int32)
+    st = Stats()
+    o = _opts(P)
+    _check(lib, lib.tip_decompose_ex(ctypes.byref(e), int(side), _ptr(theta), ctypes.byref(o),
+                                     ctypes.byref(st), _ptr(subset), _ptr(init), _ptr(bounds), _ptr(ns)))
+    k = int(ns[0])
+    return {"theta": theta, "subset": subset, "init": init, "bounds": bounds[:k + 1],
+            "n_subsets": k, "stats": st.to_dict()}
+
+
+def decompose_batch(graphs, sides=None, P: int = 0, with_stats: bool = False):
+    """Tip numbers of many graphs in one call."""
+    lib = load()
+    n = len(graphs)
+    sides = [SIDE_U] * n if sides is None else list(sides)
+    es = (Edges * max(n, 1))()
+    keep, thetas = [], []
+    for k, g in enumerate(graphs):
+        e, kp = _edges(g)
+        es[k] = e
+        keep.append(kp)
+        thetas.append(np.zeros(g.n_u if sides[k] == SIDE_U else g.n_v, np.int64))
+    sides_a = np.ascontiguousarray(sides, dtype=np.int32)
+    ptrs = (ctypes.c_void_p * max(n, 1))(*[t.ctypes.data for t in thetas])
+    sts = (Stats * max(n, 1))()
+    o = _opts(P)
+    _check(lib, lib.tip_decompose_batch(n, es, _ptr(sides_a), ctypes.cast(ptrs, ctypes.c_void_p),
+                                        ctypes.byref(o), sts))
+    if with_stats:
+        return thetas, [sts[k].to_dict() for k in range(n)]
+    return thetas
+
+
+def workspace_size(n_u: int, n_v: int, m: int, side: int = SIDE_U, P: int = 0) -> int:
+    lib = load()
+    out = ctypes.c_size_t(0)
+    o = _opts(P)
+    _check(lib, lib.tip_workspace_size(int(n_u), int(n_v), int(m), int(side), ctypes.byref(o), ctypes.byref(out)))
+    return int(out.value)
+
+
+def decompose_async(d_eu, d_ev, n_u: int, n_v: int, side: int, d_theta, workspace, stream=None,
+                    P: int = 0) -> dict:
+    """Device-resident decomposition.  d_eu/d_ev/d_theta/workspace are torch
+    CUDA(HIP) tensors (only their device pointers are passed); stream is a
+    torch.cuda.Stream or None for the current stream.  Returns the stats."""
+    lib = load()
+    m = int(d_eu.numel())
+    if int(d_ev.numel()) != m:
+        raise ValueError("eu and ev differ in length")
+    s = None
+    if stream is not None:
+        s = stream.cuda_stream
+    else:
+        import torch
+        s = torch.cuda.current_stream().cuda_stream
+    st = Stats()
+    o = _opts(P)
+    _check(lib, lib.tip_decompose_async(
+        ctypes.c_void_p(d_eu.data_ptr()), ctypes.c_void_p(d_ev.data_ptr()), int(n_u), int(n_v), m, int(side),
+        ctypes.c_void_p(d_theta.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+        int(workspace.numel() * workspace.element_size()), ctypes.c_void_p(s), ctypes.byref(o),
+        ctypes.byref(st)))
+    return st.to_dict()

@@ -1,0 +1,131 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, struct layouts agree, and argument errors are reported as
+TIP_EINVAL on the host before any device work."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2010_08695_amd import tip
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tip.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return tip.load()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tip_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_exports():
+    assert declared_functions() == sorted(tip.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(FileNotFoundError):
+        tip.load(str(tmp_path / "libtip.so"))
+
+
+def test_struct_sizes():
+    assert ctypes.sizeof(tip.Edges) == 4 + 4 + 8 + 8 + 8
+    assert ctypes.sizeof(tip.Opts) == 4 * 10
+    assert ctypes.sizeof(tip.Stats) == 10 * 8 + 5 * 8
+
+
+def _edges(n_u, n_v, eu, ev, m=None):
+    eu = np.asarray(eu, np.int32)
+    ev = np.asarray(ev, np.int32)
+    e = tip.Edges(n_u, n_v, len(eu) if m is None else m, eu.ctypes.data_as(ctypes.c_void_p),
+                  ev.ctypes.data_as(ctypes.c_void_p))
+    return e, (eu, ev)
+
+
+def _expect_einval(lib, rc):
+    assert rc == tip.TIP_EINVAL, rc
+    assert lib.tip_last_error()  # a message is set
+
+
+def test_count_rejects_bad_arguments(lib):
+    out = np.zeros(8, np.int64)
+    p = out.ctypes.data_as(ctypes.c_void_p)
+    _expect_einval(lib, lib.tip_count_butterflies(None, p, p, p))
+    e, k = _edges(2, 2, [0, 2], [0, 1])          # U id out of range
+    _expect_einval(lib, lib.tip_count_butterflies(ctypes.byref(e), p, p, p))
+    e, k = _edges(2, 2, [0, 1], [0, -1])         # negative V id
+    _expect_einval(lib, lib.tip_count_butterflies(ctypes.byref(e), p, p, p))
+    e, k = _edges(-1, 2, [], [])
+    _expect_einval(lib, lib.tip_count_butterflies(ctypes.byref(e), p, p, p))
+    e = tip.Edges(2, 2, 3, None, None)           # m > 0 with NULL arrays
+    _expect_einval(lib, lib.tip_count_butterflies(ctypes.byref(e), p, p, p))
+    e = tip.Edges(2, 2, -1, None, None)
+    _expect_einval(lib, lib.tip_count_butterflies(ctypes.byref(e), p, p, p))
+    e = tip.Edges(2, 2, 2**31, None, None)       # too many edges
+    _expect_einval(lib, lib.tip_count_butterflies(ctypes.byref(e), p, p, p))
+
+
+def test_decompose_rejects_bad_arguments(lib):
+    theta = np.full(4, 7, np.int64)
+    tp = theta.ctypes.data_as(ctypes.c_void_p)
+    e, k = _edges(3, 3, [0, 1], [1, 2])
+    _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 2, tp, None, None))
+    _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), -1, tp, None, None))
+    _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, None, None, None))
+    o = tip.Opts()
+    o.P = -3
+    _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
+    o.P = 70000
+    _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
+    o = tip.Opts()
+    o.flags = 1
+    _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
+    o = tip.Opts()
+    o.tune[3] = 2
+    _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
+    e, k = _edges(3, 3, [0, 5], [1, 2])
+    _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, None, None))
+    # outputs untouched by argument errors
+    assert (theta == 7).all()
+
+
+def test_batch_and_workspace_reject_bad_arguments(lib):
+    _expect_einval(lib, lib.tip_decompose_batch(-1, None, None, None, None, None))
+    _expect_einval(lib, lib.tip_decompose_batch(2, None, None, None, None, None))
+    es = (tip.Edges * 1)()
+    e, k = _edges(2, 2, [0, 3], [0, 0])
+    es[0] = e
+    sides = np.zeros(1, np.int32)
+    th = np.zeros(2, np.int64)
+    ptrs = (ctypes.c_void_p * 1)(th.ctypes.data)
+    _expect_einval(lib, lib.tip_decompose_batch(1, es, sides.ctypes.data_as(ctypes.c_void_p),
+                                                ctypes.cast(ptrs, ctypes.c_void_p), None, None))
+    out = ctypes.c_size_t(0)
+    _expect_einval(lib, lib.tip_workspace_size(2, 2, 4, 0, None, None))
+    _expect_einval(lib, lib.tip_workspace_size(2, 2, -4, 0, None, ctypes.byref(out)))
+    _expect_einval(lib, lib.tip_workspace_size(2, 2, 4, 3, None, ctypes.byref(out)))
+
+
+def test_async_rejects_bad_arguments(lib):
+    _expect_einval(lib, lib.tip_decompose_async(None, None, 2, 2, 4, 0, None, None, 0, None, None, None))
+    _expect_einval(lib, lib.tip_decompose_async(None, None, 2, 2, 0, 5, None, None, 0, None, None, None))
+    _expect_einval(lib, lib.tip_decompose_async(None, None, -2, 2, 0, 0, None, None, 0, None, None, None))
+
+
+def test_last_error_is_per_call(lib):
+    e, k = _edges(2, 2, [0, 9], [0, 0])
+    assert lib.tip_count_butterflies(ctypes.byref(e), None, None, None) == tip.TIP_EINVAL
+    assert b"out of range" in lib.tip_last_error()

@@ -1,0 +1,219 @@
+"""GPU parity: libtip (HIP, gfx950) against the CPU oracle, bit-exact.
+
+Counts and tip numbers are exact int64, so every comparison is equality.
+Small graphs are compared element by element with the oracle run in the
+test; the larger workloads are compared with SHA-256 digests the committed
+golden script wrote from the oracle, plus sampled entries and invariants.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2010_08695_amd import graphgen as gg
+from paper_2010_08695_amd import tip
+
+import _props
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<i8").tobytes()).hexdigest()
+
+
+def tiny_graphs(n, seed0, max_u=12, max_v=10):
+    rng = np.random.default_rng(seed0)
+    for i in range(n):
+        nu = int(rng.integers(1, max_u + 1))
+        nv = int(rng.integers(1, max_v + 1))
+        p = float(rng.choice([0.2, 0.4, 0.6, 0.8, 1.0]))
+        yield gg.tiny_random(nu, nv, p, seed0 * 10000 + i)
+
+
+def test_count_k30_20(gpu_lib):
+    bu, bv, tot = tip.count_butterflies(gg.complete_bipartite(30, 20))
+    assert tot == 82650 and (bu == 5510).all() and (bv == 8265).all()
+
+
+def test_count_tiny_random(gpu_lib):
+    for g in tiny_graphs(60, 3):
+        bu, bv, tot = tip.count_butterflies(g)
+        ou, ov, ot = oracle.count(g)
+        assert tot == ot, g.name
+        np.testing.assert_array_equal(bu, ou, err_msg=g.name)
+        np.testing.assert_array_equal(bv, ov, err_msg=g.name)
+
+
+def test_count_plain_small(gpu_lib):
+    g = gg.config_graph("plain-small")
+    bu, bv, tot = tip.count_butterflies(g)
+    ou, ov, ot = oracle.count(g)
+    assert tot == ot
+    np.testing.assert_array_equal(bu, ou)
+    np.testing.assert_array_equal(bv, ov)
+
+
+def test_count_chung_lu_medium(gpu_lib):
+    for seed in range(3):
+        g = gg.chung_lu(3000, 800, 30000, 2.2, 2.0, seed=60 + seed)
+        bu, bv, tot = tip.count_butterflies(g)
+        ou, ov, ot = oracle.count(g)
+        assert tot == ot
+        np.testing.assert_array_equal(bu, ou)
+        np.testing.assert_array_equal(bv, ov)
+
+
+@pytest.mark.parametrize("side", [0, 1])
+def test_decompose_tiny_random(gpu_lib, side):
+    for g in tiny_graphs(40, 7 + side):
+        th = tip.decompose(g, side)
+        np.testing.assert_array_equal(th, oracle.bup(g, side)[0], err_msg=g.name)
+
+
+def test_decompose_closed_forms(gpu_lib):
+    for a, b in ((30, 20), (5, 7), (1, 9), (9, 1), (2, 2)):
+        g = gg.complete_bipartite(a, b)
+        assert (tip.decompose(g, 0) == (a - 1) * comb(b, 2)).all()
+        assert (tip.decompose(g, 1) == (b - 1) * comb(a, 2)).all()
+    for n in (3, 6, 11):
+        g = gg.complete_minus_matching(n)
+        assert (tip.decompose(g, 0) == (n - 1) * comb(n - 2, 2)).all()
+
+
+def test_decompose_degenerate(gpu_lib):
+    empty = gg.Graph(4, 3, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert (tip.decompose(empty, 0) == 0).all() and tip.decompose(empty, 0).shape == (4,)
+    none = gg.Graph(0, 0, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert tip.decompose(none, 0).shape == (0,)
+    for g in (gg.star(9, "u"), gg.random_tree(20, 9, 4)):
+        assert not tip.decompose(g, 0).any() and not tip.decompose(g, 1).any()
+    # duplicates merged
+    g = gg.tiny_random(10, 8, 0.6, 3)
+    rep = gg.Graph(g.n_u, g.n_v, np.concatenate([g.eu, g.eu]), np.concatenate([g.ev, g.ev]))
+    np.testing.assert_array_equal(tip.decompose(rep, 0), oracle.bup(g, 0)[0])
+
+
+@pytest.mark.parametrize("side", [0, 1])
+def test_decompose_plain_small(gpu_lib, side):
+    g = gg.config_graph("plain-small")
+    th = tip.decompose(g, side)
+    np.testing.assert_array_equal(th, oracle.bup(g, side)[0])
+
+
+def test_decompose_chung_lu_medium(gpu_lib):
+    for seed in range(3):
+        g = gg.chung_lu(4000, 900, 40000, 2.3, 2.0, seed=80 + seed)
+        for side in (0, 1):
+            np.testing.assert_array_equal(tip.decompose(g, side), oracle.bup(g, side)[0])
+
+
+@pytest.mark.parametrize("P", [1, 2, 7, 150, 2001])
+def test_decompose_any_P(gpu_lib, P):
+    g = gg.chung_lu(2000, 500, 15000, 2.2, 2.1, seed=5)
+    np.testing.assert_array_equal(tip.decompose(g, 0, P=P), oracle.bup(g, 0)[0])
+
+
+def test_relabel_and_side_swap(gpu_lib):
+    g = gg.chung_lu(1500, 400, 12000, 2.2, 2.1, seed=6)
+    gp, pu, pv = gg.permute_ids(g, 9)
+    th = tip.decompose(g, 0)
+    np.testing.assert_array_equal(tip.decompose(gp, 0)[pu], th)
+    np.testing.assert_array_equal(tip.decompose(gg.transpose(g), 1), th)
+
+
+def test_cd_state_theorem1(gpu_lib):
+    """Each vertex's tip number lies in its subset's range (Theorem 1), and
+    its initial support equals its butterflies with the vertices of its own
+    and all later subsets."""
+    g = gg.chung_lu(2500, 600, 20000, 2.2, 2.1, seed=11)
+    r = tip.decompose_ex(g, 0, P=20)
+    th = oracle.bup(g, 0)[0]
+    np.testing.assert_array_equal(r["theta"], th)
+    b = r["bounds"]
+    sub = r["subset"]
+    assert r["n_subsets"] >= 1 and (np.diff(b) > 0).all()
+    assert ((b[sub] <= th) & (th < b[sub + 1])).all()
+    for i in range(r["n_subsets"]):
+        member = (sub >= i).astype(np.uint8)
+        q = np.nonzero(sub == i)[0].astype(np.int32)
+        if q.size:
+            np.testing.assert_array_equal(oracle.support_in(g, 0, member, q), r["init"][q])
+
+
+def test_repeatable(gpu_lib):
+    g = gg.chung_lu(3000, 700, 25000, 2.2, 2.1, seed=13)
+    a, sa = tip.decompose(g, 0, with_stats=True)
+    b, sb = tip.decompose(g, 0, with_stats=True)
+    np.testing.assert_array_equal(a, b)
+    for k in ("wedges_count", "wedges_cd", "wedges_fd", "pair_updates", "rounds", "subsets"):
+        assert sa[k] == sb[k], k
+
+
+def test_batch_matches_single(gpu_lib):
+    gs = [gg.chung_lu(800 + 100 * k, 300, 5000 + 500 * k, 2.2, 2.3, seed=200 + k) for k in range(5)]
+    sides = [0, 1, 0, 1, 0]
+    out = tip.decompose_batch(gs, sides)
+    for g, s, th in zip(gs, sides, out):
+        np.testing.assert_array_equal(th, oracle.bup(g, s)[0])
+
+
+def test_async_device_resident(gpu_lib):
+    import torch
+    g = gg.chung_lu(3000, 700, 25000, 2.2, 2.1, seed=17)
+    dev = torch.device("cuda:0")
+    d_eu = torch.from_numpy(g.eu).to(dev)
+    d_ev = torch.from_numpy(g.ev).to(dev)
+    for side in (0, 1):
+        n = g.n_u if side == 0 else g.n_v
+        ws = torch.empty(tip.workspace_size(g.n_u, g.n_v, g.m, side), dtype=torch.uint8, device=dev)
+        d_theta = torch.empty(n, dtype=torch.int64, device=dev)
+        tip.decompose_async(d_eu, d_ev, g.n_u, g.n_v, side, d_theta, ws)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(d_theta.cpu().numpy(), oracle.bup(g, side)[0])
+
+
+def test_async_reports_bad_ids(gpu_lib):
+    import torch
+    dev = torch.device("cuda:0")
+    d_eu = torch.tensor([0, 1, 5], dtype=torch.int32, device=dev)
+    d_ev = torch.tensor([0, 1, 1], dtype=torch.int32, device=dev)
+    ws = torch.empty(tip.workspace_size(3, 2, 3, 0), dtype=torch.uint8, device=dev)
+    d_theta = torch.empty(3, dtype=torch.int64, device=dev)
+    with pytest.raises(tip.TipError) as ei:
+        tip.decompose_async(d_eu, d_ev, 3, 2, 0, d_theta, ws)
+    assert ei.value.status == tip.TIP_EINVAL
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"no golden file for {name}")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["cl-1m", "cl-10m"])
+def test_full_size_against_golden(gpu_lib, name):
+    rec = _golden(name)
+    g = gg.config_graph(name)
+    assert gg.graph_sha256(g) == rec["graph_sha256"]
+    bu, bv, tot = tip.count_butterflies(g)
+    c = rec["count"]
+    assert tot == c["total"]
+    assert digest(bu) == c["sha256_u"] and digest(bv) == c["sha256_v"]
+    for side, key in ((0, "theta_u"), (1, "theta_v")):
+        if key not in rec:
+            continue
+        th = tip.decompose(g, side)
+        s = rec[key]["sample"]
+        np.testing.assert_array_equal(th[s["index"]], s["value"])
+        assert int(th.max()) == rec[key]["max"] and int(th.sum()) == rec[key]["sum"]
+        assert digest(th) == rec[key]["sha256"]
