@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Benchmark of the tip-decomposition hot path on one MI355X.
+
+One step = one full tip decomposition (ingest, per-vertex counting,
+coarse-grained range peeling, fine-grained subset peeling, output scatter)
+of the U side of the cl-10m workload (Chung-Lu |U| = 1e6, |V| = 2e5,
+~9.76e6 distinct edges, V exponent 2.1 capped at 5e4, U exponent 2.5, P =
+150), with the edge list already resident in HBM.  Reported value: wedges
+traversed per second (counting + coarse + fine wedges / step time).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line.  Only one GPU is used; --gpus above 1 exits with a
+message.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per unit of work of the peeling kernel: the int32 id of
+# every 2-hop vertex read, the int32 id of every first-hop vertex read, and
+# one int64 read-modify-write per support decrement.
+BYTES_PER_WEDGE = 4
+BYTES_PER_EDGE = 4
+BYTES_PER_PAIR = 16
+DOMINANT_KERNEL = "k_peel_big"
+KERNEL_SOURCES = ["paper_2010_08695_amd/csrc/peel.hip", "paper_2010_08695_amd/csrc/agg.h",
+                  "paper_2010_08695_amd/csrc/tip_common.h"]
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM traffic of the dominant kernel from committed rocprofv3 counter
+    runs, or None when there are none for the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{DOMINANT_KERNEL}.{workload}.traffic.txt")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            rec = json.loads(f.read().split("\n---\n")[0])
+    except (ValueError, OSError):
+        return None
+    if rec.get("kernel_sha") != kernel_source_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(g, seconds: float) -> dict:
+    """The oracle's 2-hop aggregation (the update step of bottom-up peeling)
+    on random U vertices of the same graph, sized to ~`seconds` of CPU work."""
+    import numpy as np
+
+    import oracle
+    oracle.build()
+    dv = np.bincount(g.ev, minlength=g.n_v).astype(np.int64)
+    per_u = np.zeros(g.n_u, np.int64)
+    np.add.at(per_u, g.eu, dv[g.ev] - 1)
+    order = np.random.default_rng(0).permutation(g.n_u).astype(np.int32)
+    member = np.ones(g.n_u, np.uint8)
+    t0 = time.perf_counter()
+    oracle.support_in(g, 0, member, order[:0])
+    t_build = time.perf_counter() - t0
+    k = 64
+    while True:
+        t0 = time.perf_counter()
+        oracle.support_in(g, 0, member, order[:k])
+        dt = time.perf_counter() - t0 - t_build
+        if dt > 0.5 or k >= g.n_u:
+            break
+        k = min(g.n_u, k * 4)
+    rate = max(dt, 1e-9) / k
+    k = int(min(g.n_u, max(k, seconds / rate)))
+    t0 = time.perf_counter()
+    oracle.support_in(g, 0, member, order[:k])
+    dt = time.perf_counter() - t0 - t_build
+    wedges = int(per_u[order[:k]].sum())
+    return {"value": wedges / dt, "unit": "wedges/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle 2-hop aggregation (the update step of sequential bottom-up peeling) for {k} "
+                       f"random U vertices of {g.name}: {wedges} wedges in {dt:.1f} s on one host core; "
+                       f"adjacency build ({t_build:.1f} s) excluded; heap upkeep of the full oracle not "
+                       f"included, so this overstates the full oracle's rate")}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cl-10m")
+    ap.add_argument("--side", type=int, default=0)
+    ap.add_argument("--P", type=int, default=150)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2010_08695_amd import graphgen, tip
+
+    g = graphgen.config_graph(args.workload)
+    dev = torch.device("cuda:0")
+    d_eu = torch.from_numpy(g.eu).to(dev)
+    d_ev = torch.from_numpy(g.ev).to(dev)
+    n_side = g.n_u if args.side == 0 else g.n_v
+    ws = torch.empty(tip.workspace_size(g.n_u, g.n_v, g.m, args.side, args.P), dtype=torch.uint8, device=dev)
+    d_theta = torch.empty(n_side, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(flags=0):
+        return tip.decompose_async(d_eu, d_ev, g.n_u, g.n_v, args.side, d_theta, ws, stream, P=args.P,
+                                   flags=flags)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(step(tip.TIP_FLAG_TIME_KERNELS))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sec_per_step = elapsed / max(args.steps, 1)
+    st = stats[-1]
+    wedges = st["wedges_count"] + st["wedges_cd"] + st["wedges_fd"]
+
+    # dominant kernel: algorithmic bytes per launch over its mean launch time
+    launches = sum(s["peel_launches"] for s in stats)
+    peel_ms = sum(s["peel_ms"] for s in stats)
+    alg_bytes = sum(BYTES_PER_WEDGE * s["peel_wedges"] + BYTES_PER_EDGE * s["peel_edges"] +
+                    BYTES_PER_PAIR * s["peel_pairs"] for s in stats)
+    achieved = (alg_bytes / (peel_ms / 1e3)) / 1e9 if peel_ms > 0 else None
+    traffic = load_traffic(args.workload)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                "kernel": DOMINANT_KERNEL, "launches_per_step": launches / max(args.steps, 1),
+                "mean_launch_ms": peel_ms / max(launches, 1),
+                "alg_bytes_per_launch": alg_bytes / max(launches, 1)}
+
+    # bit-exactness against the oracle's stored digest
+    theta = d_theta.cpu().numpy()
+    bit_exact = None
+    gpath = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            rec = json.load(f)
+        key = "theta_u" if args.side == 0 else "theta_v"
+        if key in rec:
+            dig = hashlib.sha256(np.ascontiguousarray(theta, dtype="<i8").tobytes()).hexdigest()
+            bit_exact = dig == rec[key]["sha256"]
+
+    out = {
+        "metric": "wedges/s (full tip decomposition, bit-exact)",
+        "value": wedges / sec_per_step,
+        "unit": "wedges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec_per_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: Chung-Lu |U|={g.n_u} |V|={g.n_v} m={g.m} "
+                               f"side={'U' if args.side == 0 else 'V'} P={args.P}",
+                   "n_u": g.n_u, "n_v": g.n_v, "m": g.m, "side": args.side, "P": args.P},
+        "bit_exact": bit_exact,
+        "wedges": {"count": st["wedges_count"], "cd": st["wedges_cd"], "fd": st["wedges_fd"]},
+        "phase_ms": {k: st[k] for k in ("t_ingest_ms", "t_count_ms", "t_cd_ms", "t_fd_ms", "t_total_ms")},
+        "rounds": st["rounds"], "subsets": st["subsets"], "pair_updates": st["pair_updates"],
+        "spills": st["spills"],
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -54,13 +54,21 @@ typedef struct {
     const int32_t* ev; /* [m] V ids */
 } tip_edges;
 
+/* TIP_FLAG_TIME_KERNELS: time every launch of the coarse-grained
+ * workgroup peeling kernel (the dominant kernel) with HIP events on the
+ * call's stream and report it in tip_stats.peel_*. */
+#define TIP_FLAG_TIME_KERNELS 1
+
 /* Options.  Zero-initialised means defaults. */
 typedef struct {
     int32_t P;       /* number of tip-number ranges of the coarse-grained step
                         (Alg. 3); 0 = 150, the value the paper's experiments
                         settle on; at most 65535 */
-    int32_t flags;   /* reserved, must be 0 */
-    int32_t tune[8]; /* reserved, must be 0 */
+    int32_t flags;   /* TIP_FLAG_* bits; other bits must be 0 */
+    int32_t tune[8]; /* tune[0]: wedge count above which a vertex's update
+                        uses the dense key-tile kernel (0 = default, a
+                        quarter of the side's vertex count, at least 65536);
+                        tune[1..7] reserved, must be 0 */
 } tip_opts;
 
 /* Work and time accounting of one decomposition (NULL = not wanted). */
@@ -75,6 +83,12 @@ typedef struct {
     int64_t spills;       /* repeat keys that did not fit in LDS (kept in HBM) */
     int64_t skipped;      /* peeled vertices with no butterfly left (no update needed) */
     int64_t m_unique;     /* edges after duplicate merging */
+    /* the coarse-grained workgroup peeling kernel alone */
+    int64_t peel_launches; /* launches */
+    int64_t peel_wedges;   /* wedges it traversed */
+    int64_t peel_edges;    /* first-hop edges (u, v) it read */
+    int64_t peel_pairs;    /* support decrements it applied */
+    double peel_ms;        /* summed launch time (TIP_FLAG_TIME_KERNELS), else 0 */
     double t_ingest_ms, t_count_ms, t_cd_ms, t_fd_ms, t_total_ms; /* device time per phase */
 } tip_stats;
 

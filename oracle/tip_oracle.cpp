@@ -183,6 +183,16 @@ int oracle_bup(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu, const int
                 heap.emplace(lowered, w);
             }
         }
+        // Keep the heap's memory bounded: once stale entries dominate,
+        // rebuild it with one current entry per remaining vertex.
+        const int64_t left = static_cast<int64_t>(n) - peeled;
+        if (static_cast<int64_t>(heap.size()) > 4 * left + 4096) {
+            std::vector<Entry> fresh;
+            fresh.reserve(static_cast<size_t>(left));
+            for (int32_t x = 0; x < n; ++x)
+                if (remaining[x]) fresh.emplace_back(support[x], x);
+            heap = decltype(heap)(decltype(heap)::value_compare(), std::move(fresh));
+        }
     }
     if (wedges) *wedges = visited;
     return 0;

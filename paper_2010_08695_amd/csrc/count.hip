@@ -1,0 +1,264 @@
+// Per-vertex butterfly counting (Alg. 1) on the device.
+#include "kern_util.h"
+
+namespace tip {
+namespace {
+// ===========================================================================
+// Per-vertex butterfly counting (Alg. 1)
+// ===========================================================================
+//
+// Start vertex x on side X, middle vertex y in N_x, end vertex z in N_y with
+// z before both x and y in the joint degree order.  Since every list is sorted
+// by rank, the admissible z of the edge (x, y) are the first
+// min(cut[y], pos of x in N_y) entries of N_y.  With c = number of wedges from
+// x ending at z: x and z each gain C(c, 2) and y gains c - 1 per wedge.
+
+struct SideView {
+    const int64_t* own_off;
+    const int32_t* own_adj;
+    const int32_t* own_rev;
+    const int64_t* oth_off;
+    const int32_t* oth_adj;
+    const int32_t* oth_cut;
+    int64_t* own_bfly;
+    int64_t* oth_bfly;
+};
+
+__device__ inline SideView side_view(const DevGraph& g, bool side_b, int64_t* bfly_a, int64_t* bfly_b) {
+    SideView v;
+    if (!side_b) {
+        v = {g.a_off, g.a_adj, g.a_rev, g.b_off, g.b_adj, g.b_cut, bfly_a, bfly_b};
+    } else {
+        v = {g.b_off, g.b_adj, g.b_rev, g.a_off, g.a_adj, g.a_cut, bfly_b, bfly_a};
+    }
+    return v;
+}
+
+__global__ void k_count_work(DevGraph g, int64_t* work) {
+    GRID_STRIDE(p, g.m) {
+        const int32_t x = g.a_row[p], y = g.a_adj[p];
+        const int64_t l1 = min(g.b_cut[y], g.a_rev[p]);
+        if (l1) atomic_add_i64(&work[x], l1);
+        const int32_t yb = g.b_row[p], xb = g.b_adj[p];
+        const int64_t l2 = min(g.a_cut[xb], g.b_rev[p]);
+        if (l2) atomic_add_i64(&work[(int64_t)g.n_a + yb], l2);
+    }
+}
+
+__global__ void k_count_bins(const int64_t* __restrict__ work, int64_t n, int32_t* small, int32_t* big, Ctl* ctl) {
+    unsigned long long tot = 0;
+    UNIFORM_STRIDE(base, n) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t w = i < n ? work[i] : 0;
+        tot += (unsigned long long)w;
+        wave_append(w > 0 && w <= kSmallMaxWedges, (int32_t)i, small, &ctl->n_items[0]);
+        wave_append(w > kSmallMaxWedges, (int32_t)i, big, &ctl->n_items[1]);
+    }
+    tot = (unsigned long long)wave_sum_i64((int64_t)tot);
+    if ((threadIdx.x & (kWave - 1)) == 0 && tot) atomicAdd(&ctl->wedges_count, tot);
+}
+
+__global__ void __launch_bounds__(kSmallThreads)
+k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64_t* bfly_a, int64_t* bfly_b) {
+    __shared__ WaveLds WL[kSmallThreads / kWave];
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    WaveLds& W = WL[wid];
+    for (int s = lane; s < kSmallSlots; s += kWave) W.tab[s] = 0;
+    wave_sync();
+    const int64_t n_items = ctl->n_items[0];
+    const int nw = kSmallThreads / kWave;
+    for (int64_t it = (int64_t)blockIdx.x * nw + wid; it < n_items; it += (int64_t)gridDim.x * nw) {
+        const int32_t item = items[it];
+        const bool side_b = item >= g.n_a;
+        const int32_t x = side_b ? item - g.n_a : item;
+        const SideView sv = side_view(g, side_b, bfly_a, bfly_b);
+        const int64_t e0 = sv.own_off[x], d = sv.own_off[x + 1] - e0;
+        // pass 1: wedge counts c(x, z)
+        for (int64_t g0 = 0; g0 < d; g0 += kWave) {
+            const int gs = (int)min<int64_t>(kWave, d - g0);
+            int64_t len = 0;
+            if (lane < gs) {
+                const int64_t e = e0 + g0 + lane;
+                const int32_t y = sv.own_adj[e];
+                W.sbeg[lane] = sv.oth_off[y];
+                len = min(sv.oth_cut[y], sv.own_rev[e]);
+            }
+            const int64_t tot = wave_scan_lengths(W, len);
+            for (int64_t i = lane; i < tot; i += kWave) {
+                const int j = wave_find_slice(W, gs, i);
+                wave_insert(W, (uint32_t)sv.oth_adj[W.sbeg[j] + (i - W.pre[j])]);
+            }
+            wave_sync();
+        }
+        // pass 2: middle vertices gain c - 1 per wedge
+        for (int64_t g0 = 0; g0 < d; g0 += kWave) {
+            const int gs = (int)min<int64_t>(kWave, d - g0);
+            int64_t len = 0;
+            int32_t y = 0;
+            if (lane < gs) {
+                const int64_t e = e0 + g0 + lane;
+                y = sv.own_adj[e];
+                W.sbeg[lane] = sv.oth_off[y];
+                len = min(sv.oth_cut[y], sv.own_rev[e]);
+            }
+            W.acc[lane] = 0;
+            const int64_t tot = wave_scan_lengths(W, len);
+            for (int64_t i = lane; i < tot; i += kWave) {
+                const int j = wave_find_slice(W, gs, i);
+                const int32_t c = wave_lookup(W, (uint32_t)sv.oth_adj[W.sbeg[j] + (i - W.pre[j])]);
+                if (c > 1) atomicAdd(reinterpret_cast<unsigned long long*>(&W.acc[j]), (unsigned long long)(c - 1));
+            }
+            wave_sync();
+            if (lane < gs && W.acc[lane]) atomic_add_i64(&sv.oth_bfly[y], W.acc[lane]);
+            wave_sync();
+        }
+        // pass 3: start and end vertices gain C(c, 2)
+        int64_t local = 0;
+        for (int s = lane; s < kSmallSlots; s += kWave) {
+            const unsigned long long v = W.tab[s];
+            if (v) {
+                const int64_t c = (int64_t)(v & 0xffffffffull);
+                if (c >= 2) {
+                    const int64_t b = choose2(c);
+                    atomic_add_i64(&sv.own_bfly[(int64_t)(v >> 32) - 1], b);
+                    local += b;
+                }
+                W.tab[s] = 0;
+            }
+        }
+        local = wave_sum_i64(local);
+        if (lane == 0 && local) atomic_add_i64(&sv.own_bfly[x], local);
+        wave_sync();
+    }
+}
+
+// Slice of the counting wedges of edge e restricted to keys [klo, khi).
+struct CountSlice {
+    __device__ static inline void get(const SideView& sv, int64_t e, bool multi, int32_t klo, int32_t khi,
+                                      int64_t& s0, int64_t& len) {
+        const int32_t y = sv.own_adj[e];
+        int64_t a = sv.oth_off[y];
+        int64_t b = a + min(sv.oth_cut[y], sv.own_rev[e]);
+        if (multi) {
+            a = lower_bound_i32(sv.oth_adj, a, b, klo);
+            b = lower_bound_i32(sv.oth_adj, a, b, khi);
+        }
+        s0 = a;
+        len = b - a;
+    }
+};
+
+__global__ void __launch_bounds__(kBigThreads)
+k_count_big(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64_t* bfly_a, int64_t* bfly_b,
+            SpillArena spa, Ctl* ctl_rw) {
+    __shared__ BigLds L;
+    constexpr int NT = kBigThreads;
+    const int tid = threadIdx.x;
+    bm_clear<NT>(L, kBmBits);
+    if (tid == 0) L.spill_n = 0;
+    __syncthreads();
+    const Spill sp{spa.dense + (int64_t)blockIdx.x * spa.stride, spa.list + (int64_t)blockIdx.x * spa.stride};
+    const int64_t n_items = ctl->n_items[1];
+    unsigned long long spills = 0;
+    for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int32_t item = items[it];
+        const bool side_b = item >= g.n_a;
+        const int32_t x = side_b ? item - g.n_a : item;
+        const SideView sv = side_view(g, side_b, bfly_a, bfly_b);
+        const int64_t e0 = sv.own_off[x], d = sv.own_off[x + 1] - e0;
+        const bool multi = x > kBmBits;
+        for (int32_t klo = 0; klo < x; klo += kBmBits) {
+            const int32_t khi = (int32_t)min<int64_t>(x, (int64_t)klo + kBmBits);
+            // pass 1
+            for (int64_t g0 = 0; g0 < d; g0 += kGroup) {
+                const int gs = (int)min<int64_t>(kGroup, d - g0);
+                int64_t len = 0;
+                if (tid < gs) {
+                    int64_t s0;
+                    CountSlice::get(sv, e0 + g0 + tid, multi, klo, khi, s0, len);
+                    L.sbeg[tid] = s0;
+                }
+                const int64_t tot = block_scan_lengths<NT>(L, gs, len);
+                for (int64_t i = tid; i < tot; i += NT) {
+                    const int j = find_slice(L, gs, i);
+                    bm_mark(L, sp, (uint32_t)(sv.oth_adj[L.sbeg[j] + (i - L.pre[j])] - klo));
+                }
+                __syncthreads();
+            }
+            const bool spilled = L.spill_n > 0;
+            // pass 2
+            for (int64_t g0 = 0; g0 < d; g0 += kGroup) {
+                const int gs = (int)min<int64_t>(kGroup, d - g0);
+                int64_t len = 0;
+                if (tid < gs) {
+                    int64_t s0;
+                    CountSlice::get(sv, e0 + g0 + tid, multi, klo, khi, s0, len);
+                    L.sbeg[tid] = s0;
+                    L.acc[tid] = 0;
+                }
+                const int64_t tot = block_scan_lengths<NT>(L, gs, len);
+                for (int64_t i = tid; i < tot; i += NT) {
+                    const int j = find_slice(L, gs, i);
+                    const uint32_t k = (uint32_t)(sv.oth_adj[L.sbeg[j] + (i - L.pre[j])] - klo);
+                    const int32_t c = rep_lookup(L, sp, spilled, k);
+                    if (c > 1) atomicAdd(reinterpret_cast<unsigned long long*>(&L.acc[j]), (unsigned long long)(c - 1));
+                }
+                __syncthreads();
+                if (tid < gs && L.acc[tid]) atomic_add_i64(&sv.oth_bfly[sv.own_adj[e0 + g0 + tid]], L.acc[tid]);
+                __syncthreads();
+            }
+            // pass 3
+            int64_t local = 0;
+            for (int s = tid; s < kRepSlots; s += NT) {
+                const unsigned long long v = L.rep[s];
+                if (v) {
+                    const int64_t c = 1 + (int64_t)(v & 0xffffffffull);
+                    const int64_t b = choose2(c);
+                    atomic_add_i64(&sv.own_bfly[klo + (int64_t)(v >> 32) - 1], b);
+                    local += b;
+                }
+            }
+            const int32_t nsp = L.spill_n;
+            spills += (tid == 0) ? (unsigned long long)nsp : 0ull;
+            for (int32_t i = tid; i < nsp; i += NT) {
+                const int32_t k = sp.list[i];
+                const int64_t b = choose2(1 + (int64_t)sp.dense[k]);
+                atomic_add_i64(&sv.own_bfly[klo + (int64_t)k], b);
+                local += b;
+                sp.dense[k] = 0;
+            }
+            const int64_t total = block_sum_i64<NT>(L, local);
+            if (tid == 0 && total) atomic_add_i64(&sv.own_bfly[x], total);
+            bm_clear<NT>(L, khi - klo);
+            if (tid == 0) L.spill_n = 0;
+            __syncthreads();
+        }
+    }
+    if (tid == 0 && spills) atomicAdd(&ctl_rw->spills, spills);
+}
+
+}  // namespace
+
+int count_occupancy() {
+    int n = 0;
+    TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_count_big, kBigThreads, 0));
+    return std::max(1, n);
+}
+
+void launch_count(const DevGraph& g, CountBuffers& cb, Ctl* ctl, const SpillArena& spill, int big_grid, hipStream_t s) {
+    const int64_t n_tot = (int64_t)g.n_a + g.n_b;
+    fill_i64(cb.bfly_a, 0, g.n_a, s);
+    fill_i64(cb.bfly_b, 0, g.n_b, s);
+    fill_i64(cb.work, 0, n_tot, s);
+    if (g.m == 0) return;
+    k_count_work<<<grid1(g.m), kT, 0, s>>>(g, cb.work);
+    TIP_HIP_TRY(hipGetLastError());
+    k_count_bins<<<grid1(n_tot, 4096), kT, 0, s>>>(cb.work, n_tot, cb.items_small, cb.items_big, ctl);
+    TIP_HIP_TRY(hipGetLastError());
+    k_count_small<<<2048, kSmallThreads, 0, s>>>(g, cb.items_small, ctl, cb.bfly_a, cb.bfly_b);
+    TIP_HIP_TRY(hipGetLastError());
+    k_count_big<<<big_grid, kBigThreads, 0, s>>>(g, cb.items_big, ctl, cb.bfly_a, cb.bfly_b, spill, ctl);
+    TIP_HIP_TRY(hipGetLastError());
+}
+
+}  // namespace tip

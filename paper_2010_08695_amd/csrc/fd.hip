@@ -1,0 +1,293 @@
+// Fine-grained decomposition (Alg. 4) and output scatter.
+#include "kern_util.h"
+
+namespace tip {
+namespace {
+// ===========================================================================
+// Fine-grained decomposition (Alg. 4)
+// ===========================================================================
+
+__global__ void k_fd_vertex_keys(const int32_t* __restrict__ state, int32_t n_a, uint64_t* keys, int32_t* vals,
+                                 int64_t* sub_cnt) {
+    GRID_STRIDE(u, (int64_t)n_a) {
+        const int32_t s = state[u];
+        keys[u] = (uint64_t)s;
+        vals[u] = (int32_t)u;
+        atomic_add_i64(&sub_cnt[s], 1);
+    }
+}
+
+__global__ void k_fd_positions(const int32_t* __restrict__ fd_vert, int32_t n_a, int32_t* fd_pos) {
+    GRID_STRIDE(p, (int64_t)n_a) fd_pos[fd_vert[p]] = (int32_t)p;
+}
+
+// Partitioned CSC: key (row, subset of the entry), value = entry's index
+// inside its subset.  The stable sort keeps each (row, subset) run ascending.
+__global__ void k_fd_csc_keys(DevGraph g, const int32_t* __restrict__ state, const int32_t* __restrict__ fd_pos,
+                              const int64_t* __restrict__ sub_off, int32_t S, uint64_t* keys, int32_t* vals) {
+    GRID_STRIDE(q, g.m) {
+        const int32_t w = g.b_adj[q];
+        const int32_t s = state[w];
+        keys[q] = (uint64_t)g.b_row[q] * (uint64_t)S + (uint64_t)s;
+        vals[q] = (int32_t)(fd_pos[w] - sub_off[s]);
+    }
+}
+
+__device__ inline int64_t lower_bound_u64(const uint64_t* __restrict__ a, int64_t lo, int64_t hi, uint64_t key) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// For every CSR edge (u, v): the run of N_v inside u's own subset, i.e. the
+// edges of the induced subgraph G_i seen from v (Alg. 4 induced subgraph).
+__global__ void k_fd_slices(DevGraph g, const int32_t* __restrict__ state, const uint64_t* __restrict__ pkeys,
+                            int32_t S, int64_t* fd_beg, int32_t* fd_len, int64_t* task_w) {
+    GRID_STRIDE(p, g.m) {
+        const int32_t u = g.a_row[p], v = g.a_adj[p];
+        const int32_t s = state[u];
+        const uint64_t k0 = (uint64_t)v * (uint64_t)S + (uint64_t)s;
+        const int64_t lo = lower_bound_u64(pkeys, g.b_off[v], g.b_off[v + 1], k0);
+        const int64_t hi = lower_bound_u64(pkeys, lo, g.b_off[v + 1], k0 + 1);
+        fd_beg[p] = lo;
+        fd_len[p] = (int32_t)(hi - lo);
+        if (hi - lo > 1) atomic_add_i64(&task_w[s], hi - lo - 1);
+    }
+}
+
+// Workload-aware schedule: subsets in decreasing order of induced wedges
+// (ties by subset id).
+__global__ void k_fd_order(const int64_t* __restrict__ task_w, int32_t S, int32_t* order) {
+    for (int32_t i = threadIdx.x; i < S; i += blockDim.x) {
+        const int64_t wi = task_w[i];
+        int32_t r = 0;
+        for (int32_t j = 0; j < S; ++j) {
+            const int64_t wj = task_w[j];
+            r += (wj > wi) || (wj == wi && j < i);
+        }
+        order[r] = i;
+    }
+}
+
+__global__ void k_fd_reset_head(Ctl* ctl) { ctl->fd_head = 0; }
+
+template <int NT>
+__device__ inline int32_t block_excl_scan_i32(BigLds& L, int32_t x, int32_t& total) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int64_t inc = wave_incl_scan_i64<NT>(x);
+    __syncthreads();
+    if (lane == kWave - 1) L.red[wid] = inc;
+    __syncthreads();
+    int64_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NT / kWave; ++w) {
+        const int64_t v = L.red[w];
+        off += w < wid ? v : 0;
+        tot += v;
+    }
+    total = (int32_t)tot;
+    __syncthreads();
+    return (int32_t)(off + inc - x);
+}
+
+// One workgroup peels one subset at a time, taking subsets from the
+// workload-sorted queue (dynamic allocation).  Inside a subset it runs
+// bottom-up peeling level by level: the level is max(level, minimum live
+// support), and every live vertex whose support is at most the level is
+// peeled at that level (equal to one-at-a-time peeling, whatever the order).
+__global__ void __launch_bounds__(kBigThreads)
+k_fd_peel(DevGraph g, FdBuffers fb, const int64_t* __restrict__ init, int32_t S, SpillArena spa, Ctl* ctl) {
+    __shared__ BigLds L;
+    constexpr int NT = kBigThreads;
+    const int tid = threadIdx.x;
+    bm_clear<NT>(L, kBmBits);
+    if (tid == 0) L.spill_n = 0;
+    __syncthreads();
+    const Spill sp{spa.dense + (int64_t)blockIdx.x * spa.stride, spa.list + (int64_t)blockIdx.x * spa.stride};
+    unsigned long long wedges = 0, pairs = 0, levels = 0, spills = 0;
+    for (;;) {
+        if (tid == 0) L.flag = atomicAdd(&ctl->fd_head, 1);
+        __syncthreads();
+        const int32_t t = L.flag;
+        __syncthreads();
+        if (t >= S) break;
+        const int32_t sub = fb.order[t];
+        const int64_t P0 = fb.sub_off[sub];
+        const int32_t n_i = (int32_t)(fb.sub_off[sub + 1] - P0);
+        if (n_i == 0) continue;
+        int32_t* lc = fb.lst[0] + P0;
+        int32_t* ln = fb.lst[1] + P0;
+        int32_t* pl = fb.lst[2] + P0;
+        int64_t* sup = fb.supp_fd + P0;
+        int32_t* alive = fb.alive + P0;
+        const int32_t* vert = fb.fd_vert + P0;
+        for (int32_t j = tid; j < n_i; j += NT) {
+            lc[j] = j;
+            sup[j] = init[vert[j]];
+            alive[j] = 1;
+        }
+        __syncthreads();
+        const bool multi = n_i > kBmBits;
+        int32_t n_live = n_i;
+        int64_t level = 0;
+        while (n_live > 0) {
+            int64_t mn = INT64_MAX;
+            for (int32_t j = tid; j < n_live; j += NT) {
+                const int64_t s = sup[lc[j]];
+                mn = s < mn ? s : mn;
+            }
+            mn = block_min_i64<NT>(L, mn);
+            level = mn > level ? mn : level;
+            int32_t n_peel = 0, n_keep = 0;
+            for (int32_t b0 = 0; b0 < n_live; b0 += NT) {
+                const int32_t j = b0 + tid;
+                int32_t x = 0;
+                bool pe = false, ke = false;
+                if (j < n_live) {
+                    x = lc[j];
+                    pe = sup[x] <= level;
+                    ke = !pe;
+                }
+                int32_t tp, tk;
+                const int32_t op = block_excl_scan_i32<NT>(L, pe ? 1 : 0, tp);
+                const int32_t ok = block_excl_scan_i32<NT>(L, ke ? 1 : 0, tk);
+                if (pe) {
+                    pl[n_peel + op] = x;
+                    alive[x] = 0;
+                    fb.theta[vert[x]] = level;
+                }
+                if (ke) ln[n_keep + ok] = x;
+                n_peel += tp;
+                n_keep += tk;
+            }
+            __syncthreads();
+            levels += tid == 0;
+            for (int32_t q = 0; q < n_peel; ++q) {
+                const int32_t x = pl[q];
+                if (sup[x] == 0) continue;
+                const int32_t ux = vert[x];
+                const int64_t e0 = g.a_off[ux], d = g.a_off[ux + 1] - e0;
+                for (int32_t klo = 0; klo < n_i; klo += kBmBits) {
+                    const int32_t khi = (int32_t)min<int64_t>(n_i, (int64_t)klo + kBmBits);
+                    const bool self_in = x >= klo && x < khi;
+                    for (int64_t g0 = 0; g0 < d; g0 += kGroup) {
+                        const int gs = (int)min<int64_t>(kGroup, d - g0);
+                        int64_t len = 0;
+                        if (tid < gs) {
+                            const int64_t e = e0 + g0 + tid;
+                            int64_t a = fb.fd_beg[e], b = a + fb.fd_len[e];
+                            if (multi) {
+                                a = lower_bound_i32(fb.pcsc, a, b, klo);
+                                b = lower_bound_i32(fb.pcsc, a, b, khi);
+                            }
+                            L.sbeg[tid] = a;
+                            len = b - a;
+                        }
+                        const int64_t tot = block_scan_lengths<NT>(L, gs, len);
+                        for (int64_t i = tid; i < tot; i += NT) {
+                            const int j = find_slice(L, gs, i);
+                            const int32_t w = fb.pcsc[L.sbeg[j] + (i - L.pre[j])];
+                            if (w != x) bm_mark(L, sp, (uint32_t)(w - klo));
+                        }
+                        if (tid == 0) wedges += (unsigned long long)(tot - (self_in ? gs : 0));
+                        __syncthreads();
+                    }
+                    for (int s = tid; s < kRepSlots; s += NT) {
+                        const unsigned long long v = L.rep[s];
+                        if (v) {
+                            const int32_t w = klo + (int32_t)((v >> 32) - 1);
+                            if (alive[w]) {
+                                atomic_add_i64(&sup[w], -choose2(1 + (int64_t)(v & 0xffffffffull)));
+                                ++pairs;
+                            }
+                        }
+                    }
+                    const int32_t nsp = L.spill_n;
+                    if (tid == 0) spills += (unsigned long long)nsp;
+                    for (int32_t i = tid; i < nsp; i += NT) {
+                        const int32_t k = sp.list[i];
+                        const int32_t w = klo + k;
+                        if (alive[w]) {
+                            atomic_add_i64(&sup[w], -choose2(1 + (int64_t)sp.dense[k]));
+                            ++pairs;
+                        }
+                        sp.dense[k] = 0;
+                    }
+                    __syncthreads();
+                    bm_clear<NT>(L, khi - klo);
+                    if (tid == 0) L.spill_n = 0;
+                    __syncthreads();
+                }
+            }
+            int32_t* tmp = lc;
+            lc = ln;
+            ln = tmp;
+            n_live = n_keep;
+        }
+    }
+    wedges = (unsigned long long)wave_sum_i64((int64_t)wedges);
+    pairs = (unsigned long long)wave_sum_i64((int64_t)pairs);
+    levels = (unsigned long long)wave_sum_i64((int64_t)levels);
+    spills = (unsigned long long)wave_sum_i64((int64_t)spills);
+    if ((tid & (kWave - 1)) == 0) {
+        if (wedges) atomicAdd(&ctl->wedges_fd, wedges);
+        if (pairs) atomicAdd(&ctl->pair_updates, pairs);
+        if (levels) atomicAdd(&ctl->fd_levels, levels);
+        if (spills) atomicAdd(&ctl->spills, spills);
+    }
+}
+
+__global__ void k_scatter_i64(const int64_t* __restrict__ by_rank, const int32_t* __restrict__ orig, int32_t n,
+                              int64_t* out) {
+    GRID_STRIDE(r, (int64_t)n) out[orig[r]] = by_rank[r];
+}
+
+}  // namespace
+
+int fd_occupancy() {
+    int n = 0;
+    TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fd_peel, kBigThreads, 0));
+    return std::max(1, n);
+}
+
+void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl, const SpillArena& spill,
+               int big_grid, uint64_t* tmp_keys, int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp,
+               uint64_t* keys_scratch, int32_t* vals_scratch, hipStream_t s) {
+    const int32_t n_a = g.n_a;
+    if (n_a <= 0) return;
+    // vertices grouped by subset, ascending rank inside each subset
+    fill_i64(fb.sub_cnt, 0, (int64_t)S + 1, s);
+    k_fd_vertex_keys<<<grid1(n_a), kT, 0, s>>>(pb.state, n_a, keys_scratch, fb.fd_vert, fb.sub_cnt);
+    TIP_HIP_TRY(hipGetLastError());
+    radix_sort_pairs(keys_scratch, fb.fd_vert, tmp_keys, tmp_vals, n_a, bits_for((uint64_t)S), hist, scan_tmp, s);
+    scan_exclusive_i64(fb.sub_cnt, fb.sub_off, (int64_t)S + 1, scan_tmp, s);
+    k_fd_positions<<<grid1(n_a), kT, 0, s>>>(fb.fd_vert, n_a, fb.fd_pos);
+    TIP_HIP_TRY(hipGetLastError());
+    fill_i64(fb.task_w, 0, S, s);
+    if (g.m > 0) {
+        k_fd_csc_keys<<<grid1(g.m), kT, 0, s>>>(g, pb.state, fb.fd_pos, fb.sub_off, S, fb.pkeys, fb.pcsc);
+        TIP_HIP_TRY(hipGetLastError());
+        radix_sort_pairs(fb.pkeys, fb.pcsc, tmp_keys, tmp_vals, g.m,
+                         bits_for((uint64_t)g.n_b * (uint64_t)S), hist, scan_tmp, s);
+        k_fd_slices<<<grid1(g.m), kT, 0, s>>>(g, pb.state, fb.pkeys, S, fb.fd_beg, fb.fd_len, fb.task_w);
+        TIP_HIP_TRY(hipGetLastError());
+    }
+    k_fd_order<<<1, 1024, 0, s>>>(fb.task_w, S, fb.order);
+    TIP_HIP_TRY(hipGetLastError());
+    k_fd_reset_head<<<1, 1, 0, s>>>(ctl);
+    TIP_HIP_TRY(hipGetLastError());
+    const int grid = std::max(1, std::min<int>(S, big_grid));
+    k_fd_peel<<<grid, kBigThreads, 0, s>>>(g, fb, pb.init, S, spill, ctl);
+    TIP_HIP_TRY(hipGetLastError());
+}
+
+void launch_scatter_i64(const int64_t* by_rank, const int32_t* orig, int32_t n, int64_t* out, hipStream_t s) {
+    if (n <= 0) return;
+    k_scatter_i64<<<grid1(n), kT, 0, s>>>(by_rank, orig, n, out);
+    TIP_HIP_TRY(hipGetLastError());
+}
+
+}  // namespace tip

@@ -1,0 +1,774 @@
+// Coarse-grained decomposition (Alg. 3): range bounds, activeSets and the
+// delete-update peeling kernels.
+//
+// Supports are stored raw (uncapped) and decremented with 64-bit atomics; the
+// cap of the paper's update (never below the current level) is applied when a
+// support is read: the effective support is max(level, raw).  A live vertex's
+// raw support is exactly its butterflies with the other live vertices, so it
+// never underflows.
+//
+// A peeled vertex u's update aggregates c(u, w) over its 2-hop neighbourhood
+// (Alg. 2, update).  Three kernels share the work by the size of that
+// neighbourhood (w[u], the wedges of u in the original graph):
+//   * wave path: a few hundred wedges, one wavefront per vertex with its own
+//     LDS hash table of every key;
+//   * bitmap path: one workgroup per vertex, one LDS bit per key of a key
+//     tile, keys reached again go to an LDS table of repeat counts;
+//   * dense path: 2-hop neighbourhoods that cover a large share of the key
+//     space; one small workgroup per (vertex, key tile) with an 8- or 16-bit
+//     counter per key, so a heavy vertex is spread over many workgroups.
+// All lists of the other side are sorted, so the part of N_v inside a key
+// tile is a contiguous run whose bounds come from a per-list table.
+#include "kern_util.h"
+
+namespace tip {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Shared staging of neighbour-list runs and unit-wise traversal
+// ---------------------------------------------------------------------------
+
+template <int NT>
+struct Stage {
+    int64_t sbeg[NT];
+    int32_t len[NT];
+    int32_t upre[NT + 1];
+    int64_t red[NT / kWave];
+};
+
+// Stages the runs held by threads j < gs (one run per thread: start, length)
+// and returns the number of traversal units (kUnit entries of one run).
+template <int NT>
+__device__ inline int32_t stage_units(Stage<NT>& S, int gs, int64_t s0, int32_t len) {
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const int32_t units = tid < gs ? (len + kUnit - 1) / kUnit : 0;
+    if (tid < gs) {
+        S.sbeg[tid] = s0;
+        S.len[tid] = len;
+    }
+    const int64_t inc = wave_incl_scan_i64<NT>(units);
+    __syncthreads();
+    if (lane == kWave - 1) S.red[wid] = inc;
+    __syncthreads();
+    int64_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NT / kWave; ++w) {
+        const int64_t v = S.red[w];
+        off += w < wid ? v : 0;
+        tot += v;
+    }
+    if (tid < gs) S.upre[tid] = (int32_t)(off + inc - units);
+    if (tid == 0) S.upre[gs] = (int32_t)tot;
+    __syncthreads();
+    return (int32_t)tot;
+}
+
+// Every wave takes units in turn; a unit is read with coalesced loads.
+template <int NT, class F>
+__device__ inline void traverse_units(const Stage<NT>& S, int gs, int32_t nunits, const int32_t* __restrict__ adj,
+                                      F&& f) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    for (int32_t k = wid; k < nunits; k += NT / kWave) {
+        int lo = 0, hi = gs;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (S.upre[mid] <= k) lo = mid;
+            else hi = mid;
+        }
+        const int32_t off = (k - S.upre[lo]) * kUnit;
+        const int32_t n = min(kUnit, S.len[lo] - off);
+        const int32_t* p = adj + S.sbeg[lo] + off;
+        const int32_t x0 = lane < n ? p[lane] : -1;
+        const int32_t x1 = lane + kWave < n ? p[lane + kWave] : -1;
+        if (x0 >= 0) f(x0);
+        if (x1 >= 0) f(x1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Range set-up kernels
+// ---------------------------------------------------------------------------
+
+// w[u]: wedges of G with endpoint u (the range-sizing proxy), i.e. the sum
+// over v in N_u of d_v - 1.
+__global__ void k_wproxy(DevGraph g, const int32_t* __restrict__ deg_b, int64_t* wprox) {
+    GRID_STRIDE(p, g.m) {
+        const int32_t dv = deg_b[g.a_adj[p]];
+        if (dv > 1) atomic_add_i64(&wprox[g.a_row[p]], dv - 1);
+    }
+}
+
+// Which update kernel peels u: by its wedge count and degree (the counter
+// width of the dense kernel must hold c(u, w) <= d_u).
+__global__ void k_peel_bins(const int64_t* __restrict__ a_off, const int64_t* __restrict__ wprox, int32_t n_a,
+                            int64_t w_dense, uint8_t* bin) {
+    GRID_STRIDE(u, (int64_t)n_a) {
+        const int64_t w = wprox[u];
+        const int64_t d = a_off[u + 1] - a_off[u];
+        uint8_t b = kBinBitmap;
+        if (w <= kSmallMaxWedges) b = kBinWave;
+        else if (w > w_dense && d <= kDense8MaxDegree) b = kBinDense8;
+        else if (w > w_dense && d <= kDense16MaxDegree) b = kBinDense16;
+        bin[u] = b;
+    }
+}
+
+// tb[v * (ntt + 1) + t] = offset in N_v of the first entry >= t * tk.
+__global__ void k_tile_bounds(const int64_t* __restrict__ b_off, const int32_t* __restrict__ b_adj, int32_t n_b,
+                              int32_t tk, int32_t ntt, int32_t* tb) {
+    const int64_t n = (int64_t)n_b * (ntt + 1);
+    GRID_STRIDE(i, n) {
+        const int64_t v = i / (ntt + 1);
+        const int32_t t = (int32_t)(i % (ntt + 1));
+        const int64_t lo = b_off[v], hi = b_off[v + 1];
+        int64_t pos = hi;
+        if (t < ntt) pos = lower_bound_i32(b_adj, lo, hi, (int32_t)min<int64_t>((int64_t)t * tk, INT32_MAX));
+        tb[i] = (int32_t)(pos - lo);
+    }
+}
+
+__global__ void k_ctl_begin_range(Ctl* ctl) {
+    ctl->n_live_next = 0;
+    ctl->max_supp = 0;
+    ctl->w_rem = 0;
+    ctl->w_range = 0;
+    for (int b = 0; b < kBins; ++b) ctl->n_front[b] = ctl->n_next[b] = 0;
+}
+
+// Compacts the live list, snapshots the supports of the live vertices
+// (Alg. 3 support init) and reduces the maximum support and the wedge proxy
+// of the remaining vertices.
+__global__ void k_range_start(const int32_t* __restrict__ live_in, int32_t n_in, int32_t* live_out,
+                              const int32_t* __restrict__ state, const int64_t* __restrict__ supp, int64_t* init,
+                              const int64_t* __restrict__ wprox, Ctl* ctl) {
+    unsigned long long mx = 0;
+    long long ws = 0;
+    UNIFORM_STRIDE(base, (int64_t)n_in) {
+        const int64_t j = base + threadIdx.x;
+        int32_t u = 0;
+        bool keep = false;
+        if (j < n_in) {
+            u = live_in[j];
+            keep = state[u] == kLive;
+        }
+        if (keep) {
+            const int64_t su = supp[u];
+            init[u] = su;
+            mx = max(mx, (unsigned long long)su);
+            ws += wprox[u];
+        }
+        wave_append(keep, u, live_out, &ctl->n_live_next);
+    }
+    __shared__ unsigned long long smx[kT / kWave];
+    __shared__ long long sws[kT / kWave];
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        const unsigned long long o = __shfl_xor(mx, d, kWave);
+        mx = o > mx ? o : mx;
+    }
+    ws = wave_sum_i64(ws);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) {
+        smx[wid] = mx;
+        sws[wid] = ws;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m2 = 0;
+        long long w2 = 0;
+        for (int w = 0; w < kT / kWave; ++w) {
+            m2 = smx[w] > m2 ? smx[w] : m2;
+            w2 += sws[w];
+        }
+        if (m2) atomicMax(&ctl->max_supp, m2);
+        if (w2) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->w_rem), (unsigned long long)w2);
+    }
+}
+
+__global__ void k_ctl_select_init(Ctl* ctl, long long tgt) {
+    ctl->sel_prefix = 0;
+    ctl->sel_cum = 0;
+    ctl->sel_found = 1;
+    ctl->sel_tgt = tgt;
+}
+
+// findHi as a weighted radix select: one 8-bit digit per pass, most
+// significant first.  The histogram adds w[u] over live u whose support
+// matches the prefix chosen so far.
+__global__ void k_select_hist(const int32_t* __restrict__ live, int32_t n_live, const int64_t* __restrict__ supp,
+                              const int64_t* __restrict__ wprox, int shift, const Ctl* ctl, int64_t* hist) {
+    if (!ctl->sel_found) return;
+    __shared__ unsigned long long h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t prefix = ctl->sel_prefix;
+    const int hs = shift + 8;
+    GRID_STRIDE(j, (int64_t)n_live) {
+        const int32_t u = live[j];
+        const uint64_t key = (uint64_t)supp[u];
+        if (hs >= 64 || (key >> hs) == (prefix >> hs))
+            atomicAdd(&h[(key >> shift) & 255], (unsigned long long)wprox[u]);
+    }
+    __syncthreads();
+    if (h[threadIdx.x]) atomicAdd(reinterpret_cast<unsigned long long*>(&hist[threadIdx.x]), h[threadIdx.x]);
+}
+
+__global__ void k_select_pick(int shift, Ctl* ctl, int64_t* hist) {
+    __shared__ long long hh[256];
+    hh[threadIdx.x] = hist[threadIdx.x];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0 && ctl->sel_found) {
+        long long run = ctl->sel_cum;
+        const long long tgt = ctl->sel_tgt;
+        int chosen = -1;
+        for (int d = 0; d < 256; ++d) {
+            if (run + hh[d] >= tgt) {
+                chosen = d;
+                break;
+            }
+            run += hh[d];
+        }
+        if (chosen < 0) {
+            ctl->sel_found = 0;
+        } else {
+            ctl->sel_cum = run;
+            ctl->sel_prefix |= (unsigned long long)chosen << shift;
+        }
+    }
+}
+
+struct Fronts {
+    int32_t* list[kBins];
+    int32_t* count;  // [kBins]
+};
+
+// Appends u to the frontier list of its bin; all lanes of the wave must call.
+__device__ inline void append_binned(bool pred, int32_t u, uint8_t b, const Fronts& f) {
+#pragma unroll
+    for (int k = 0; k < kBins; ++k) wave_append(pred && b == k, u, f.list[k], &f.count[k]);
+}
+
+// First activeSet of a range: live vertices with support below the upper
+// bound.  They are assigned to the subset here; vertices with zero support
+// share no butterfly with any live vertex and need no update.
+__global__ void k_frontier_init(const int32_t* __restrict__ live, int32_t n_live, const int64_t* __restrict__ supp,
+                                int32_t* state, const int64_t* __restrict__ wprox, const uint8_t* __restrict__ bin,
+                                long long hi, int32_t label, Fronts fr, Ctl* ctl) {
+    long long ws = 0;
+    unsigned long long skipped = 0;
+    UNIFORM_STRIDE(base, (int64_t)n_live) {
+        const int64_t j = base + threadIdx.x;
+        bool pred = false;
+        int32_t u = 0;
+        uint8_t b = 0;
+        if (j < n_live) {
+            u = live[j];
+            const int64_t su = supp[u];
+            if (su < hi) {
+                state[u] = label;
+                ws += wprox[u];
+                if (su == 0) ++skipped;
+                else {
+                    pred = true;
+                    b = bin[u];
+                }
+            }
+        }
+        append_binned(pred, u, b, fr);
+    }
+    ws = wave_sum_i64(ws);
+    skipped = (unsigned long long)wave_sum_i64((int64_t)skipped);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        if (ws) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->w_range), (unsigned long long)ws);
+        if (skipped) atomicAdd(&ctl->skipped, skipped);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Delete-update
+// ---------------------------------------------------------------------------
+
+// Applies the decrement C(c, 2) of a (peeled u, live w) pair and appends w to
+// the next activeSet when its support crosses below the range's upper bound.
+struct CdApply {
+    int64_t* supp;
+    const int32_t* state;
+    const uint8_t* bin;
+    long long hi;
+    Fronts next;
+
+    // Must be reached by all lanes of the wave.
+    __device__ inline void apply(bool valid, int32_t w, int64_t c, unsigned long long& pairs) const {
+        bool cross = false;
+        uint8_t b = 0;
+        if (valid && c >= 2 && state[w] == kLive) {
+            const int64_t dec = choose2(c);
+            const int64_t old = atomic_add_i64_ret(&supp[w], -dec);
+            cross = old >= hi && old - dec < hi;
+            ++pairs;
+            if (cross) b = bin[w];
+        }
+        append_binned(cross, w, b, next);
+    }
+};
+
+struct PeelCounters {
+    unsigned long long wedges = 0, pairs = 0, skipped = 0, spills = 0, edges = 0;
+
+    __device__ inline void flush(Ctl* ctl, bool big) {
+        wedges = (unsigned long long)wave_sum_i64((int64_t)wedges);
+        pairs = (unsigned long long)wave_sum_i64((int64_t)pairs);
+        skipped = (unsigned long long)wave_sum_i64((int64_t)skipped);
+        spills = (unsigned long long)wave_sum_i64((int64_t)spills);
+        edges = (unsigned long long)wave_sum_i64((int64_t)edges);
+        if ((threadIdx.x & (kWave - 1)) == 0) {
+            if (wedges) atomicAdd(&ctl->wedges_cd, wedges);
+            if (pairs) atomicAdd(&ctl->pair_updates, pairs);
+            if (skipped) atomicAdd(&ctl->skipped, skipped);
+            if (spills) atomicAdd(&ctl->spills, spills);
+            if (big) {
+                if (wedges) atomicAdd(&ctl->big_wedges, wedges);
+                if (pairs) atomicAdd(&ctl->big_pairs, pairs);
+                if (edges) atomicAdd(&ctl->big_edges, edges);
+            }
+        }
+    }
+};
+
+// Wave path: one wavefront per vertex, every 2-hop key in a per-wave LDS hash
+// table sized to the vertex's wedge count.
+__global__ void __launch_bounds__(kSmallThreads)
+k_peel_wave(DevGraph g, const int32_t* __restrict__ front, const int32_t* n_front_p, CdApply ap, Ctl* ctl) {
+    __shared__ WaveLds WL[kSmallThreads / kWave];
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    WaveLds& W = WL[wid];
+    for (int s = lane; s < kSmallSlots; s += kWave) W.tab[s] = 0;
+    wave_sync();
+    const int64_t n_front = *n_front_p;
+    const int nw = kSmallThreads / kWave;
+    PeelCounters pc;
+    for (int64_t it = (int64_t)blockIdx.x * nw + wid; it < n_front; it += (int64_t)gridDim.x * nw) {
+        const int32_t u = front[it];
+        if (ap.supp[u] == 0) {
+            pc.skipped += lane == 0;
+            continue;
+        }
+        const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
+        for (int64_t g0 = 0; g0 < d; g0 += kWave) {
+            const int gs = (int)min<int64_t>(kWave, d - g0);
+            int64_t len = 0;
+            if (lane < gs) {
+                const int32_t v = g.a_adj[e0 + g0 + lane];
+                W.sbeg[lane] = g.b_off[v];
+                len = g.b_off[v + 1] - W.sbeg[lane];
+            }
+            const int64_t tot = wave_scan_lengths(W, len);
+            for (int64_t i = lane; i < tot; i += kWave) {
+                const int j = wave_find_slice(W, gs, i);
+                const int32_t w = g.b_adj[W.sbeg[j] + (i - W.pre[j])];
+                if (w != u) wave_insert(W, (uint32_t)w);
+            }
+            if (lane == 0) pc.wedges += (unsigned long long)(tot - gs);
+            wave_sync();
+        }
+        for (int s = lane; s < kSmallSlots; s += kWave) {
+            const unsigned long long v = W.tab[s];
+            if (v) W.tab[s] = 0;
+            ap.apply(v != 0, (int32_t)((v >> 32) - 1), (int64_t)(v & 0xffffffffull), pc.pairs);
+        }
+        wave_sync();
+    }
+    pc.flush(ctl, false);
+}
+
+// Bitmap path LDS: one bit per key of a kBmTile-key tile, a table of repeat
+// counts, staging.
+struct BmLds {
+    uint32_t bm[kBmTile / 32];
+    unsigned long long rep[kBmRep];
+    Stage<kBigThreads> st;
+    int32_t spill_n;
+};
+
+__device__ inline void bm_rep_insert(BmLds& L, const Spill& sp, uint32_t k) {
+    const unsigned long long tag = (unsigned long long)(k + 1) << 32;
+    const uint32_t h = hash32(k) & (kBmRep - 1);
+#pragma unroll 1
+    for (int p = 0; p < kRepProbe; ++p) {
+        unsigned long long* slot = &L.rep[(h + p) & (kBmRep - 1)];
+        unsigned long long cur = __atomic_load_n(slot, __ATOMIC_RELAXED);
+        if (cur == 0) {
+            const unsigned long long prev = atomicCAS(slot, 0ull, tag | 1ull);
+            if (prev == 0) return;
+            cur = prev;
+        }
+        if ((cur & 0xffffffff00000000ull) == tag) {
+            atomicAdd(slot, 1ull);
+            return;
+        }
+    }
+    if (atomicAdd(&sp.dense[k], 1) == 0) {
+        const int32_t idx = atomicAdd(&L.spill_n, 1);
+        sp.list[idx] = (int32_t)k;
+    }
+}
+
+__global__ void __launch_bounds__(kBigThreads)
+k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, const int32_t* __restrict__ front,
+              const int32_t* n_front_p, CdApply ap, SpillArena spa, Ctl* ctl) {
+    __shared__ BmLds L;
+    constexpr int NT = kBigThreads;
+    constexpr int kPer = kBmRep / NT;  // repeat slots scanned by each thread
+    static_assert(kBmRep % NT == 0 && kPer <= 32, "repeat slots per thread");
+    const int tid = threadIdx.x;
+    for (int w = tid; w < kBmTile / 32; w += NT) L.bm[w] = 0;
+    for (int s = tid; s < kBmRep; s += NT) L.rep[s] = 0;
+    if (tid == 0) L.spill_n = 0;
+    __syncthreads();
+    const Spill sp{spa.dense + (int64_t)blockIdx.x * spa.stride, spa.list + (int64_t)blockIdx.x * spa.stride};
+    const int64_t n_front = *n_front_p;
+    const int32_t sub = kBmTile / tk;  // table tiles per bitmap tile
+    PeelCounters pc;
+    for (int64_t it = blockIdx.x; it < n_front; it += gridDim.x) {
+        const int32_t u = front[it];
+        if (ap.supp[u] == 0) {
+            pc.skipped += tid == 0;
+            continue;
+        }
+        const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
+        if (tid == 0) pc.edges += (unsigned long long)d;
+        for (int32_t klo = 0; klo < g.n_a; klo += kBmTile) {
+            const int32_t khi = (int32_t)min<int64_t>(g.n_a, (int64_t)klo + kBmTile);
+            const int32_t t0 = klo / tk, t1 = min(t0 + sub, ntt);
+            for (int64_t g0 = 0; g0 < d; g0 += NT) {
+                const int gs = (int)min<int64_t>(NT, d - g0);
+                int64_t s0 = 0;
+                int32_t len = 0;
+                if (tid < gs) {
+                    const int32_t v = g.a_adj[e0 + g0 + tid];
+                    const int32_t* row = tb + (int64_t)v * (ntt + 1);
+                    const int32_t a = row[t0];
+                    s0 = g.b_off[v] + a;
+                    len = row[t1] - a;
+                }
+                const int32_t nu = stage_units<NT>(L.st, gs, s0, len);
+                unsigned long long wl = 0;
+                traverse_units<NT>(L.st, gs, nu, g.b_adj, [&](int32_t w) {
+                    if (w != u) {
+                        ++wl;
+                        const uint32_t k = (uint32_t)(w - klo);
+                        const uint32_t bit = 1u << (k & 31);
+                        if (atomicOr(&L.bm[k >> 5], bit) & bit) bm_rep_insert(L, sp, k);
+                    }
+                });
+                pc.wedges += wl;
+                __syncthreads();
+            }
+            // repeat keys: each thread owns kPer slots; apply one occupied slot
+            // per lane and step until no lane of the wave has any left
+            unsigned long long held[kPer];
+            uint32_t mask = 0;
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                held[q] = L.rep[tid + q * NT];
+                if (held[q]) mask |= 1u << q;
+            }
+            while (__ballot(mask != 0)) {
+                unsigned long long v = 0;
+                if (mask) {
+                    const int q = __ffs(mask) - 1;
+                    mask &= mask - 1;
+#pragma unroll
+                    for (int r = 0; r < kPer; ++r)
+                        if (r == q) v = held[r];
+                }
+                ap.apply(v != 0, klo + (int32_t)((v >> 32) - 1), 1 + (int64_t)(v & 0xffffffffull), pc.pairs);
+            }
+            const int32_t nsp = L.spill_n;
+            if (tid == 0) pc.spills += (unsigned long long)nsp;
+            for (int32_t b0 = 0; b0 < nsp; b0 += NT) {
+                const int32_t i = b0 + tid;
+                int32_t k = 0, r = 0;
+                if (i < nsp) {
+                    k = sp.list[i];
+                    r = sp.dense[k];
+                    sp.dense[k] = 0;
+                }
+                ap.apply(i < nsp, klo + k, 1 + (int64_t)r, pc.pairs);
+            }
+            __syncthreads();
+            const int32_t words = (khi - klo + 31) >> 5;
+            for (int w = tid; w < words; w += NT) L.bm[w] = 0;
+            for (int s = tid; s < kBmRep; s += NT) L.rep[s] = 0;
+            if (tid == 0) L.spill_n = 0;
+            __syncthreads();
+        }
+    }
+    pc.flush(ctl, true);
+}
+
+// Dense path: work item k = (frontier vertex k / ntt, key tile k % ntt).
+// Counters are CB bytes wide (CB = 1 or 2); the bins guarantee
+// c(u, w) <= d_u fits.  LDS: tk * CB counter bytes (dynamic) + staging.
+template <int CB>
+__global__ void __launch_bounds__(kDenseThreads)
+k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, const int32_t* __restrict__ front,
+             const int32_t* n_front_p, CdApply ap, Ctl* ctl) {
+    constexpr int NT = kDenseThreads;
+    constexpr int PER_WORD = 4 / CB;             // counters per 32-bit word
+    constexpr uint32_t CMASK = CB == 1 ? 0xffu : 0xffffu;
+    extern __shared__ __align__(16) uint32_t dyn[];
+    uint32_t* cnt = dyn;
+    Stage<NT>& S = *reinterpret_cast<Stage<NT>*>(dyn + (int64_t)tk * CB / 4);
+    uint4* cnt4 = reinterpret_cast<uint4*>(cnt);
+    const int tid = threadIdx.x;
+    const int32_t n4 = tk * CB / 16;            // uint4 words per tile
+    for (int w = tid; w < n4; w += NT) cnt4[w] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+    const int64_t n_items = (int64_t)(*n_front_p) * ntt;
+    PeelCounters pc;
+    for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int32_t u = front[it / ntt];
+        const int32_t t = (int32_t)(it % ntt);
+        if (ap.supp[u] == 0) {
+            pc.skipped += (tid == 0 && t == 0);
+            continue;
+        }
+        const int32_t klo = t * tk;
+        const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
+        if (tid == 0 && t == 0) pc.edges += (unsigned long long)d;
+        for (int64_t g0 = 0; g0 < d; g0 += NT) {
+            const int gs = (int)min<int64_t>(NT, d - g0);
+            int64_t s0 = 0;
+            int32_t len = 0;
+            if (tid < gs) {
+                const int32_t v = g.a_adj[e0 + g0 + tid];
+                const int32_t* row = tb + (int64_t)v * (ntt + 1);
+                const int32_t a = row[t];
+                s0 = g.b_off[v] + a;
+                len = row[t + 1] - a;
+            }
+            const int32_t nu = stage_units<NT>(S, gs, s0, len);
+            unsigned long long wl = 0;
+            traverse_units<NT>(S, gs, nu, g.b_adj, [&](int32_t w) {
+                if (w != u) {
+                    ++wl;
+                    const uint32_t k = (uint32_t)(w - klo);
+                    atomicAdd(&cnt[k / PER_WORD], 1u << ((k % PER_WORD) * 8 * CB));
+                }
+            });
+            pc.wedges += wl;
+            __syncthreads();
+        }
+        // keys with c >= 2: apply (one per lane per step), then clear the tile
+        for (int32_t w4 = tid; w4 < n4; w4 += NT) {
+            const uint4 x = cnt4[w4];
+            const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+            if (x.x | x.y | x.z | x.w) cnt4[w4] = make_uint4(0, 0, 0, 0);
+            uint32_t mask = 0;  // counters >= 2, bit i = counter i of the 16 (or 8)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int b = 0; b < PER_WORD; ++b)
+                    if (((xs[q] >> (8 * CB * b)) & CMASK) >= 2) mask |= 1u << (q * PER_WORD + b);
+            while (__ballot(mask != 0)) {
+                int64_t c = 0;
+                int32_t key = 0;
+                if (mask) {
+                    const int i = __ffs(mask) - 1;
+                    mask &= mask - 1;
+                    const int q = i / PER_WORD, b = i % PER_WORD;
+                    uint32_t word = 0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (r == q) word = xs[r];
+                    c = (word >> (8 * CB * b)) & CMASK;
+                    key = klo + w4 * (4 * PER_WORD) + i;
+                }
+                ap.apply(c >= 2, key, c, pc.pairs);
+            }
+        }
+        __syncthreads();
+    }
+    pc.flush(ctl, true);
+}
+
+size_t dense_lds_bytes(int32_t tk, int cb) { return (size_t)tk * cb + sizeof(Stage<kDenseThreads>); }
+
+// Vertices that crossed below the upper bound during the round become the
+// next activeSet: assign them to the subset before any of them is peeled.
+__global__ void k_round_end(Fronts nx, int32_t* state, const int64_t* __restrict__ wprox, int32_t label, Ctl* ctl) {
+    int64_t n[kBins], tot = 0;
+#pragma unroll
+    for (int b = 0; b < kBins; ++b) {
+        n[b] = nx.count[b];
+        tot += n[b];
+    }
+    long long ws = 0;
+    GRID_STRIDE(j, tot) {
+        int64_t r = j;
+        int b = 0;
+        while (r >= n[b]) {
+            r -= n[b];
+            ++b;
+        }
+        const int32_t u = nx.list[b][r];
+        state[u] = label;
+        ws += wprox[u];
+    }
+    ws = wave_sum_i64(ws);
+    if ((threadIdx.x & (kWave - 1)) == 0 && ws)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->w_range), (unsigned long long)ws);
+}
+
+__global__ void k_ctl_swap_front(Ctl* ctl) {
+    for (int b = 0; b < kBins; ++b) {
+        ctl->n_front[b] = ctl->n_next[b];
+        ctl->n_next[b] = 0;
+    }
+}
+
+__global__ void k_assign_live(const int32_t* __restrict__ live, int32_t n_live, int32_t* state, int32_t label) {
+    GRID_STRIDE(j, (int64_t)n_live) state[live[j]] = label;
+}
+
+Fronts fronts_of(PeelBuffers& pb, int buf, int32_t* counts) {
+    Fronts f;
+    for (int b = 0; b < kBins; ++b) f.list[b] = pb.front[buf][b];
+    f.count = counts;
+    return f;
+}
+
+}  // namespace
+
+int peel_occupancy() {
+    int a = 0;
+    TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_peel_bitmap, kBigThreads, 0));
+    return std::max(1, a);
+}
+
+// Resident dense-kernel workgroups per CU for a tile size (LDS-limited).
+static int dense_occupancy(int32_t tk, int cb) {
+    int a = 0;
+    if (cb == 1)
+        TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_peel_dense<1>, kDenseThreads,
+                                                                 dense_lds_bytes(tk, 1)));
+    else
+        TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_peel_dense<2>, kDenseThreads,
+                                                                 dense_lds_bytes(tk, 2)));
+    return std::max(1, a);
+}
+
+void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers& pb, int64_t w_dense,
+                       hipStream_t s) {
+    fill_i64(pb.wprox, 0, g.n_a, s);
+    if (g.m > 0) {
+        k_wproxy<<<grid1(g.m), kT, 0, s>>>(g, deg_b_rank, pb.wprox);
+        TIP_HIP_TRY(hipGetLastError());
+    }
+    if (g.n_a > 0) {
+        k_peel_bins<<<grid1(g.n_a), kT, 0, s>>>(g.a_off, pb.wprox, g.n_a, w_dense, pb.bin);
+        TIP_HIP_TRY(hipGetLastError());
+    }
+    const int64_t n_tb = (int64_t)g.n_b * (pb.ntt + 1);
+    if (n_tb > 0) {
+        k_tile_bounds<<<grid1(n_tb), kT, 0, s>>>(g.b_off, g.b_adj, g.n_b, pb.tk, pb.ntt, pb.tb);
+        TIP_HIP_TRY(hipGetLastError());
+    }
+}
+
+void launch_range_start(PeelBuffers& pb, int cur_live, int32_t n_live, Ctl* ctl, hipStream_t s) {
+    k_ctl_begin_range<<<1, 1, 0, s>>>(ctl);
+    TIP_HIP_TRY(hipGetLastError());
+    if (n_live <= 0) return;
+    k_range_start<<<grid1(n_live, 4096), kT, 0, s>>>(pb.live[cur_live], n_live, pb.live[1 - cur_live], pb.state,
+                                                      pb.supp, pb.init, pb.wprox, ctl);
+    TIP_HIP_TRY(hipGetLastError());
+}
+
+void launch_select(PeelBuffers& pb, int cur_live, int32_t n_live, uint64_t max_supp, int64_t tgt, Ctl* ctl,
+                   hipStream_t s) {
+    k_ctl_select_init<<<1, 1, 0, s>>>(ctl, (long long)tgt);
+    TIP_HIP_TRY(hipGetLastError());
+    const int bits = bits_for(max_supp);
+    const int passes = (bits + 7) / 8;
+    for (int p = passes - 1; p >= 0; --p) {
+        const int shift = 8 * p;
+        k_select_hist<<<grid1(n_live, 2048), kT, 0, s>>>(pb.live[cur_live], n_live, pb.supp, pb.wprox, shift, ctl,
+                                                          pb.sel_hist);
+        TIP_HIP_TRY(hipGetLastError());
+        k_select_pick<<<1, 256, 0, s>>>(shift, ctl, pb.sel_hist);
+        TIP_HIP_TRY(hipGetLastError());
+    }
+}
+
+void launch_frontier_init(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi, int32_t label, int cur_front,
+                          Ctl* ctl, hipStream_t s) {
+    if (n_live <= 0) return;
+    k_frontier_init<<<grid1(n_live, 4096), kT, 0, s>>>(pb.live[cur_live], n_live, pb.supp, pb.state, pb.wprox,
+                                                        pb.bin, (long long)hi, label,
+                                                        fronts_of(pb, cur_front, ctl->n_front), ctl);
+    TIP_HIP_TRY(hipGetLastError());
+}
+
+void launch_peel_round(const DevGraph& g, PeelBuffers& pb, int cur_front, const int32_t* n_cur, int64_t hi,
+                       Ctl* ctl, const SpillArena& spill, int big_grid, hipStream_t s, hipEvent_t* ev_big) {
+    const int nxt = 1 - cur_front;
+    CdApply ap{pb.supp, pb.state, pb.bin, (long long)hi, fronts_of(pb, nxt, ctl->n_next)};
+    if (n_cur[kBinWave] > 0) {
+        const int nw = kSmallThreads / kWave;
+        const int64_t blocks = std::min<int64_t>((n_cur[kBinWave] + nw - 1) / nw, 8192);
+        k_peel_wave<<<(unsigned)blocks, kSmallThreads, 0, s>>>(g, pb.front[cur_front][kBinWave],
+                                                               &ctl->n_front[kBinWave], ap, ctl);
+        TIP_HIP_TRY(hipGetLastError());
+    }
+    const bool big = n_cur[kBinBitmap] > 0 || n_cur[kBinDense8] > 0 || n_cur[kBinDense16] > 0;
+    if (big && ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[0], s));
+    if (n_cur[kBinBitmap] > 0) {
+        const int grid = (int)std::min<int64_t>(n_cur[kBinBitmap], std::min(big_grid, spill.slots));
+        k_peel_bitmap<<<grid, kBigThreads, 0, s>>>(g, pb.tb, pb.tk, pb.ntt, pb.front[cur_front][kBinBitmap],
+                                                   &ctl->n_front[kBinBitmap], ap, spill, ctl);
+        TIP_HIP_TRY(hipGetLastError());
+    }
+    for (int cb = 1; cb <= 2; ++cb) {
+        const int bin = cb == 1 ? kBinDense8 : kBinDense16;
+        if (n_cur[bin] <= 0) continue;
+        static int cus = 0;
+        if (!cus) {
+            int dev = 0;
+            TIP_HIP_TRY(hipGetDevice(&dev));
+            TIP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        }
+        const int64_t slots = (int64_t)cus * dense_occupancy(pb.tk, cb);
+        const int grid = (int)std::min<int64_t>((int64_t)n_cur[bin] * pb.ntt, slots);
+        const size_t lds = dense_lds_bytes(pb.tk, cb);
+        if (cb == 1)
+            k_peel_dense<1><<<grid, kDenseThreads, lds, s>>>(g, pb.tb, pb.tk, pb.ntt, pb.front[cur_front][bin],
+                                                              &ctl->n_front[bin], ap, ctl);
+        else
+            k_peel_dense<2><<<grid, kDenseThreads, lds, s>>>(g, pb.tb, pb.tk, pb.ntt, pb.front[cur_front][bin],
+                                                              &ctl->n_front[bin], ap, ctl);
+        TIP_HIP_TRY(hipGetLastError());
+    }
+    if (big && ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[1], s));
+}
+
+void launch_round_end(PeelBuffers& pb, int next_front, int32_t max_items, int32_t label, Ctl* ctl,
+                      hipStream_t s) {
+    if (max_items > 0) {
+        k_round_end<<<grid1(max_items, 4096), kT, 0, s>>>(fronts_of(pb, next_front, ctl->n_next), pb.state,
+                                                           pb.wprox, label, ctl);
+        TIP_HIP_TRY(hipGetLastError());
+    }
+    k_ctl_swap_front<<<1, 1, 0, s>>>(ctl);
+    TIP_HIP_TRY(hipGetLastError());
+}
+
+void launch_assign_live(PeelBuffers& pb, int cur_live, int32_t n_live, int32_t label, hipStream_t s) {
+    if (n_live <= 0) return;
+    k_assign_live<<<grid1(n_live), kT, 0, s>>>(pb.live[cur_live], n_live, pb.state, label);
+    TIP_HIP_TRY(hipGetLastError());
+}
+
+}  // namespace tip

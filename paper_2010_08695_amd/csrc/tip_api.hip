@@ -47,7 +47,7 @@ int resident_workgroups() {
     if (dev != cached_dev) {
         int cus = 0;
         TIP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        cached = std::max(1, cus) * big_kernel_occupancy();
+        cached = std::max(1, cus) * std::min(count_occupancy(), std::min(peel_occupancy(), fd_occupancy()));
         cached_dev = dev;
     }
     return cached;
@@ -71,8 +71,12 @@ void plan(Arena& ar, int32_t n_a, int32_t n_b, int64_t m, int32_t P, int slots, 
     w.pb.init = ar.take<int64_t>(na);
     for (int i = 0; i < 2; ++i) w.pb.live[i] = ar.take<int32_t>(na);
     for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) w.pb.front[i][j] = ar.take<int32_t>(na);
+        for (int j = 0; j < kBins; ++j) w.pb.front[i][j] = ar.take<int32_t>(na);
     w.pb.sel_hist = ar.take<int64_t>(256);
+    w.pb.bin = ar.take<uint8_t>(na);
+    w.pb.tk = dense_tile_keys(na);
+    w.pb.ntt = (int32_t)((na + w.pb.tk - 1) / w.pb.tk);
+    w.pb.tb = ar.take<int32_t>(nb * (w.pb.ntt + 1));
     w.fb.fd_vert = ar.take<int32_t>(na);
     w.fb.fd_pos = ar.take<int32_t>(na);
     w.fb.sub_off = ar.take<int64_t>(S + 1);
@@ -214,9 +218,18 @@ __global__ void k_scatter_i32(const int32_t* by_rank, const int32_t* orig, int32
 
 // Ingest + count (+ CD + FD when decomposing).  Returns TIP_OK or an error
 // status (EINVAL for out-of-range ids found on the device).
+// Wedge count above which a vertex is peeled by the dense (vertex, tile)
+// kernel: its 2-hop neighbourhood then covers a large share of the key space.
+int64_t default_dense_threshold(int32_t n_a) { return std::max<int64_t>(4096, (int64_t)n_a / 16); }
+
 tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int32_t n_b, int64_t m, bool a_is_u,
-               int32_t P, bool decompose, RunOut& out, tip_stats* st, hipStream_t s) {
+               int32_t P, int32_t flags, int64_t w_dense, bool decompose, RunOut& out, tip_stats* st,
+               hipStream_t s) {
     Events ev;
+    Events kev;  // [0], [1]: around one workgroup peeling launch
+    const bool time_kernels = (flags & TIP_FLAG_TIME_KERNELS) != 0;
+    double peel_ms = 0.0;
+    int64_t peel_launches = 0;
     TIP_HIP_TRY(hipEventRecord(ev.e[0], s));
     TIP_HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s));
     if (!ingest(d_a, d_b, n_a, n_b, m, a_is_u, w.ib, w.g, w.aux, s)) {
@@ -245,7 +258,7 @@ tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int
     } else {
         // Coarse-grained decomposition (Alg. 3).
         PeelBuffers& pb = w.pb;
-        launch_wproxy(g, w.aux.deg_b, pb.wprox, s);
+        launch_peel_setup(g, w.aux.deg_b, pb, w_dense > 0 ? w_dense : default_dense_threshold(n_a), s);
         fill_i32(pb.state, kLive, n_a, s);
         iota_i32(pb.live[0], n_a, s);
         int cur_live = 0;
@@ -279,10 +292,21 @@ tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int
             launch_frontier_init(pb, cur_live, n_live, hi, label, cur_front, w.ctl, s);
             for (;;) {
                 const Ctl& c2 = read_ctl(w, s);
-                const int32_t ns = c2.n_front[0], nb = c2.n_front[1];
-                if (ns + nb == 0) break;
-                launch_peel_round(g, pb, cur_front, ns, nb, hi, w.ctl, w.spill, big_grid, s);
-                launch_round_end(pb, 1 - cur_front, n_live, 0, label, w.ctl, s);
+                int32_t n_cur[kBins];
+                int64_t n_tot = 0;
+                for (int b = 0; b < kBins; ++b) n_tot += (n_cur[b] = c2.n_front[b]);
+                if (n_tot == 0) break;
+                const int32_t nb = n_cur[kBinBitmap] + n_cur[kBinDense8] + n_cur[kBinDense16];
+                launch_peel_round(g, pb, cur_front, n_cur, hi, w.ctl, w.spill, big_grid, s,
+                                  time_kernels && nb > 0 ? kev.e : nullptr);
+                launch_round_end(pb, 1 - cur_front, n_live, label, w.ctl, s);
+                if (nb > 0) {
+                    ++peel_launches;
+                    if (time_kernels) {
+                        TIP_HIP_TRY(hipEventSynchronize(kev.e[1]));
+                        peel_ms += kev.ms(0, 1);
+                    }
+                }
                 cur_front ^= 1;
                 ++rounds;
             }
@@ -333,6 +357,11 @@ tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int
         st->spills = (int64_t)cf.spills;
         st->skipped = (int64_t)cf.skipped;
         st->m_unique = g.m;
+        st->peel_launches = peel_launches;
+        st->peel_wedges = (int64_t)cf.big_wedges;
+        st->peel_edges = (int64_t)cf.big_edges;
+        st->peel_pairs = (int64_t)cf.big_pairs;
+        st->peel_ms = peel_ms;
         st->t_ingest_ms = ev.ms(0, 1);
         st->t_count_ms = ev.ms(1, 2);
         st->t_cd_ms = ev.ms(2, 3);
@@ -379,9 +408,10 @@ void check_edges(const tip_edges* g) {
 int32_t check_opts(const tip_opts* opt) {
     if (!opt) return kDefaultP;
     if (opt->P < 0 || opt->P > kMaxP) throw InvalidArg("P must be in [0, 65535]");
-    if (opt->flags != 0) throw InvalidArg("flags must be 0");
-    for (int i = 0; i < 8; ++i)
-        if (opt->tune[i] != 0) throw InvalidArg("tune must be all 0");
+    if (opt->flags & ~TIP_FLAG_TIME_KERNELS) throw InvalidArg("unknown flag bits");
+    if (opt->tune[0] < 0) throw InvalidArg("tune[0] must be >= 0");
+    for (int i = 1; i < 8; ++i)
+        if (opt->tune[i] != 0) throw InvalidArg("tune[1..7] must be 0");
     return opt->P == 0 ? kDefaultP : opt->P;
 }
 
@@ -409,8 +439,9 @@ tip_status guard(F&& f) {
 }
 
 // Host-pointer decomposition of one graph (side already validated).
-tip_status decompose_host(const tip_edges* g, int32_t side, int64_t* theta, int32_t P, tip_stats* st,
-                          int32_t* subset, int64_t* init, int64_t* bounds, int32_t* n_subsets) {
+tip_status decompose_host(const tip_edges* g, int32_t side, int64_t* theta, int32_t P, int32_t flags,
+                          int64_t w_dense, tip_stats* st, int32_t* subset, int64_t* init, int64_t* bounds,
+                          int32_t* n_subsets) {
     const bool a_is_u = side == TIP_SIDE_U;
     const int32_t n_a = a_is_u ? g->n_u : g->n_v;
     const int32_t n_b = a_is_u ? g->n_v : g->n_u;
@@ -445,7 +476,7 @@ tip_status decompose_host(const tip_edges* g, int32_t side, int64_t* theta, int3
     out.bounds = &bvec;
     int32_t ns = 0;
     out.n_subsets = &ns;
-    const tip_status rc = run(w, d_a, d_b, n_a, n_b, m, a_is_u, P, true, out, st, s);
+    const tip_status rc = run(w, d_a, d_b, n_a, n_b, m, a_is_u, P, flags, w_dense, true, out, st, s);
     if (rc != TIP_OK) return rc;
     if (n_a > 0) {
         TIP_HIP_TRY(hipMemcpyAsync(theta, d_theta, sizeof(int64_t) * n_a, hipMemcpyDeviceToHost, s));
@@ -507,7 +538,7 @@ tip_status tip_count_butterflies(const tip_edges* g, int64_t* bfly_u, int64_t* b
         RunOut out;
         out.bfly_a = d_bu;
         out.bfly_b = d_bv;
-        const tip_status rc = run(w, d_a, d_b, n_a, n_b, m, true, 1, false, out, nullptr, s);
+        const tip_status rc = run(w, d_a, d_b, n_a, n_b, m, true, 1, 0, 0, false, out, nullptr, s);
         if (rc != TIP_OK) return rc;
         if (total) {
             k_sum_i64<<<1, 1024, 0, s>>>(w.cb.bfly_a, n_a, w.total);
@@ -533,7 +564,8 @@ tip_status tip_decompose_ex(const tip_edges* g, int32_t side, int64_t* theta, co
         const int32_t P = check_opts(opt);
         const int32_t n_side = side == TIP_SIDE_U ? g->n_u : g->n_v;
         if (n_side > 0 && !theta) throw InvalidArg("theta is NULL");
-        return decompose_host(g, side, theta, P, st, subset, init_support, bounds, n_subsets);
+        return decompose_host(g, side, theta, P, opt ? opt->flags : 0, opt ? opt->tune[0] : 0, st, subset,
+                              init_support, bounds, n_subsets);
     });
 }
 
@@ -554,8 +586,9 @@ tip_status tip_decompose_batch(int32_t n, const tip_edges* gs, const int32_t* si
             if (n_side > 0 && !thetas[k]) throw InvalidArg("theta is NULL");
         }
         for (int32_t k = 0; k < n; ++k) {
-            const tip_status rc = decompose_host(&gs[k], sides[k], thetas[k], P, st ? &st[k] : nullptr, nullptr,
-                                                 nullptr, nullptr, nullptr);
+            const tip_status rc = decompose_host(&gs[k], sides[k], thetas[k], P, opt ? opt->flags : 0,
+                                                 opt ? opt->tune[0] : 0, st ? &st[k] : nullptr, nullptr, nullptr,
+                                                 nullptr, nullptr);
             if (rc != TIP_OK) return rc;
         }
         return TIP_OK;
@@ -601,7 +634,8 @@ tip_status tip_decompose_async(const int32_t* d_eu, const int32_t* d_ev, int32_t
         TIP_HIP_TRY(hipMemsetAsync(w.spill.dense, 0, sizeof(int32_t) * w.spill.stride * w.spill.slots, s));
         RunOut out;
         out.theta = d_theta;
-        return run(w, a_is_u ? d_eu : d_ev, a_is_u ? d_ev : d_eu, n_a, n_b, m, a_is_u, P, true, out, st, s);
+        return run(w, a_is_u ? d_eu : d_ev, a_is_u ? d_ev : d_eu, n_a, n_b, m, a_is_u, P, opt ? opt->flags : 0,
+                   opt ? opt->tune[0] : 0, true, out, st, s);
     });
 }
 

@@ -24,6 +24,25 @@ constexpr int kSmallThreads = 256;         // threads of the wave-per-vertex ker
 constexpr int kSmallSlots = 1024;          // per-wave hash slots (8 KiB)
 constexpr int64_t kSmallMaxWedges = 448;   // wave path handles <= this many wedges
 
+// Coarse-grained update kernels (see peel.hip).
+constexpr int kBmTile = 1 << 19;           // keys per bitmap-path tile (64 KiB of bits)
+constexpr int kBmRep = 8192;               // bitmap-path repeat slots (64 KiB)
+constexpr int kUnit = 128;                 // consecutive list entries per traversal unit
+constexpr int kDenseThreads = 256;         // threads of the dense (vertex, key tile) kernel
+constexpr int kMinTileKeys = 4096;         // key-tile size range of the dense kernel; the
+constexpr int kMaxTileKeys = 65536;        //   per-list tile-bound table uses the same tiles
+constexpr int64_t kDense8MaxDegree = 255;      // 8-bit counters: c(u, w) <= d_u
+constexpr int64_t kDense16MaxDegree = 65535;   // 16-bit counters
+constexpr int kBins = 4;
+constexpr int kBinWave = 0, kBinBitmap = 1, kBinDense8 = 2, kBinDense16 = 3;
+
+// Key-tile size of the dense kernel for a side of n keys: about 64 tiles.
+inline int32_t dense_tile_keys(int64_t n) {
+    int64_t t = kMinTileKeys;
+    while (t < kMaxTileKeys && t * 64 < n) t <<= 1;
+    return (int32_t)t;
+}
+
 constexpr int32_t kLive = -1;              // subset id of a vertex not yet assigned
 
 // 64-bit hash-table slot: (key + 1) << 32 | count; 0 = empty.

@@ -9,12 +9,12 @@ namespace tip {
 struct Ctl {
     int32_t n_live;         // live-list length (after the last compaction)
     int32_t n_live_next;    // compaction output counter
-    int32_t n_front[2];     // current frontier sizes [wave bin, workgroup bin]
-    int32_t n_next[2];      // next frontier sizes
+    int32_t n_front[kBins]; // current frontier sizes per update kernel
+    int32_t n_next[kBins];  // next frontier sizes
     int32_t n_items[2];     // counting work items [wave bin, workgroup bin]
     int32_t fd_head;        // fine-grained task queue head
     int32_t sel_found;      // 0 once no support value reaches the target
-    int32_t pad[6];
+    int32_t pad[4];
     unsigned long long max_supp;
     long long w_rem;        // wedge proxy summed over live vertices
     long long w_range;      // wedge proxy summed over the current subset
@@ -29,6 +29,9 @@ struct Ctl {
     unsigned long long spills;
     unsigned long long skipped;
     unsigned long long fd_levels;
+    unsigned long long big_wedges;   // workgroup peeling kernel only
+    unsigned long long big_edges;
+    unsigned long long big_pairs;
 };
 
 struct CountBuffers {
@@ -45,8 +48,12 @@ struct PeelBuffers {
     int32_t* state;      // [n_a] kLive or subset id
     int64_t* init;       // [n_a] support at the start of u's range
     int32_t* live[2];    // [n_a] live lists (ping-pong)
-    int32_t* front[2][2];  // [buffer][bin] frontier lists
+    int32_t* front[2][kBins];  // [buffer][bin] frontier lists
     int64_t* sel_hist;   // [256]
+    uint8_t* bin;        // [n_a] update kernel of each vertex
+    int32_t* tb;         // [n_b * (ntt + 1)] tile bounds of every list of the other side
+    int32_t tk;          // keys per tile (dense_tile_keys(n_a))
+    int32_t ntt;         // number of tiles of side A
 };
 
 struct FdBuffers {
@@ -70,16 +77,18 @@ struct FdBuffers {
 void launch_count(const DevGraph& g, CountBuffers& cb, Ctl* ctl, const SpillArena& spill, int big_grid,
                   hipStream_t s);
 // CD
-void launch_wproxy(const DevGraph& g, const int32_t* deg_b_rank, int64_t* wprox, hipStream_t s);
+void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers& pb, int64_t w_dense,
+                       hipStream_t s);
 void launch_range_start(PeelBuffers& pb, int cur_live, int32_t n_live, Ctl* ctl, hipStream_t s);
 void launch_select(PeelBuffers& pb, int cur_live, int32_t n_live, uint64_t max_supp, int64_t tgt, Ctl* ctl,
                    hipStream_t s);
 void launch_frontier_init(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi, int32_t label, int cur_front,
                           Ctl* ctl, hipStream_t s);
-void launch_peel_round(const DevGraph& g, PeelBuffers& pb, int cur_front, int32_t n_small, int32_t n_big,
-                       int64_t hi, Ctl* ctl, const SpillArena& spill, int big_grid, hipStream_t s);
-void launch_round_end(PeelBuffers& pb, int next_front, int32_t n_small, int32_t n_big, int32_t label, Ctl* ctl,
-                      hipStream_t s);
+// n_cur: host copy of the current frontier sizes; ev_big: optional pair of
+// events recorded around the workgroup update kernels.
+void launch_peel_round(const DevGraph& g, PeelBuffers& pb, int cur_front, const int32_t* n_cur, int64_t hi,
+                       Ctl* ctl, const SpillArena& spill, int big_grid, hipStream_t s, hipEvent_t* ev_big);
+void launch_round_end(PeelBuffers& pb, int next_front, int32_t max_items, int32_t label, Ctl* ctl, hipStream_t s);
 void launch_assign_live(PeelBuffers& pb, int cur_live, int32_t n_live, int32_t label, hipStream_t s);
 // FD
 void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl, const SpillArena& spill,
@@ -88,6 +97,9 @@ void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl
 // output
 void launch_scatter_i64(const int64_t* by_rank, const int32_t* orig, int32_t n, int64_t* out, hipStream_t s);
 
-int big_kernel_occupancy();  // resident workgroups per CU of the workgroup kernels
+// resident workgroups per CU of the workgroup kernels of each unit
+int count_occupancy();
+int peel_occupancy();
+int fd_occupancy();
 
 }  // namespace tip

@@ -1,0 +1,165 @@
+"""Helpers for rocprofv3 measurements of libtip kernels.
+
+    # plain copy of a known size, the calibration for FETCH_SIZE / WRITE_SIZE
+    python -m paper_2010_08695_amd.profiling calib [--mib 1024]
+    # short text summary of a --kernel-trace --stats run
+    python -m paper_2010_08695_amd.profiling stats <dir> --cmd "<command>" --out profiles/x.txt
+    # per-launch HBM traffic of one kernel from two counter runs + calibration
+    python -m paper_2010_08695_amd.profiling traffic --fetch <dir> --write <dir> \\
+        --calib-fetch <dir> --calib-write <dir> --kernel k_peel_big --workload cl-10m --cmd "..."
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = ["paper_2010_08695_amd/csrc/peel.hip", "paper_2010_08695_amd/csrc/agg.h",
+                  "paper_2010_08695_amd/csrc/tip_common.h"]
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def find_csv(d: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[-1]
+
+
+def short_name(name: str) -> str:
+    # demangled names look like "tip::(anonymous namespace)::k_peel_big(...)"
+    base = name.replace("(anonymous namespace)", "anon").split("(")[0]
+    return base.split("::")[-1] if "::" in base else base
+
+
+def kernel_stats(d: str) -> list[dict]:
+    rows = []
+    with open(find_csv(d, "kernel_stats.csv")) as f:
+        for r in csv.DictReader(f):
+            rows.append({"name": short_name(r["Name"]), "calls": int(r["Calls"]),
+                         "total_ns": float(r["TotalDurationNs"]), "avg_ns": float(r["AverageNs"]),
+                         "pct": float(r["Percentage"]), "min_ns": float(r["MinNs"]),
+                         "max_ns": float(r["MaxNs"])})
+    rows.sort(key=lambda r: -r["total_ns"])
+    return rows
+
+
+def counter_per_dispatch(d: str, counter: str) -> dict[str, list[float]]:
+    """{kernel short name: [counter value per dispatch]} (values summed over
+    the per-XCD/per-instance rows of one dispatch)."""
+    per: dict[tuple, float] = {}
+    names: dict[tuple, str] = {}
+    with open(find_csv(d, "counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") != counter:
+                continue
+            key = (r.get("Dispatch_Id") or r.get("Correlation_Id"), r.get("Kernel_Name"))
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+            names[key] = short_name(r.get("Kernel_Name", ""))
+    out: dict[str, list[float]] = {}
+    for k, v in per.items():
+        out.setdefault(names[k], []).append(v)
+    return out
+
+
+def cmd_calib(args) -> int:
+    import torch
+    n = args.mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"copied {args.mib} MiB", flush=True)
+    return 0
+
+
+def cmd_stats(args) -> int:
+    rows = kernel_stats(args.dir)
+    lines = [f"# rocprofv3 kernel statistics", f"command: {args.cmd}", "",
+             f"{'kernel':<28}{'calls':>8}{'total ms':>12}{'avg us':>12}{'min us':>10}{'max us':>10}{'%':>7}"]
+    for r in rows[: args.top]:
+        lines.append(f"{r['name']:<28}{r['calls']:>8}{r['total_ns'] / 1e6:>12.3f}{r['avg_ns'] / 1e3:>12.2f}"
+                     f"{r['min_ns'] / 1e3:>10.2f}{r['max_ns'] / 1e3:>10.2f}{r['pct']:>7.2f}")
+    text = "\n".join(lines) + "\n"
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text)
+    return 0
+
+
+def cmd_traffic(args) -> int:
+    fetch = counter_per_dispatch(args.fetch, "FETCH_SIZE")
+    write = counter_per_dispatch(args.write, "WRITE_SIZE")
+    cf = counter_per_dispatch(args.calib_fetch, "FETCH_SIZE")
+    cw = counter_per_dispatch(args.calib_write, "WRITE_SIZE")
+    copy_bytes = args.calib_mib * (1 << 20)
+    # the calibration copy is the dispatch with the largest reading
+    cf_kib = max(v for vs in cf.values() for v in vs)
+    cw_kib = max(v for vs in cw.values() for v in vs)
+    f_scale = copy_bytes / (cf_kib * 1024.0)
+    w_scale = copy_bytes / (cw_kib * 1024.0)
+    kf = fetch.get(args.kernel, [])
+    kw = write.get(args.kernel, [])
+    if not kf or not kw:
+        raise SystemExit(f"kernel {args.kernel} not found in the counter runs")
+    mean_f = sum(kf) / len(kf)
+    mean_w = sum(kw) / len(kw)
+    per_launch = mean_f * 1024.0 * f_scale + mean_w * 1024.0 * w_scale
+    rec = {"kernel": args.kernel, "workload": args.workload, "kernel_sha": kernel_source_sha(),
+           "dispatches": len(kf), "fetch_kib_per_dispatch": mean_f, "write_kib_per_dispatch": mean_w,
+           "fetch_scale": f_scale, "write_scale": w_scale, "bytes_per_launch": per_launch}
+    text = (json.dumps(rec) + "\n---\n"
+            f"HBM traffic of {args.kernel} on {args.workload} (rocprofv3 --pmc, one counter per run)\n"
+            f"command: {args.cmd}\n"
+            f"calibration: plain copy of {args.calib_mib} MiB read FETCH_SIZE {cf_kib:.0f} KiB and WRITE_SIZE "
+            f"{cw_kib:.0f} KiB -> scale {f_scale:.4f} / {w_scale:.4f}\n"
+            f"{args.kernel}: {len(kf)} dispatches, mean FETCH_SIZE {mean_f:.1f} KiB, mean WRITE_SIZE "
+            f"{mean_w:.1f} KiB -> {per_launch / 1e6:.3f} MB per launch after scaling\n")
+    out = args.out or os.path.join(ROOT, "profiles", f"{args.kernel}.{args.workload}.traffic.txt")
+    with open(out, "w") as f:
+        f.write(text)
+    print(text)
+    return 0
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd_name", required=True)
+    p = sub.add_parser("calib")
+    p.add_argument("--mib", type=int, default=1024)
+    p.set_defaults(fn=cmd_calib)
+    p = sub.add_parser("stats")
+    p.add_argument("dir")
+    p.add_argument("--cmd", default="")
+    p.add_argument("--out", default="")
+    p.add_argument("--top", type=int, default=25)
+    p.set_defaults(fn=cmd_stats)
+    p = sub.add_parser("traffic")
+    for k in ("fetch", "write", "calib_fetch", "calib_write"):
+        p.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    p.add_argument("--calib-mib", type=int, default=1024)
+    p.add_argument("--kernel", default="k_peel_big")
+    p.add_argument("--workload", default="cl-10m")
+    p.add_argument("--cmd", default="")
+    p.add_argument("--out", default="")
+    p.set_defaults(fn=cmd_traffic)
+    args = ap.parse_args(argv)
+    return args.fn(args)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

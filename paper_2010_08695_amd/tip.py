@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtip.so")
 
 TIP_OK, TIP_EINVAL, TIP_ENOMEM, TIP_EDEVICE, TIP_EOVERFLOW, TIP_EBUSY = 0, -1, -2, -3, -4, -5
+TIP_FLAG_TIME_KERNELS = 1
 SIDE_U, SIDE_V = 0, 1
 STATUS_NAMES = {0: "TIP_OK", -1: "TIP_EINVAL", -2: "TIP_ENOMEM", -3: "TIP_EDEVICE",
                 -4: "TIP_EOVERFLOW", -5: "TIP_EBUSY"}
@@ -47,9 +48,10 @@ class Opts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("wedges_count", "wedges_cd", "wedges_fd", "pair_updates", "rounds", "subsets",
-                 "fd_levels", "spills", "skipped", "m_unique")] + \
+                 "fd_levels", "spills", "skipped", "m_unique",
+                 "peel_launches", "peel_wedges", "peel_edges", "peel_pairs")] + \
                [(n, ctypes.c_double) for n in
-                ("t_ingest_ms", "t_count_ms", "t_cd_ms", "t_fd_ms", "t_total_ms")]
+                ("peel_ms", "t_ingest_ms", "t_count_ms", "t_cd_ms", "t_fd_ms", "t_total_ms")]
 
     def to_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -126,9 +128,11 @@ def _edges(g) -> tuple[Edges, tuple]:
     return e, (eu, ev)
 
 
-def _opts(P: int = 0) -> Opts:
+def _opts(P: int = 0, flags: int = 0, dense_threshold: int = 0) -> Opts:
     o = Opts()
     o.P = int(P)
+    o.flags = int(flags)
+    o.tune[0] = int(dense_threshold)
     return o
 
 
@@ -143,14 +147,16 @@ def count_butterflies(g):
     return bu, bv, int(tot[0])
 
 
-def decompose(g, side: int = SIDE_U, P: int = 0, with_stats: bool = False):
-    """Tip numbers int64[n_side] of ``side``; with_stats adds a stats dict."""
+def decompose(g, side: int = SIDE_U, P: int = 0, with_stats: bool = False, flags: int = 0,
+              dense_threshold: int = 0):
+    """Tip numbers int64[n_side] of ``side``; with_stats adds a stats dict.
+    dense_threshold: tip_opts.tune[0] (0 = library default)."""
     lib = load()
     e, keep = _edges(g)
     n = g.n_u if side == SIDE_U else g.n_v
     theta = np.zeros(max(n, 0), np.int64)
     st = Stats()
-    o = _opts(P)
+    o = _opts(P, flags, dense_threshold)
     _check(lib, lib.tip_decompose(ctypes.byref(e), int(side), _ptr(theta), ctypes.byref(o), ctypes.byref(st)))
     return (theta, st.to_dict()) if with_stats else theta
 
@@ -207,7 +213,7 @@ def workspace_size(n_u: int, n_v: int, m: int, side: int = SIDE_U, P: int = 0) -
 
 
 def decompose_async(d_eu, d_ev, n_u: int, n_v: int, side: int, d_theta, workspace, stream=None,
-                    P: int = 0) -> dict:
+                    P: int = 0, flags: int = 0, dense_threshold: int = 0) -> dict:
     """Device-resident decomposition.  d_eu/d_ev/d_theta/workspace are torch
     CUDA(HIP) tensors (only their device pointers are passed); stream is a
     torch.cuda.Stream or None for the current stream.  Returns the stats."""
@@ -222,7 +228,7 @@ def decompose_async(d_eu, d_ev, n_u: int, n_v: int, side: int, d_theta, workspac
         import torch
         s = torch.cuda.current_stream().cuda_stream
     st = Stats()
-    o = _opts(P)
+    o = _opts(P, flags, dense_threshold)
     _check(lib, lib.tip_decompose_async(
         ctypes.c_void_p(d_eu.data_ptr()), ctypes.c_void_p(d_ev.data_ptr()), int(n_u), int(n_v), m, int(side),
         ctypes.c_void_p(d_theta.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
