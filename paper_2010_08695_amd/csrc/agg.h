@@ -227,9 +227,17 @@ struct WaveLds {
     int64_t acc[kWave];
 };
 
-__device__ inline void wave_insert(WaveLds& W, uint32_t k) {
+// Slots used for a vertex with `wedges` wedges: a power of two >= 2 * wedges
+// (at least one per lane), so the table stays at most half full.
+__device__ inline uint32_t wave_slots(int64_t wedges) {
+    uint32_t s = kWave;
+    while (s < kSmallSlots && (int64_t)s < 2 * wedges) s <<= 1;
+    return s;
+}
+
+__device__ inline void wave_insert(WaveLds& W, uint32_t k, uint32_t mask = kSmallSlots - 1) {
     const unsigned long long tag = (unsigned long long)(k + 1) << 32;
-    uint32_t h = hash32(k) & (kSmallSlots - 1);
+    uint32_t h = hash32(k) & mask;
 #pragma unroll 1
     for (;;) {
         unsigned long long* slot = &W.tab[h];
@@ -243,19 +251,19 @@ __device__ inline void wave_insert(WaveLds& W, uint32_t k) {
             atomicAdd(slot, 1ull);
             return;
         }
-        h = (h + 1) & (kSmallSlots - 1);
+        h = (h + 1) & mask;
     }
 }
 
-__device__ inline int32_t wave_lookup(const WaveLds& W, uint32_t k) {
+__device__ inline int32_t wave_lookup(const WaveLds& W, uint32_t k, uint32_t mask = kSmallSlots - 1) {
     const unsigned long long tag = (unsigned long long)(k + 1) << 32;
-    uint32_t h = hash32(k) & (kSmallSlots - 1);
+    uint32_t h = hash32(k) & mask;
 #pragma unroll 1
-    for (int p = 0; p < kSmallSlots; ++p) {
+    for (uint32_t p = 0; p <= mask; ++p) {
         const unsigned long long cur = W.tab[h];
         if (cur == 0) return 0;
         if ((cur & 0xffffffff00000000ull) == tag) return (int32_t)(cur & 0xffffffffull);
-        h = (h + 1) & (kSmallSlots - 1);
+        h = (h + 1) & mask;
     }
     return 0;
 }

@@ -59,7 +59,8 @@ __global__ void k_count_bins(const int64_t* __restrict__ work, int64_t n, int32_
 }
 
 __global__ void __launch_bounds__(kSmallThreads)
-k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64_t* bfly_a, int64_t* bfly_b) {
+k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, const int64_t* __restrict__ work,
+              int64_t* bfly_a, int64_t* bfly_b) {
     __shared__ WaveLds WL[kSmallThreads / kWave];
     const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     WaveLds& W = WL[wid];
@@ -73,6 +74,8 @@ k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int
         const int32_t x = side_b ? item - g.n_a : item;
         const SideView sv = side_view(g, side_b, bfly_a, bfly_b);
         const int64_t e0 = sv.own_off[x], d = sv.own_off[x + 1] - e0;
+        const uint32_t slots = wave_slots(work[item]);
+        const uint32_t mask = slots - 1;
         // pass 1: wedge counts c(x, z)
         for (int64_t g0 = 0; g0 < d; g0 += kWave) {
             const int gs = (int)min<int64_t>(kWave, d - g0);
@@ -86,7 +89,7 @@ k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int
             const int64_t tot = wave_scan_lengths(W, len);
             for (int64_t i = lane; i < tot; i += kWave) {
                 const int j = wave_find_slice(W, gs, i);
-                wave_insert(W, (uint32_t)sv.oth_adj[W.sbeg[j] + (i - W.pre[j])]);
+                wave_insert(W, (uint32_t)sv.oth_adj[W.sbeg[j] + (i - W.pre[j])], mask);
             }
             wave_sync();
         }
@@ -105,7 +108,7 @@ k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int
             const int64_t tot = wave_scan_lengths(W, len);
             for (int64_t i = lane; i < tot; i += kWave) {
                 const int j = wave_find_slice(W, gs, i);
-                const int32_t c = wave_lookup(W, (uint32_t)sv.oth_adj[W.sbeg[j] + (i - W.pre[j])]);
+                const int32_t c = wave_lookup(W, (uint32_t)sv.oth_adj[W.sbeg[j] + (i - W.pre[j])], mask);
                 if (c > 1) atomicAdd(reinterpret_cast<unsigned long long*>(&W.acc[j]), (unsigned long long)(c - 1));
             }
             wave_sync();
@@ -114,7 +117,7 @@ k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int
         }
         // pass 3: start and end vertices gain C(c, 2)
         int64_t local = 0;
-        for (int s = lane; s < kSmallSlots; s += kWave) {
+        for (uint32_t s = lane; s < slots; s += kWave) {
             const unsigned long long v = W.tab[s];
             if (v) {
                 const int64_t c = (int64_t)(v & 0xffffffffull);
@@ -255,7 +258,7 @@ void launch_count(const DevGraph& g, CountBuffers& cb, Ctl* ctl, const SpillAren
     TIP_HIP_TRY(hipGetLastError());
     k_count_bins<<<grid1(n_tot, 4096), kT, 0, s>>>(cb.work, n_tot, cb.items_small, cb.items_big, ctl);
     TIP_HIP_TRY(hipGetLastError());
-    k_count_small<<<2048, kSmallThreads, 0, s>>>(g, cb.items_small, ctl, cb.bfly_a, cb.bfly_b);
+    k_count_small<<<2048, kSmallThreads, 0, s>>>(g, cb.items_small, ctl, cb.work, cb.bfly_a, cb.bfly_b);
     TIP_HIP_TRY(hipGetLastError());
     k_count_big<<<big_grid, kBigThreads, 0, s>>>(g, cb.items_big, ctl, cb.bfly_a, cb.bfly_b, spill, ctl);
     TIP_HIP_TRY(hipGetLastError());

@@ -45,7 +45,8 @@ __device__ inline int64_t lower_bound_u64(const uint64_t* __restrict__ a, int64_
 // For every CSR edge (u, v): the run of N_v inside u's own subset, i.e. the
 // edges of the induced subgraph G_i seen from v (Alg. 4 induced subgraph).
 __global__ void k_fd_slices(DevGraph g, const int32_t* __restrict__ state, const uint64_t* __restrict__ pkeys,
-                            int32_t S, int64_t* fd_beg, int32_t* fd_len, int64_t* task_w) {
+                            int32_t S, const int32_t* __restrict__ fd_pos, int64_t* fd_beg, int32_t* fd_len,
+                            int64_t* task_w, int64_t* fd_w) {
     GRID_STRIDE(p, g.m) {
         const int32_t u = g.a_row[p], v = g.a_adj[p];
         const int32_t s = state[u];
@@ -54,7 +55,10 @@ __global__ void k_fd_slices(DevGraph g, const int32_t* __restrict__ state, const
         const int64_t hi = lower_bound_u64(pkeys, lo, g.b_off[v + 1], k0 + 1);
         fd_beg[p] = lo;
         fd_len[p] = (int32_t)(hi - lo);
-        if (hi - lo > 1) atomic_add_i64(&task_w[s], hi - lo - 1);
+        if (hi - lo > 1) {
+            atomic_add_i64(&task_w[s], hi - lo - 1);
+            atomic_add_i64(&fd_w[fd_pos[u]], hi - lo - 1);
+        }
     }
 }
 
@@ -74,8 +78,28 @@ __global__ void k_fd_order(const int64_t* __restrict__ task_w, int32_t S, int32_
 
 __global__ void k_fd_reset_head(Ctl* ctl) { ctl->fd_head = 0; }
 
+// LDS of the fine-grained kernel.  The per-wave hash tables (light peeled
+// vertices) and the bitmap + repeat table (heavy ones) are used in separate
+// phases of a level and share storage; both are all zero between uses.
+struct FdLds {
+    union Shared {
+        struct {
+            uint32_t bm[kFdBits / 32];
+            unsigned long long rep[kFdRep];
+        } big;
+        unsigned long long wtab[kFdThreads / kWave][kFdWaveSlots];
+    } u;
+    int64_t sbeg[kGroup];
+    int64_t pre[kGroup + 1];
+    int64_t wsbeg[kFdThreads / kWave][kWave];
+    int64_t wpre[kFdThreads / kWave][kWave + 1];
+    int64_t red[kFdThreads / kWave];
+    int32_t spill_n;
+    int32_t flag;
+};
+
 template <int NT>
-__device__ inline int32_t block_excl_scan_i32(BigLds& L, int32_t x, int32_t& total) {
+__device__ inline int32_t fd_scan_i32(FdLds& L, int32_t x, int32_t& total) {
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int64_t inc = wave_incl_scan_i64<NT>(x);
     __syncthreads();
@@ -93,21 +117,86 @@ __device__ inline int32_t block_excl_scan_i32(BigLds& L, int32_t x, int32_t& tot
     return (int32_t)(off + inc - x);
 }
 
+template <int NT>
+__device__ inline int64_t fd_min(FdLds& L, int64_t x) {
+    x = wave_min_i64(x);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) L.red[wid] = x;
+    __syncthreads();
+    int64_t s = L.red[0];
+#pragma unroll
+    for (int w = 1; w < NT / kWave; ++w) s = L.red[w] < s ? L.red[w] : s;
+    __syncthreads();
+    return s;
+}
+
+__device__ inline void fd_wave_insert(unsigned long long* tab, uint32_t k, uint32_t mask) {
+    const unsigned long long tag = (unsigned long long)(k + 1) << 32;
+    uint32_t h = hash32(k) & mask;
+#pragma unroll 1
+    for (;;) {
+        unsigned long long* slot = &tab[h];
+        unsigned long long cur = __atomic_load_n(slot, __ATOMIC_RELAXED);
+        if (cur == 0) {
+            const unsigned long long prev = atomicCAS(slot, 0ull, tag | 1ull);
+            if (prev == 0) return;
+            cur = prev;
+        }
+        if ((cur & 0xffffffff00000000ull) == tag) {
+            atomicAdd(slot, 1ull);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+__device__ inline void fd_rep_insert(FdLds& L, const Spill& sp, uint32_t k) {
+    const unsigned long long tag = (unsigned long long)(k + 1) << 32;
+    const uint32_t h = hash32(k) & (kFdRep - 1);
+#pragma unroll 1
+    for (int p = 0; p < kRepProbe; ++p) {
+        unsigned long long* slot = &L.u.big.rep[(h + p) & (kFdRep - 1)];
+        unsigned long long cur = __atomic_load_n(slot, __ATOMIC_RELAXED);
+        if (cur == 0) {
+            const unsigned long long prev = atomicCAS(slot, 0ull, tag | 1ull);
+            if (prev == 0) return;
+            cur = prev;
+        }
+        if ((cur & 0xffffffff00000000ull) == tag) {
+            atomicAdd(slot, 1ull);
+            return;
+        }
+    }
+    if (atomicAdd(&sp.dense[k], 1) == 0) {
+        const int32_t idx = atomicAdd(&L.spill_n, 1);
+        sp.list[idx] = (int32_t)k;
+    }
+}
+
 // One workgroup peels one subset at a time, taking subsets from the
 // workload-sorted queue (dynamic allocation).  Inside a subset it runs
 // bottom-up peeling level by level: the level is max(level, minimum live
 // support), and every live vertex whose support is at most the level is
 // peeled at that level (equal to one-at-a-time peeling, whatever the order).
-__global__ void __launch_bounds__(kBigThreads)
+// The vertices peeled at one level update the survivors concurrently: light
+// ones one per wavefront with a private hash table, heavy ones one at a time
+// with the whole workgroup and a key bitmap.
+__global__ void __launch_bounds__(kFdThreads)
 k_fd_peel(DevGraph g, FdBuffers fb, const int64_t* __restrict__ init, int32_t S, SpillArena spa, Ctl* ctl) {
-    __shared__ BigLds L;
-    constexpr int NT = kBigThreads;
-    const int tid = threadIdx.x;
-    bm_clear<NT>(L, kBmBits);
+    __shared__ FdLds L;
+    constexpr int NT = kFdThreads;
+    constexpr int NW = NT / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    {
+        unsigned long long* all = &L.u.wtab[0][0];
+        for (int i = tid; i < (int)(sizeof(L.u) / 8); i += NT) all[i] = 0;
+    }
     if (tid == 0) L.spill_n = 0;
     __syncthreads();
     const Spill sp{spa.dense + (int64_t)blockIdx.x * spa.stride, spa.list + (int64_t)blockIdx.x * spa.stride};
     unsigned long long wedges = 0, pairs = 0, levels = 0, spills = 0;
+    unsigned long long* tab = L.u.wtab[wid];
     for (;;) {
         if (tid == 0) L.flag = atomicAdd(&ctl->fd_head, 1);
         __syncthreads();
@@ -121,7 +210,9 @@ k_fd_peel(DevGraph g, FdBuffers fb, const int64_t* __restrict__ init, int32_t S,
         int32_t* lc = fb.lst[0] + P0;
         int32_t* ln = fb.lst[1] + P0;
         int32_t* pl = fb.lst[2] + P0;
+        int32_t* ph = fb.lst[3] + P0;
         int64_t* sup = fb.supp_fd + P0;
+        const int64_t* fw = fb.fd_w + P0;
         int32_t* alive = fb.alive + P0;
         const int32_t* vert = fb.fd_vert + P0;
         for (int32_t j = tid; j < n_i; j += NT) {
@@ -130,7 +221,7 @@ k_fd_peel(DevGraph g, FdBuffers fb, const int64_t* __restrict__ init, int32_t S,
             alive[j] = 1;
         }
         __syncthreads();
-        const bool multi = n_i > kBmBits;
+        const bool multi = n_i > kFdBits;
         int32_t n_live = n_i;
         int64_t level = 0;
         while (n_live > 0) {
@@ -139,39 +230,98 @@ k_fd_peel(DevGraph g, FdBuffers fb, const int64_t* __restrict__ init, int32_t S,
                 const int64_t s = sup[lc[j]];
                 mn = s < mn ? s : mn;
             }
-            mn = block_min_i64<NT>(L, mn);
+            mn = fd_min<NT>(L, mn);
             level = mn > level ? mn : level;
-            int32_t n_peel = 0, n_keep = 0;
+            // peel every live vertex at or below the level; light ones (few
+            // wedges inside the subset) and heavy ones go to separate lists,
+            // vertices without support left need no update at all
+            int32_t n_light = 0, n_heavy = 0, n_keep = 0;
             for (int32_t b0 = 0; b0 < n_live; b0 += NT) {
                 const int32_t j = b0 + tid;
                 int32_t x = 0;
-                bool pe = false, ke = false;
+                bool pe = false, ke = false, li = false, he = false;
                 if (j < n_live) {
                     x = lc[j];
-                    pe = sup[x] <= level;
+                    const int64_t sx = sup[x];
+                    pe = sx <= level;
                     ke = !pe;
+                    if (pe && sx > 0) {
+                        he = fw[x] > kFdWaveMax;
+                        li = !he;
+                    }
                 }
-                int32_t tp, tk;
-                const int32_t op = block_excl_scan_i32<NT>(L, pe ? 1 : 0, tp);
-                const int32_t ok = block_excl_scan_i32<NT>(L, ke ? 1 : 0, tk);
+                int32_t tl, th, tk;
+                const int32_t ol = fd_scan_i32<NT>(L, li ? 1 : 0, tl);
+                const int32_t oh = fd_scan_i32<NT>(L, he ? 1 : 0, th);
+                const int32_t ok = fd_scan_i32<NT>(L, ke ? 1 : 0, tk);
                 if (pe) {
-                    pl[n_peel + op] = x;
                     alive[x] = 0;
                     fb.theta[vert[x]] = level;
                 }
+                if (li) pl[n_light + ol] = x;
+                if (he) ph[n_heavy + oh] = x;
                 if (ke) ln[n_keep + ok] = x;
-                n_peel += tp;
+                n_light += tl;
+                n_heavy += th;
                 n_keep += tk;
             }
             __syncthreads();
             levels += tid == 0;
-            for (int32_t q = 0; q < n_peel; ++q) {
+            // light peeled vertices: one per wave
+            for (int32_t q = wid; q < n_light; q += NW) {
                 const int32_t x = pl[q];
-                if (sup[x] == 0) continue;
+                const uint32_t slots = min<uint32_t>(kFdWaveSlots, wave_slots(fw[x]));
+                const uint32_t mask = slots - 1;
                 const int32_t ux = vert[x];
                 const int64_t e0 = g.a_off[ux], d = g.a_off[ux + 1] - e0;
-                for (int32_t klo = 0; klo < n_i; klo += kBmBits) {
-                    const int32_t khi = (int32_t)min<int64_t>(n_i, (int64_t)klo + kBmBits);
+                for (int64_t g0 = 0; g0 < d; g0 += kWave) {
+                    const int gs = (int)min<int64_t>(kWave, d - g0);
+                    int64_t len = 0;
+                    if (lane < gs) {
+                        const int64_t e = e0 + g0 + lane;
+                        L.wsbeg[wid][lane] = fb.fd_beg[e];
+                        len = fb.fd_len[e];
+                    }
+                    const int64_t inc = wave_incl_scan_i64<kWave>(len);
+                    L.wpre[wid][lane] = inc - len;
+                    const int64_t tot = __shfl(inc, kWave - 1, kWave);
+                    if (lane == 0) L.wpre[wid][kWave] = tot;
+                    wave_sync();
+                    for (int64_t i = lane; i < tot; i += kWave) {
+                        int lo = 0, hi = gs;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (L.wpre[wid][mid] <= i) lo = mid;
+                            else hi = mid;
+                        }
+                        const int32_t w = fb.pcsc[L.wsbeg[wid][lo] + (i - L.wpre[wid][lo])];
+                        if (w != x) fd_wave_insert(tab, (uint32_t)w, mask);
+                    }
+                    if (lane == 0) wedges += (unsigned long long)(tot - gs);
+                    wave_sync();
+                }
+                for (uint32_t s = lane; s < slots; s += kWave) {
+                    const unsigned long long v = tab[s];
+                    if (v) {
+                        tab[s] = 0;
+                        const int64_t c = (int64_t)(v & 0xffffffffull);
+                        const int32_t w = (int32_t)((v >> 32) - 1);
+                        if (c >= 2 && alive[w]) {
+                            atomic_add_i64(&sup[w], -choose2(c));
+                            ++pairs;
+                        }
+                    }
+                }
+                wave_sync();
+            }
+            __syncthreads();
+            // heavy peeled vertices: one at a time with the whole workgroup
+            for (int32_t q = 0; q < n_heavy; ++q) {
+                const int32_t x = ph[q];
+                const int32_t ux = vert[x];
+                const int64_t e0 = g.a_off[ux], d = g.a_off[ux + 1] - e0;
+                for (int32_t klo = 0; klo < n_i; klo += kFdBits) {
+                    const int32_t khi = (int32_t)min<int64_t>(n_i, (int64_t)klo + kFdBits);
                     const bool self_in = x >= klo && x < khi;
                     for (int64_t g0 = 0; g0 < d; g0 += kGroup) {
                         const int gs = (int)min<int64_t>(kGroup, d - g0);
@@ -186,17 +336,43 @@ k_fd_peel(DevGraph g, FdBuffers fb, const int64_t* __restrict__ init, int32_t S,
                             L.sbeg[tid] = a;
                             len = b - a;
                         }
-                        const int64_t tot = block_scan_lengths<NT>(L, gs, len);
+                        int32_t tot32;
+                        // exclusive scan of run lengths into L.pre
+                        const int64_t x64 = tid < gs ? len : 0;
+                        const int64_t incl = wave_incl_scan_i64<NT>(x64);
+                        __syncthreads();
+                        if (lane == kWave - 1) L.red[wid] = incl;
+                        __syncthreads();
+                        int64_t off = 0, tot = 0;
+#pragma unroll
+                        for (int w = 0; w < NW; ++w) {
+                            const int64_t v = L.red[w];
+                            off += w < wid ? v : 0;
+                            tot += v;
+                        }
+                        if (tid < gs) L.pre[tid] = off + incl - x64;
+                        if (tid == 0) L.pre[gs] = tot;
+                        __syncthreads();
+                        (void)tot32;
                         for (int64_t i = tid; i < tot; i += NT) {
-                            const int j = find_slice(L, gs, i);
-                            const int32_t w = fb.pcsc[L.sbeg[j] + (i - L.pre[j])];
-                            if (w != x) bm_mark(L, sp, (uint32_t)(w - klo));
+                            int lo = 0, hi = gs;
+                            while (hi - lo > 1) {
+                                const int mid = (lo + hi) >> 1;
+                                if (L.pre[mid] <= i) lo = mid;
+                                else hi = mid;
+                            }
+                            const int32_t w = fb.pcsc[L.sbeg[lo] + (i - L.pre[lo])];
+                            if (w != x) {
+                                const uint32_t k = (uint32_t)(w - klo);
+                                const uint32_t bit = 1u << (k & 31);
+                                if (atomicOr(&L.u.big.bm[k >> 5], bit) & bit) fd_rep_insert(L, sp, k);
+                            }
                         }
                         if (tid == 0) wedges += (unsigned long long)(tot - (self_in ? gs : 0));
                         __syncthreads();
                     }
-                    for (int s = tid; s < kRepSlots; s += NT) {
-                        const unsigned long long v = L.rep[s];
+                    for (int s = tid; s < kFdRep; s += NT) {
+                        const unsigned long long v = L.u.big.rep[s];
                         if (v) {
                             const int32_t w = klo + (int32_t)((v >> 32) - 1);
                             if (alive[w]) {
@@ -217,7 +393,9 @@ k_fd_peel(DevGraph g, FdBuffers fb, const int64_t* __restrict__ init, int32_t S,
                         sp.dense[k] = 0;
                     }
                     __syncthreads();
-                    bm_clear<NT>(L, khi - klo);
+                    const int32_t words = (khi - klo + 31) >> 5;
+                    for (int w = tid; w < words; w += NT) L.u.big.bm[w] = 0;
+                    for (int s = tid; s < kFdRep; s += NT) L.u.big.rep[s] = 0;
                     if (tid == 0) L.spill_n = 0;
                     __syncthreads();
                 }
@@ -232,7 +410,7 @@ k_fd_peel(DevGraph g, FdBuffers fb, const int64_t* __restrict__ init, int32_t S,
     pairs = (unsigned long long)wave_sum_i64((int64_t)pairs);
     levels = (unsigned long long)wave_sum_i64((int64_t)levels);
     spills = (unsigned long long)wave_sum_i64((int64_t)spills);
-    if ((tid & (kWave - 1)) == 0) {
+    if (lane == 0) {
         if (wedges) atomicAdd(&ctl->wedges_fd, wedges);
         if (pairs) atomicAdd(&ctl->pair_updates, pairs);
         if (levels) atomicAdd(&ctl->fd_levels, levels);
@@ -249,7 +427,7 @@ __global__ void k_scatter_i64(const int64_t* __restrict__ by_rank, const int32_t
 
 int fd_occupancy() {
     int n = 0;
-    TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fd_peel, kBigThreads, 0));
+    TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fd_peel, kFdThreads, 0));
     return std::max(1, n);
 }
 
@@ -267,12 +445,14 @@ void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl
     k_fd_positions<<<grid1(n_a), kT, 0, s>>>(fb.fd_vert, n_a, fb.fd_pos);
     TIP_HIP_TRY(hipGetLastError());
     fill_i64(fb.task_w, 0, S, s);
+    fill_i64(fb.fd_w, 0, n_a, s);
     if (g.m > 0) {
         k_fd_csc_keys<<<grid1(g.m), kT, 0, s>>>(g, pb.state, fb.fd_pos, fb.sub_off, S, fb.pkeys, fb.pcsc);
         TIP_HIP_TRY(hipGetLastError());
         radix_sort_pairs(fb.pkeys, fb.pcsc, tmp_keys, tmp_vals, g.m,
                          bits_for((uint64_t)g.n_b * (uint64_t)S), hist, scan_tmp, s);
-        k_fd_slices<<<grid1(g.m), kT, 0, s>>>(g, pb.state, fb.pkeys, S, fb.fd_beg, fb.fd_len, fb.task_w);
+        k_fd_slices<<<grid1(g.m), kT, 0, s>>>(g, pb.state, fb.pkeys, S, fb.fd_pos, fb.fd_beg, fb.fd_len, fb.task_w,
+                                              fb.fd_w);
         TIP_HIP_TRY(hipGetLastError());
     }
     k_fd_order<<<1, 1024, 0, s>>>(fb.task_w, S, fb.order);
@@ -280,7 +460,7 @@ void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl
     k_fd_reset_head<<<1, 1, 0, s>>>(ctl);
     TIP_HIP_TRY(hipGetLastError());
     const int grid = std::max(1, std::min<int>(S, big_grid));
-    k_fd_peel<<<grid, kBigThreads, 0, s>>>(g, fb, pb.init, S, spill, ctl);
+    k_fd_peel<<<grid, kFdThreads, 0, s>>>(g, fb, pb.init, S, spill, ctl);
     TIP_HIP_TRY(hipGetLastError());
 }
 

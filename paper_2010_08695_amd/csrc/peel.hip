@@ -339,7 +339,8 @@ struct PeelCounters {
 // Wave path: one wavefront per vertex, every 2-hop key in a per-wave LDS hash
 // table sized to the vertex's wedge count.
 __global__ void __launch_bounds__(kSmallThreads)
-k_peel_wave(DevGraph g, const int32_t* __restrict__ front, const int32_t* n_front_p, CdApply ap, Ctl* ctl) {
+k_peel_wave(DevGraph g, const int32_t* __restrict__ front, const int32_t* n_front_p, const int64_t* __restrict__ wprox,
+            CdApply ap, Ctl* ctl) {
     __shared__ WaveLds WL[kSmallThreads / kWave];
     const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     WaveLds& W = WL[wid];
@@ -355,6 +356,7 @@ k_peel_wave(DevGraph g, const int32_t* __restrict__ front, const int32_t* n_fron
             continue;
         }
         const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
+        const uint32_t slots = wave_slots(wprox[u]);
         for (int64_t g0 = 0; g0 < d; g0 += kWave) {
             const int gs = (int)min<int64_t>(kWave, d - g0);
             int64_t len = 0;
@@ -367,12 +369,12 @@ k_peel_wave(DevGraph g, const int32_t* __restrict__ front, const int32_t* n_fron
             for (int64_t i = lane; i < tot; i += kWave) {
                 const int j = wave_find_slice(W, gs, i);
                 const int32_t w = g.b_adj[W.sbeg[j] + (i - W.pre[j])];
-                if (w != u) wave_insert(W, (uint32_t)w);
+                if (w != u) wave_insert(W, (uint32_t)w, slots - 1);
             }
             if (lane == 0) pc.wedges += (unsigned long long)(tot - gs);
             wave_sync();
         }
-        for (int s = lane; s < kSmallSlots; s += kWave) {
+        for (uint32_t s = lane; s < slots; s += kWave) {
             const unsigned long long v = W.tab[s];
             if (v) W.tab[s] = 0;
             ap.apply(v != 0, (int32_t)((v >> 32) - 1), (int64_t)(v & 0xffffffffull), pc.pairs);
@@ -508,13 +510,15 @@ k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t nt
     pc.flush(ctl, true);
 }
 
-// Dense path: work item k = (frontier vertex k / ntt, key tile k % ntt).
-// Counters are CB bytes wide (CB = 1 or 2); the bins guarantee
-// c(u, w) <= d_u fits.  LDS: tk * CB counter bytes (dynamic) + staging.
+// Dense path: work item k = (frontier vertex k / ng, tiles [G * (k % ng),
+// G * (k % ng) + G)) with ng = ceil(ntt / G): one workgroup walks G
+// consecutive key tiles of one vertex.  Counters are CB bytes wide (CB = 1
+// or 2); the bins guarantee c(u, w) <= d_u fits.  LDS: tk * CB counter bytes
+// (dynamic) + staging.
 template <int CB>
 __global__ void __launch_bounds__(kDenseThreads)
-k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, const int32_t* __restrict__ front,
-             const int32_t* n_front_p, CdApply ap, Ctl* ctl) {
+k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, int32_t G,
+             const int32_t* __restrict__ front, const int32_t* n_front_p, CdApply ap, Ctl* ctl) {
     constexpr int NT = kDenseThreads;
     constexpr int PER_WORD = 4 / CB;             // counters per 32-bit word
     constexpr uint32_t CMASK = CB == 1 ? 0xffu : 0xffffu;
@@ -526,29 +530,51 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
     const int32_t n4 = tk * CB / 16;            // uint4 words per tile
     for (int w = tid; w < n4; w += NT) cnt4[w] = make_uint4(0, 0, 0, 0);
     __syncthreads();
-    const int64_t n_items = (int64_t)(*n_front_p) * ntt;
+    const int32_t ng = (ntt + G - 1) / G;
+    const int64_t n_items = (int64_t)(*n_front_p) * ng;
     PeelCounters pc;
     for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const int32_t u = front[it / ntt];
-        const int32_t t = (int32_t)(it % ntt);
+        const int32_t u = front[it / ng];
+        const int32_t t_begin = (int32_t)(it % ng) * G;
+        const int32_t t_end = min(ntt, t_begin + G);
         if (ap.supp[u] == 0) {
-            pc.skipped += (tid == 0 && t == 0);
+            pc.skipped += (tid == 0 && t_begin == 0);
             continue;
         }
-        const int32_t klo = t * tk;
         const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
-        if (tid == 0 && t == 0) pc.edges += (unsigned long long)d;
-        for (int64_t g0 = 0; g0 < d; g0 += NT) {
-            const int gs = (int)min<int64_t>(NT, d - g0);
-            int64_t s0 = 0;
-            int32_t len = 0;
-            if (tid < gs) {
-                const int32_t v = g.a_adj[e0 + g0 + tid];
-                const int32_t* row = tb + (int64_t)v * (ntt + 1);
-                const int32_t a = row[t];
-                s0 = g.b_off[v] + a;
-                len = row[t + 1] - a;
+        if (tid == 0 && t_begin == 0) pc.edges += (unsigned long long)d;
+        // keys with c >= 2 in the tile: apply (one per lane per step), clear
+        auto finish_tile = [&](int32_t klo) {
+            for (int32_t w4 = tid; w4 < n4; w4 += NT) {
+                const uint4 x = cnt4[w4];
+                const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+                if (x.x | x.y | x.z | x.w) cnt4[w4] = make_uint4(0, 0, 0, 0);
+                uint32_t mask = 0;  // counters >= 2 among the 16 (or 8) of this lane
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int bb = 0; bb < PER_WORD; ++bb)
+                        if (((xs[q] >> (8 * CB * bb)) & CMASK) >= 2) mask |= 1u << (q * PER_WORD + bb);
+                while (__ballot(mask != 0)) {
+                    int64_t c = 0;
+                    int32_t key = 0;
+                    if (mask) {
+                        const int i = __ffs(mask) - 1;
+                        mask &= mask - 1;
+                        const int q = i / PER_WORD, bb = i % PER_WORD;
+                        uint32_t word = 0;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (r == q) word = xs[r];
+                        c = (word >> (8 * CB * bb)) & CMASK;
+                        key = klo + w4 * (4 * PER_WORD) + i;
+                    }
+                    ap.apply(c >= 2, key, c, pc.pairs);
+                }
             }
+            __syncthreads();
+        };
+        auto count_runs = [&](int gs, int64_t s0, int32_t len, int32_t klo) {
             const int32_t nu = stage_units<NT>(S, gs, s0, len);
             unsigned long long wl = 0;
             traverse_units<NT>(S, gs, nu, g.b_adj, [&](int32_t w) {
@@ -560,36 +586,45 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
             });
             pc.wedges += wl;
             __syncthreads();
-        }
-        // keys with c >= 2: apply (one per lane per step), then clear the tile
-        for (int32_t w4 = tid; w4 < n4; w4 += NT) {
-            const uint4 x = cnt4[w4];
-            const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
-            if (x.x | x.y | x.z | x.w) cnt4[w4] = make_uint4(0, 0, 0, 0);
-            uint32_t mask = 0;  // counters >= 2, bit i = counter i of the 16 (or 8)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int b = 0; b < PER_WORD; ++b)
-                    if (((xs[q] >> (8 * CB * b)) & CMASK) >= 2) mask |= 1u << (q * PER_WORD + b);
-            while (__ballot(mask != 0)) {
-                int64_t c = 0;
-                int32_t key = 0;
-                if (mask) {
-                    const int i = __ffs(mask) - 1;
-                    mask &= mask - 1;
-                    const int q = i / PER_WORD, b = i % PER_WORD;
-                    uint32_t word = 0;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (r == q) word = xs[r];
-                    c = (word >> (8 * CB * b)) & CMASK;
-                    key = klo + w4 * (4 * PER_WORD) + i;
+        };
+        if (d <= NT) {
+            // one pass of neighbours: ids and list starts stay in registers
+            // while the tiles are walked; each tile's end is the next start
+            const int gs = (int)d;
+            const int32_t* row = tb;
+            int64_t base = 0;
+            int32_t a = 0;
+            if (tid < gs) {
+                const int32_t v = g.a_adj[e0 + tid];
+                row = tb + (int64_t)v * (ntt + 1);
+                base = g.b_off[v];
+                a = row[t_begin];
+            }
+            for (int32_t t = t_begin; t < t_end; ++t) {
+                int32_t b = a;
+                if (tid < gs) b = row[t + 1];
+                count_runs(gs, base + a, b - a, t * tk);
+                a = b;
+                finish_tile(t * tk);
+            }
+        } else {
+            for (int32_t t = t_begin; t < t_end; ++t) {
+                for (int64_t g0 = 0; g0 < d; g0 += NT) {
+                    const int gs = (int)min<int64_t>(NT, d - g0);
+                    int64_t s0 = 0;
+                    int32_t len = 0;
+                    if (tid < gs) {
+                        const int32_t v = g.a_adj[e0 + g0 + tid];
+                        const int32_t* row = tb + (int64_t)v * (ntt + 1);
+                        const int32_t a = row[t];
+                        s0 = g.b_off[v] + a;
+                        len = row[t + 1] - a;
+                    }
+                    count_runs(gs, s0, len, t * tk);
                 }
-                ap.apply(c >= 2, key, c, pc.pairs);
+                finish_tile(t * tk);
             }
         }
-        __syncthreads();
     }
     pc.flush(ctl, true);
 }
@@ -720,7 +755,7 @@ void launch_peel_round(const DevGraph& g, PeelBuffers& pb, int cur_front, const 
         const int nw = kSmallThreads / kWave;
         const int64_t blocks = std::min<int64_t>((n_cur[kBinWave] + nw - 1) / nw, 8192);
         k_peel_wave<<<(unsigned)blocks, kSmallThreads, 0, s>>>(g, pb.front[cur_front][kBinWave],
-                                                               &ctl->n_front[kBinWave], ap, ctl);
+                                                               &ctl->n_front[kBinWave], pb.wprox, ap, ctl);
         TIP_HIP_TRY(hipGetLastError());
     }
     const bool big = n_cur[kBinBitmap] > 0 || n_cur[kBinDense8] > 0 || n_cur[kBinDense16] > 0;
@@ -741,13 +776,17 @@ void launch_peel_round(const DevGraph& g, PeelBuffers& pb, int cur_front, const 
             TIP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         }
         const int64_t slots = (int64_t)cus * dense_occupancy(pb.tk, cb);
-        const int grid = (int)std::min<int64_t>((int64_t)n_cur[bin] * pb.ntt, slots);
+        // tiles per work item: as many as keeps about four items per slot
+        const int64_t n = n_cur[bin];
+        const int32_t G = (int32_t)std::max<int64_t>(1, std::min<int64_t>(pb.ntt, n * pb.ntt / (4 * slots)));
+        const int64_t items = n * ((pb.ntt + G - 1) / G);
+        const int grid = (int)std::min<int64_t>(items, slots);
         const size_t lds = dense_lds_bytes(pb.tk, cb);
         if (cb == 1)
-            k_peel_dense<1><<<grid, kDenseThreads, lds, s>>>(g, pb.tb, pb.tk, pb.ntt, pb.front[cur_front][bin],
+            k_peel_dense<1><<<grid, kDenseThreads, lds, s>>>(g, pb.tb, pb.tk, pb.ntt, G, pb.front[cur_front][bin],
                                                               &ctl->n_front[bin], ap, ctl);
         else
-            k_peel_dense<2><<<grid, kDenseThreads, lds, s>>>(g, pb.tb, pb.tk, pb.ntt, pb.front[cur_front][bin],
+            k_peel_dense<2><<<grid, kDenseThreads, lds, s>>>(g, pb.tb, pb.tk, pb.ntt, G, pb.front[cur_front][bin],
                                                               &ctl->n_front[bin], ap, ctl);
         TIP_HIP_TRY(hipGetLastError());
     }

@@ -43,6 +43,13 @@ inline int32_t dense_tile_keys(int64_t n) {
     return (int32_t)t;
 }
 
+// Fine-grained kernel (see fd.hip).
+constexpr int kFdThreads = 512;
+constexpr int kFdBits = 1 << 19;           // keys per bitmap tile for heavy peeled vertices
+constexpr int kFdRep = 2048;               // repeat slots of that path
+constexpr int kFdWaveSlots = 512;          // per-wave hash slots for light peeled vertices
+constexpr int64_t kFdWaveMax = 224;        // light: at most this many wedges inside the subset
+
 constexpr int32_t kLive = -1;              // subset id of a vertex not yet assigned
 
 // 64-bit hash-table slot: (key + 1) << 32 | count; 0 = empty.

@@ -68,8 +68,9 @@ struct FdBuffers {
     int64_t* task_w;     // [S]
     int32_t* order;      // [S]
     int64_t* supp_fd;    // [n_a] by subset position
+    int64_t* fd_w;       // [n_a] wedges of each vertex inside its subset's subgraph, by position
     int32_t* alive;      // [n_a] by subset position
-    int32_t* lst[3];     // [n_a] live / next-live / peel lists by subset position
+    int32_t* lst[4];     // [n_a] live / next-live / light-peel / heavy-peel lists by subset position
     int64_t* theta;      // [n_a] by rank
 };
 
