@@ -65,10 +65,14 @@ typedef struct {
                         (Alg. 3); 0 = 150, the value the paper's experiments
                         settle on; at most 65535 */
     int32_t flags;   /* TIP_FLAG_* bits; other bits must be 0 */
-    int32_t tune[8]; /* tune[0]: wedge count above which a vertex's update
-                        uses the dense key-tile kernel (0 = default, a
-                        quarter of the side's vertex count, at least 65536);
-                        tune[1..7] reserved, must be 0 */
+    int32_t tune[8]; /* update-kernel selection of the coarse-grained step;
+                        a vertex of degree d with w wedges in its 2-hop
+                        neighbourhood is updated by the dense key-range
+                        kernel when w > tune[1] and w > n_side * bits(d) /
+                        tune[0] (bits(d) = 2, 4, 8, 16 for d <= 3, 15, 255,
+                        65535), else by a per-vertex kernel;
+                        tune[0]: 0 = 64; tune[1]: 0 = 32768; both >= 0;
+                        tune[2..7] reserved, must be 0 */
 } tip_opts;
 
 /* Work and time accounting of one decomposition (NULL = not wanted). */

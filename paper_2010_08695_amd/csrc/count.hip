@@ -87,8 +87,9 @@ k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, con
                 len = min(sv.oth_cut[y], sv.own_rev[e]);
             }
             const int64_t tot = wave_scan_lengths(W, len);
+            int j = 0;
             for (int64_t i = lane; i < tot; i += kWave) {
-                const int j = wave_find_slice(W, gs, i);
+                while (j + 1 < gs && W.pre[j + 1] <= i) ++j;
                 wave_insert(W, (uint32_t)sv.oth_adj[W.sbeg[j] + (i - W.pre[j])], mask);
             }
             wave_sync();
@@ -106,8 +107,9 @@ k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, con
             }
             W.acc[lane] = 0;
             const int64_t tot = wave_scan_lengths(W, len);
+            int j = 0;
             for (int64_t i = lane; i < tot; i += kWave) {
-                const int j = wave_find_slice(W, gs, i);
+                while (j + 1 < gs && W.pre[j + 1] <= i) ++j;
                 const int32_t c = wave_lookup(W, (uint32_t)sv.oth_adj[W.sbeg[j] + (i - W.pre[j])], mask);
                 if (c > 1) atomicAdd(reinterpret_cast<unsigned long long*>(&W.acc[j]), (unsigned long long)(c - 1));
             }

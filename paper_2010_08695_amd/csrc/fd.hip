@@ -287,13 +287,9 @@ k_fd_peel(DevGraph g, FdBuffers fb, const int64_t* __restrict__ init, int32_t S,
                     const int64_t tot = __shfl(inc, kWave - 1, kWave);
                     if (lane == 0) L.wpre[wid][kWave] = tot;
                     wave_sync();
+                    int lo = 0;
                     for (int64_t i = lane; i < tot; i += kWave) {
-                        int lo = 0, hi = gs;
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (L.wpre[wid][mid] <= i) lo = mid;
-                            else hi = mid;
-                        }
+                        while (lo + 1 < gs && L.wpre[wid][lo + 1] <= i) ++lo;
                         const int32_t w = fb.pcsc[L.wsbeg[wid][lo] + (i - L.wpre[wid][lo])];
                         if (w != x) fd_wave_insert(tab, (uint32_t)w, mask);
                     }

@@ -34,7 +34,19 @@ struct Stage {
     int32_t len[NT];
     int32_t upre[NT + 1];
     int64_t red[NT / kWave];
+    int64_t item;
 };
+
+// Work items of a round are taken from a per-kernel counter, so workgroups
+// that drew cheap items go on to the next instead of idling behind one that
+// drew an expensive one.  All threads of the workgroup must call.
+template <int NT>
+__device__ inline int64_t next_item(Stage<NT>& S, unsigned long long* head) {
+    __syncthreads();
+    if (threadIdx.x == 0) S.item = (int64_t)atomicAdd(head, 1ull);
+    __syncthreads();
+    return S.item;
+}
 
 // Stages the runs held by threads j < gs (one run per thread: start, length)
 // and returns the number of traversal units (kUnit entries of one run).
@@ -63,25 +75,45 @@ __device__ inline int32_t stage_units(Stage<NT>& S, int gs, int64_t s0, int32_t 
     return (int32_t)tot;
 }
 
-// Every wave takes units in turn; a unit is read with coalesced loads.
+// Every wave takes units in turn (k = wave, wave + NW, ...); a unit is read
+// with coalesced loads.  A wave's unit indices only grow, so the run holding
+// a unit is found by stepping forward from the previous one; two units are
+// loaded before either is consumed, so four loads per lane are in flight.
+template <int NT>
+__device__ inline int advance_run(const Stage<NT>& S, int j, int gs, int32_t k) {
+    while (j + 1 < gs && S.upre[j + 1] <= k) ++j;
+    return j;
+}
+
 template <int NT, class F>
 __device__ inline void traverse_units(const Stage<NT>& S, int gs, int32_t nunits, const int32_t* __restrict__ adj,
                                       F&& f) {
+    constexpr int NW = NT / kWave;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    for (int32_t k = wid; k < nunits; k += NT / kWave) {
-        int lo = 0, hi = gs;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (S.upre[mid] <= k) lo = mid;
-            else hi = mid;
+    int j = 0;
+    for (int32_t k = wid; k < nunits; k += 2 * NW) {
+        const int32_t k2 = k + NW;
+        j = advance_run(S, j, gs, k);
+        const int32_t off = (k - S.upre[j]) * kUnit;
+        const int32_t n = min(kUnit, S.len[j] - off);
+        const int32_t* p = adj + S.sbeg[j] + off;
+        int32_t n2 = 0;
+        const int32_t* p2 = p;
+        if (k2 < nunits) {
+            const int j2 = advance_run(S, j, gs, k2);
+            const int32_t off2 = (k2 - S.upre[j2]) * kUnit;
+            n2 = min(kUnit, S.len[j2] - off2);
+            p2 = adj + S.sbeg[j2] + off2;
+            j = j2;
         }
-        const int32_t off = (k - S.upre[lo]) * kUnit;
-        const int32_t n = min(kUnit, S.len[lo] - off);
-        const int32_t* p = adj + S.sbeg[lo] + off;
         const int32_t x0 = lane < n ? p[lane] : -1;
         const int32_t x1 = lane + kWave < n ? p[lane + kWave] : -1;
+        const int32_t y0 = lane < n2 ? p2[lane] : -1;
+        const int32_t y1 = lane + kWave < n2 ? p2[lane + kWave] : -1;
         if (x0 >= 0) f(x0);
         if (x1 >= 0) f(x1);
+        if (y0 >= 0) f(y0);
+        if (y1 >= 0) f(y1);
     }
 }
 
@@ -98,17 +130,21 @@ __global__ void k_wproxy(DevGraph g, const int32_t* __restrict__ deg_b, int64_t*
     }
 }
 
-// Which update kernel peels u: by its wedge count and degree (the counter
-// width of the dense kernel must hold c(u, w) <= d_u).
+// Which update kernel peels u, by its wedge count w[u] and degree: the wave
+// kernel for a few hundred wedges; the bitmap kernel while the repeat keys
+// (a few percent of the wedges) fit its LDS table, i.e. up to bm_max wedges;
+// above that the dense kernel, unless its counter bytes (n_a * bits / 8,
+// bits from the degree so that c(u, w) <= d_u fits) are large against the
+// wedges (w <= n_a * bits / dense_div).
 __global__ void k_peel_bins(const int64_t* __restrict__ a_off, const int64_t* __restrict__ wprox, int32_t n_a,
-                            int64_t w_dense, uint8_t* bin) {
+                            int64_t dense_div, int64_t bm_max, uint8_t* bin) {
     GRID_STRIDE(u, (int64_t)n_a) {
         const int64_t w = wprox[u];
         const int64_t d = a_off[u + 1] - a_off[u];
+        const int bits = dense_bits(d);
         uint8_t b = kBinBitmap;
         if (w <= kSmallMaxWedges) b = kBinWave;
-        else if (w > w_dense && d <= kDense8MaxDegree) b = kBinDense8;
-        else if (w > w_dense && d <= kDense16MaxDegree) b = kBinDense16;
+        else if (bits && w > max<int64_t>(bm_max, (int64_t)n_a * bits / dense_div)) b = (uint8_t)dense_bin(bits);
         bin[u] = b;
     }
 }
@@ -132,7 +168,7 @@ __global__ void k_ctl_begin_range(Ctl* ctl) {
     ctl->max_supp = 0;
     ctl->w_rem = 0;
     ctl->w_range = 0;
-    for (int b = 0; b < kBins; ++b) ctl->n_front[b] = ctl->n_next[b] = 0;
+    for (int b = 0; b < kBins; ++b) ctl->n_front[b] = ctl->n_next[b] = ctl->head[b] = 0;
 }
 
 // Compacts the live list, snapshots the supports of the live vertices
@@ -289,7 +325,59 @@ __global__ void k_frontier_init(const int32_t* __restrict__ live, int32_t n_live
 // Delete-update
 // ---------------------------------------------------------------------------
 
-// Applies the decrement C(c, 2) of a (peeled u, live w) pair and appends w to
+// Up to B (key, c) pairs held by one lane in registers: every index is a
+// compile-time constant after unrolling, so nothing goes to private memory.
+template <int B>
+struct PairBuf {
+    int32_t key[B];
+    int32_t cnt[B];
+    int n = 0;
+
+    __device__ inline void push(int32_t k, int32_t c) {
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            if (i == n) {
+                key[i] = k;
+                cnt[i] = c;
+            }
+        ++n;
+    }
+};
+
+// Appends the keys with cross[i] to the frontier list of their bin: one
+// wave-wide scan and one counter atomic per bin that receives any key.  Must
+// be reached by all lanes of the wave.
+template <int B>
+__device__ inline void append_many(const bool (&cross)[B], const int32_t (&key)[B], const uint8_t (&bn)[B],
+                                   const Fronts& f) {
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < B; ++i) any = any || cross[i];
+    if (!__ballot(any)) return;
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int k = 0; k < kBins; ++k) {
+        int c = 0;
+#pragma unroll
+        for (int i = 0; i < B; ++i) c += (cross[i] && bn[i] == k) ? 1 : 0;
+        if (!__ballot(c > 0)) continue;
+        int incl = c;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int y = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += y;
+        }
+        const int tot = __shfl(incl, kWave - 1, kWave);
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&f.count[k], tot);
+        int pos = __shfl(base, 0, kWave) + incl - c;
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            if (cross[i] && bn[i] == k) f.list[k][pos++] = key[i];
+    }
+}
+
+// Applies the decrement C(c, 2) of (peeled u, live w) pairs and appends w to
 // the next activeSet when its support crosses below the range's upper bound.
 struct CdApply {
     int64_t* supp;
@@ -298,18 +386,39 @@ struct CdApply {
     long long hi;
     Fronts next;
 
+    // Applies and empties the lane's buffered pairs (all with c >= 2).  The
+    // state loads of the whole batch are issued together, then its atomics,
+    // so a batch costs two memory round trips however many pairs it holds.
     // Must be reached by all lanes of the wave.
-    __device__ inline void apply(bool valid, int32_t w, int64_t c, unsigned long long& pairs) const {
-        bool cross = false;
-        uint8_t b = 0;
-        if (valid && c >= 2 && state[w] == kLive) {
-            const int64_t dec = choose2(c);
-            const int64_t old = atomic_add_i64_ret(&supp[w], -dec);
-            cross = old >= hi && old - dec < hi;
-            ++pairs;
-            if (cross) b = bin[w];
+    template <int B>
+    __device__ inline void flush(PairBuf<B>& pb, unsigned long long& pairs) const {
+        int32_t st[B];
+        uint8_t bn[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            st[i] = 0;
+            bn[i] = 0;
+            if (i < pb.n) {
+                st[i] = state[pb.key[i]];
+                bn[i] = bin[pb.key[i]];
+            }
         }
-        append_binned(cross, w, b, next);
+        int64_t old[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            old[i] = 0;
+            if (i < pb.n && st[i] == kLive) old[i] = atomic_add_i64_ret(&supp[pb.key[i]], -choose2(pb.cnt[i]));
+        }
+        bool cross[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const bool live = i < pb.n && st[i] == kLive;
+            const int64_t dec = choose2(pb.cnt[i]);
+            cross[i] = live && old[i] >= hi && old[i] - dec < hi;
+            pairs += live ? 1 : 0;
+        }
+        append_many<B>(cross, pb.key, bn, next);
+        pb.n = 0;
     }
 };
 
@@ -366,19 +475,25 @@ k_peel_wave(DevGraph g, const int32_t* __restrict__ front, const int32_t* n_fron
                 len = g.b_off[v + 1] - W.sbeg[lane];
             }
             const int64_t tot = wave_scan_lengths(W, len);
+            int j = 0;
             for (int64_t i = lane; i < tot; i += kWave) {
-                const int j = wave_find_slice(W, gs, i);
+                while (j + 1 < gs && W.pre[j + 1] <= i) ++j;
                 const int32_t w = g.b_adj[W.sbeg[j] + (i - W.pre[j])];
                 if (w != u) wave_insert(W, (uint32_t)w, slots - 1);
             }
             if (lane == 0) pc.wedges += (unsigned long long)(tot - gs);
             wave_sync();
         }
+        // slots is a multiple of the wave size, so the loop is wave-uniform
+        PairBuf<4> pbuf;
         for (uint32_t s = lane; s < slots; s += kWave) {
             const unsigned long long v = W.tab[s];
             if (v) W.tab[s] = 0;
-            ap.apply(v != 0, (int32_t)((v >> 32) - 1), (int64_t)(v & 0xffffffffull), pc.pairs);
+            const int32_t c = (int32_t)(v & 0xffffffffull);
+            if (c >= 2) pbuf.push((int32_t)((v >> 32) - 1), c);
+            if (__ballot(pbuf.n == 4)) ap.flush(pbuf, pc.pairs);
         }
+        ap.flush(pbuf, pc.pairs);
         wave_sync();
     }
     pc.flush(ctl, false);
@@ -432,7 +547,9 @@ k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t nt
     const int64_t n_front = *n_front_p;
     const int32_t sub = kBmTile / tk;  // table tiles per bitmap tile
     PeelCounters pc;
-    for (int64_t it = blockIdx.x; it < n_front; it += gridDim.x) {
+    for (;;) {
+        const int64_t it = next_item(L.st, &ctl->head[kBinBitmap]);
+        if (it >= n_front) break;
         const int32_t u = front[it];
         if (ap.supp[u] == 0) {
             pc.skipped += tid == 0;
@@ -467,38 +584,27 @@ k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t nt
                 pc.wedges += wl;
                 __syncthreads();
             }
-            // repeat keys: each thread owns kPer slots; apply one occupied slot
-            // per lane and step until no lane of the wave has any left
-            unsigned long long held[kPer];
-            uint32_t mask = 0;
-#pragma unroll
+            // repeat keys: each thread owns kPer slots, applied in batches
+            PairBuf<kApplyBatch> pbuf;
             for (int q = 0; q < kPer; ++q) {
-                held[q] = L.rep[tid + q * NT];
-                if (held[q]) mask |= 1u << q;
+                const unsigned long long v = L.rep[tid + q * NT];
+                if (v) pbuf.push(klo + (int32_t)((v >> 32) - 1), 1 + (int32_t)(v & 0xffffffffull));
+                if (__ballot(pbuf.n == kApplyBatch)) ap.flush(pbuf, pc.pairs);
             }
-            while (__ballot(mask != 0)) {
-                unsigned long long v = 0;
-                if (mask) {
-                    const int q = __ffs(mask) - 1;
-                    mask &= mask - 1;
-#pragma unroll
-                    for (int r = 0; r < kPer; ++r)
-                        if (r == q) v = held[r];
-                }
-                ap.apply(v != 0, klo + (int32_t)((v >> 32) - 1), 1 + (int64_t)(v & 0xffffffffull), pc.pairs);
-            }
+            ap.flush(pbuf, pc.pairs);
             const int32_t nsp = L.spill_n;
             if (tid == 0) pc.spills += (unsigned long long)nsp;
             for (int32_t b0 = 0; b0 < nsp; b0 += NT) {
                 const int32_t i = b0 + tid;
-                int32_t k = 0, r = 0;
                 if (i < nsp) {
-                    k = sp.list[i];
-                    r = sp.dense[k];
+                    const int32_t k = sp.list[i];
+                    const int32_t r = sp.dense[k];
                     sp.dense[k] = 0;
+                    pbuf.push(klo + k, 1 + r);
                 }
-                ap.apply(i < nsp, klo + k, 1 + (int64_t)r, pc.pairs);
+                if (__ballot(pbuf.n == kApplyBatch)) ap.flush(pbuf, pc.pairs);
             }
+            ap.flush(pbuf, pc.pairs);
             __syncthreads();
             const int32_t words = (khi - klo + 31) >> 5;
             for (int w = tid; w < words; w += NT) L.bm[w] = 0;
@@ -510,30 +616,53 @@ k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t nt
     pc.flush(ctl, true);
 }
 
-// Dense path: work item k = (frontier vertex k / ng, tiles [G * (k % ng),
-// G * (k % ng) + G)) with ng = ceil(ntt / G): one workgroup walks G
-// consecutive key tiles of one vertex.  Counters are CB bytes wide (CB = 1
-// or 2); the bins guarantee c(u, w) <= d_u fits.  LDS: tk * CB counter bytes
-// (dynamic) + staging.
-template <int CB>
+// Counters of value >= 2 in a word of BITS-bit counters: the top bit of
+// every such field is set in the result.
+template <int BITS>
+__device__ inline uint32_t ge2_mask(uint32_t x) {
+    if (BITS == 2) return x & 0xaaaaaaaau;
+    if (BITS == 4) {
+        const uint32_t t = x & 0xeeeeeeeeu;
+        return (((t & 0x77777777u) + 0x77777777u) | t) & 0x88888888u;
+    }
+    if (BITS == 8) {
+        const uint32_t t = x & 0xfefefefeu;
+        return (((t & 0x7f7f7f7fu) + 0x7f7f7f7fu) | t) & 0x80808080u;
+    }
+    const uint32_t t = x & 0xfffefffeu;
+    return (((t & 0x7fff7fffu) + 0x7fff7fffu) | t) & 0x80008000u;
+}
+
+// Dense path: work item k = (frontier vertex k / ng, table tiles
+// [G * (k % ng), G * (k % ng) + G)) with ng = ceil(ntt / G): one workgroup
+// counts the 2-hop keys of one vertex inside a key range of G * tk keys with
+// one BITS-bit LDS counter per key; the bins guarantee c(u, w) <= d_u fits.
+// LDS: G * tk * BITS / 8 counter bytes (dynamic) + staging.
+template <int BITS>
 __global__ void __launch_bounds__(kDenseThreads)
 k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, int32_t G,
-             const int32_t* __restrict__ front, const int32_t* n_front_p, CdApply ap, Ctl* ctl) {
+             const int32_t* __restrict__ front, const int32_t* n_front_p, unsigned long long* head, CdApply ap,
+             Ctl* ctl) {
     constexpr int NT = kDenseThreads;
-    constexpr int PER_WORD = 4 / CB;             // counters per 32-bit word
-    constexpr uint32_t CMASK = CB == 1 ? 0xffu : 0xffffu;
+    constexpr int PER_WORD = 32 / BITS;          // counters per 32-bit word
+    constexpr uint32_t FMASK = BITS == 16 ? 0xffffu : ((1u << BITS) - 1);
     extern __shared__ __align__(16) uint32_t dyn[];
     uint32_t* cnt = dyn;
-    Stage<NT>& S = *reinterpret_cast<Stage<NT>*>(dyn + (int64_t)tk * CB / 4);
+    const int64_t max_keys = (int64_t)G * tk;
+    Stage<NT>& S = *reinterpret_cast<Stage<NT>*>(dyn + max_keys / PER_WORD);
     uint4* cnt4 = reinterpret_cast<uint4*>(cnt);
     const int tid = threadIdx.x;
-    const int32_t n4 = tk * CB / 16;            // uint4 words per tile
-    for (int w = tid; w < n4; w += NT) cnt4[w] = make_uint4(0, 0, 0, 0);
+    {
+        const int32_t n4 = (int32_t)(max_keys / PER_WORD / 4);
+        for (int w = tid; w < n4; w += NT) cnt4[w] = make_uint4(0, 0, 0, 0);
+    }
     __syncthreads();
     const int32_t ng = (ntt + G - 1) / G;
     const int64_t n_items = (int64_t)(*n_front_p) * ng;
     PeelCounters pc;
-    for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    for (;;) {
+        const int64_t it = next_item(S, head);
+        if (it >= n_items) break;
         const int32_t u = front[it / ng];
         const int32_t t_begin = (int32_t)(it % ng) * G;
         const int32_t t_end = min(ntt, t_begin + G);
@@ -541,95 +670,95 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
             pc.skipped += (tid == 0 && t_begin == 0);
             continue;
         }
+        const int32_t klo = t_begin * tk;
         const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
         if (tid == 0 && t_begin == 0) pc.edges += (unsigned long long)d;
-        // keys with c >= 2 in the tile: apply (one per lane per step), clear
-        auto finish_tile = [&](int32_t klo) {
-            for (int32_t w4 = tid; w4 < n4; w4 += NT) {
-                const uint4 x = cnt4[w4];
-                const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
-                if (x.x | x.y | x.z | x.w) cnt4[w4] = make_uint4(0, 0, 0, 0);
-                uint32_t mask = 0;  // counters >= 2 among the 16 (or 8) of this lane
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int bb = 0; bb < PER_WORD; ++bb)
-                        if (((xs[q] >> (8 * CB * bb)) & CMASK) >= 2) mask |= 1u << (q * PER_WORD + bb);
-                while (__ballot(mask != 0)) {
-                    int64_t c = 0;
-                    int32_t key = 0;
-                    if (mask) {
-                        const int i = __ffs(mask) - 1;
-                        mask &= mask - 1;
-                        const int q = i / PER_WORD, bb = i % PER_WORD;
-                        uint32_t word = 0;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (r == q) word = xs[r];
-                        c = (word >> (8 * CB * bb)) & CMASK;
-                        key = klo + w4 * (4 * PER_WORD) + i;
-                    }
-                    ap.apply(c >= 2, key, c, pc.pairs);
-                }
+        for (int64_t g0 = 0; g0 < d; g0 += NT) {
+            const int gs = (int)min<int64_t>(NT, d - g0);
+            int64_t s0 = 0;
+            int32_t len = 0;
+            if (tid < gs) {
+                const int32_t v = g.a_adj[e0 + g0 + tid];
+                const int32_t* row = tb + (int64_t)v * (ntt + 1);
+                const int32_t a = row[t_begin];
+                s0 = g.b_off[v] + a;
+                len = row[t_end] - a;
             }
-            __syncthreads();
-        };
-        auto count_runs = [&](int gs, int64_t s0, int32_t len, int32_t klo) {
             const int32_t nu = stage_units<NT>(S, gs, s0, len);
             unsigned long long wl = 0;
             traverse_units<NT>(S, gs, nu, g.b_adj, [&](int32_t w) {
                 if (w != u) {
                     ++wl;
                     const uint32_t k = (uint32_t)(w - klo);
-                    atomicAdd(&cnt[k / PER_WORD], 1u << ((k % PER_WORD) * 8 * CB));
+                    atomicAdd(&cnt[k / PER_WORD], 1u << ((k % PER_WORD) * BITS));
                 }
             });
             pc.wedges += wl;
             __syncthreads();
-        };
-        if (d <= NT) {
-            // one pass of neighbours: ids and list starts stay in registers
-            // while the tiles are walked; each tile's end is the next start
-            const int gs = (int)d;
-            const int32_t* row = tb;
-            int64_t base = 0;
-            int32_t a = 0;
-            if (tid < gs) {
-                const int32_t v = g.a_adj[e0 + tid];
-                row = tb + (int64_t)v * (ntt + 1);
-                base = g.b_off[v];
-                a = row[t_begin];
+        }
+        // keys with c >= 2 are gathered per lane in registers and applied in
+        // batches; counters are cleared as they are read
+        const int32_t n4 = (int32_t)((int64_t)(t_end - t_begin) * tk / PER_WORD / 4);
+        PairBuf<kApplyBatch> pbuf;
+        for (int32_t base = 0; base < n4; base += NT) {
+            const int32_t w4 = base + tid;
+            uint4 x = make_uint4(0, 0, 0, 0);
+            if (w4 < n4) {
+                x = cnt4[w4];
+                if (x.x | x.y | x.z | x.w) cnt4[w4] = make_uint4(0, 0, 0, 0);
             }
-            for (int32_t t = t_begin; t < t_end; ++t) {
-                int32_t b = a;
-                if (tid < gs) b = row[t + 1];
-                count_runs(gs, base + a, b - a, t * tk);
-                a = b;
-                finish_tile(t * tk);
-            }
-        } else {
-            for (int32_t t = t_begin; t < t_end; ++t) {
-                for (int64_t g0 = 0; g0 < d; g0 += NT) {
-                    const int gs = (int)min<int64_t>(NT, d - g0);
-                    int64_t s0 = 0;
-                    int32_t len = 0;
-                    if (tid < gs) {
-                        const int32_t v = g.a_adj[e0 + g0 + tid];
-                        const int32_t* row = tb + (int64_t)v * (ntt + 1);
-                        const int32_t a = row[t];
-                        s0 = g.b_off[v] + a;
-                        len = row[t + 1] - a;
+            const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+            uint32_t msk[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) msk[q] = ge2_mask<BITS>(xs[q]);
+            const int32_t kbase = klo + w4 * 4 * PER_WORD;
+            for (;;) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    while (msk[q] && pbuf.n < kApplyBatch) {
+                        const int bit = __ffs(msk[q]) - 1;
+                        msk[q] &= msk[q] - 1;
+                        const int f = bit / BITS;
+                        pbuf.push(kbase + q * PER_WORD + f, (int32_t)((xs[q] >> (f * BITS)) & FMASK));
                     }
-                    count_runs(gs, s0, len, t * tk);
                 }
-                finish_tile(t * tk);
+                if (!__ballot((msk[0] | msk[1] | msk[2] | msk[3]) != 0)) break;
+                ap.flush(pbuf, pc.pairs);
             }
         }
+        ap.flush(pbuf, pc.pairs);
+        __syncthreads();
     }
     pc.flush(ctl, true);
 }
 
-size_t dense_lds_bytes(int32_t tk, int cb) { return (size_t)tk * cb + sizeof(Stage<kDenseThreads>); }
+size_t dense_lds_bytes(int64_t keys, int bits) { return (size_t)(keys * bits / 8) + sizeof(Stage<kDenseThreads>); }
+
+template <int BITS>
+void launch_dense(const DevGraph& g, PeelBuffers& pb, int cur_front, int32_t n, CdApply ap, Ctl* ctl,
+                  hipStream_t s) {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        TIP_HIP_TRY(hipGetDevice(&dev));
+        TIP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    }
+    const int bin = dense_bin(BITS);
+    // widest key range per item the LDS allows, narrowed while there would
+    // be fewer than about four items per resident workgroup
+    const int32_t g_max = (int32_t)std::min<int64_t>(pb.ntt, dense_item_keys(BITS, pb.tk) / pb.tk);
+    const size_t lds = dense_lds_bytes((int64_t)g_max * pb.tk, BITS);
+    int occ = 0;
+    TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel_dense<BITS>, kDenseThreads, lds));
+    const int64_t slots = (int64_t)cus * std::max(1, occ);
+    int32_t G = g_max;
+    while (G > 1 && (int64_t)n * ((pb.ntt + G - 1) / G) < 4 * slots) G = (G + 1) / 2;
+    const int64_t items = (int64_t)n * ((pb.ntt + G - 1) / G);
+    const int grid = (int)std::min<int64_t>(items, slots);
+    k_peel_dense<BITS><<<grid, kDenseThreads, dense_lds_bytes((int64_t)G * pb.tk, BITS), s>>>(
+        g, pb.tb, pb.tk, pb.ntt, G, pb.front[cur_front][bin], &ctl->n_front[bin], &ctl->head[bin], ap, ctl);
+    TIP_HIP_TRY(hipGetLastError());
+}
 
 // Vertices that crossed below the upper bound during the round become the
 // next activeSet: assign them to the subset before any of them is peeled.
@@ -661,6 +790,7 @@ __global__ void k_ctl_swap_front(Ctl* ctl) {
     for (int b = 0; b < kBins; ++b) {
         ctl->n_front[b] = ctl->n_next[b];
         ctl->n_next[b] = 0;
+        ctl->head[b] = 0;
     }
 }
 
@@ -683,19 +813,7 @@ int peel_occupancy() {
     return std::max(1, a);
 }
 
-// Resident dense-kernel workgroups per CU for a tile size (LDS-limited).
-static int dense_occupancy(int32_t tk, int cb) {
-    int a = 0;
-    if (cb == 1)
-        TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_peel_dense<1>, kDenseThreads,
-                                                                 dense_lds_bytes(tk, 1)));
-    else
-        TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_peel_dense<2>, kDenseThreads,
-                                                                 dense_lds_bytes(tk, 2)));
-    return std::max(1, a);
-}
-
-void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers& pb, int64_t w_dense,
+void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers& pb, const Tune& tune,
                        hipStream_t s) {
     fill_i64(pb.wprox, 0, g.n_a, s);
     if (g.m > 0) {
@@ -703,7 +821,8 @@ void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers
         TIP_HIP_TRY(hipGetLastError());
     }
     if (g.n_a > 0) {
-        k_peel_bins<<<grid1(g.n_a), kT, 0, s>>>(g.a_off, pb.wprox, g.n_a, w_dense, pb.bin);
+        k_peel_bins<<<grid1(g.n_a), kT, 0, s>>>(g.a_off, pb.wprox, g.n_a, tune.dense_div, tune.bitmap_max,
+                                                pb.bin);
         TIP_HIP_TRY(hipGetLastError());
     }
     const int64_t n_tb = (int64_t)g.n_b * (pb.ntt + 1);
@@ -758,7 +877,8 @@ void launch_peel_round(const DevGraph& g, PeelBuffers& pb, int cur_front, const 
                                                                &ctl->n_front[kBinWave], pb.wprox, ap, ctl);
         TIP_HIP_TRY(hipGetLastError());
     }
-    const bool big = n_cur[kBinBitmap] > 0 || n_cur[kBinDense8] > 0 || n_cur[kBinDense16] > 0;
+    bool big = false;
+    for (int b = kBinBitmap; b < kBins; ++b) big = big || n_cur[b] > 0;
     if (big && ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[0], s));
     if (n_cur[kBinBitmap] > 0) {
         const int grid = (int)std::min<int64_t>(n_cur[kBinBitmap], std::min(big_grid, spill.slots));
@@ -766,30 +886,10 @@ void launch_peel_round(const DevGraph& g, PeelBuffers& pb, int cur_front, const 
                                                    &ctl->n_front[kBinBitmap], ap, spill, ctl);
         TIP_HIP_TRY(hipGetLastError());
     }
-    for (int cb = 1; cb <= 2; ++cb) {
-        const int bin = cb == 1 ? kBinDense8 : kBinDense16;
-        if (n_cur[bin] <= 0) continue;
-        static int cus = 0;
-        if (!cus) {
-            int dev = 0;
-            TIP_HIP_TRY(hipGetDevice(&dev));
-            TIP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        }
-        const int64_t slots = (int64_t)cus * dense_occupancy(pb.tk, cb);
-        // tiles per work item: as many as keeps about four items per slot
-        const int64_t n = n_cur[bin];
-        const int32_t G = (int32_t)std::max<int64_t>(1, std::min<int64_t>(pb.ntt, n * pb.ntt / (4 * slots)));
-        const int64_t items = n * ((pb.ntt + G - 1) / G);
-        const int grid = (int)std::min<int64_t>(items, slots);
-        const size_t lds = dense_lds_bytes(pb.tk, cb);
-        if (cb == 1)
-            k_peel_dense<1><<<grid, kDenseThreads, lds, s>>>(g, pb.tb, pb.tk, pb.ntt, G, pb.front[cur_front][bin],
-                                                              &ctl->n_front[bin], ap, ctl);
-        else
-            k_peel_dense<2><<<grid, kDenseThreads, lds, s>>>(g, pb.tb, pb.tk, pb.ntt, G, pb.front[cur_front][bin],
-                                                              &ctl->n_front[bin], ap, ctl);
-        TIP_HIP_TRY(hipGetLastError());
-    }
+    if (n_cur[kBinDense2] > 0) launch_dense<2>(g, pb, cur_front, n_cur[kBinDense2], ap, ctl, s);
+    if (n_cur[kBinDense4] > 0) launch_dense<4>(g, pb, cur_front, n_cur[kBinDense4], ap, ctl, s);
+    if (n_cur[kBinDense8] > 0) launch_dense<8>(g, pb, cur_front, n_cur[kBinDense8], ap, ctl, s);
+    if (n_cur[kBinDense16] > 0) launch_dense<16>(g, pb, cur_front, n_cur[kBinDense16], ap, ctl, s);
     if (big && ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[1], s));
 }
 

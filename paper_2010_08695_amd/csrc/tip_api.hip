@@ -3,6 +3,7 @@
 // decomposition.  All arithmetic runs in the HIP kernels; the host only
 // sequences launches and reads a small control block between CD rounds.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -219,16 +220,18 @@ __global__ void k_scatter_i32(const int32_t* by_rank, const int32_t* orig, int32
 
 // Ingest + count (+ CD + FD when decomposing).  Returns TIP_OK or an error
 // status (EINVAL for out-of-range ids found on the device).
-// Wedge count above which a vertex is peeled by the dense (vertex, tile)
-// kernel: its 2-hop neighbourhood then covers a large share of the key space.
-int64_t default_dense_threshold(int32_t n_a) { return std::max<int64_t>(4096, (int64_t)n_a / 16); }
-
 tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int32_t n_b, int64_t m, bool a_is_u,
-               int32_t P, int32_t flags, int64_t w_dense, bool decompose, RunOut& out, tip_stats* st,
+               int32_t P, int32_t flags, const Tune& tune, bool decompose, RunOut& out, tip_stats* st,
                hipStream_t s) {
     Events ev;
     Events kev;  // [0], [1]: around one workgroup peeling launch
     const bool time_kernels = (flags & TIP_FLAG_TIME_KERNELS) != 0;
+    // diagnostic: with kernel timing on, TIP_TRACE_ROUNDS=1 prints every
+    // coarse-grained round's frontier sizes and update time to stderr
+    static const bool trace_rounds = [] {
+        const char* e = std::getenv("TIP_TRACE_ROUNDS");
+        return e && e[0] == '1';
+    }();
     double peel_ms = 0.0;
     int64_t peel_launches = 0;
     TIP_HIP_TRY(hipEventRecord(ev.e[0], s));
@@ -259,7 +262,7 @@ tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int
     } else {
         // Coarse-grained decomposition (Alg. 3).
         PeelBuffers& pb = w.pb;
-        launch_peel_setup(g, w.aux.deg_b, pb, w_dense > 0 ? w_dense : default_dense_threshold(n_a), s);
+        launch_peel_setup(g, w.aux.deg_b, pb, tune, s);
         fill_i32(pb.state, kLive, n_a, s);
         iota_i32(pb.live[0], n_a, s);
         int cur_live = 0;
@@ -297,7 +300,8 @@ tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int
                 int64_t n_tot = 0;
                 for (int b = 0; b < kBins; ++b) n_tot += (n_cur[b] = c2.n_front[b]);
                 if (n_tot == 0) break;
-                const int32_t nb = n_cur[kBinBitmap] + n_cur[kBinDense8] + n_cur[kBinDense16];
+                int32_t nb = 0;
+                for (int b = kBinBitmap; b < kBins; ++b) nb += n_cur[b];
                 launch_peel_round(g, pb, cur_front, n_cur, hi, w.ctl, w.spill, big_grid, s,
                                   time_kernels && nb > 0 ? kev.e : nullptr);
                 launch_round_end(pb, 1 - cur_front, n_live, label, w.ctl, s);
@@ -305,7 +309,12 @@ tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int
                     ++peel_launches;
                     if (time_kernels) {
                         TIP_HIP_TRY(hipEventSynchronize(kev.e[1]));
-                        peel_ms += kev.ms(0, 1);
+                        const double ms = kev.ms(0, 1);
+                        peel_ms += ms;
+                        if (trace_rounds)
+                            std::fprintf(stderr, "tip-round range=%d round=%lld bins=%d,%d,%d,%d,%d,%d ms=%.4f\n",
+                                         label, (long long)rounds, n_cur[0], n_cur[1], n_cur[2], n_cur[3],
+                                         n_cur[4], n_cur[5], ms);
                     }
                 }
                 cur_front ^= 1;
@@ -411,9 +420,17 @@ int32_t check_opts(const tip_opts* opt) {
     if (opt->P < 0 || opt->P > kMaxP) throw InvalidArg("P must be in [0, 65535]");
     if (opt->flags & ~TIP_FLAG_TIME_KERNELS) throw InvalidArg("unknown flag bits");
     if (opt->tune[0] < 0) throw InvalidArg("tune[0] must be >= 0");
-    for (int i = 1; i < 8; ++i)
-        if (opt->tune[i] != 0) throw InvalidArg("tune[1..7] must be 0");
+    if (opt->tune[1] < 0) throw InvalidArg("tune[1] must be >= 0");
+    for (int i = 2; i < 8; ++i)
+        if (opt->tune[i] != 0) throw InvalidArg("tune[2..7] must be 0");
     return opt->P == 0 ? kDefaultP : opt->P;
+}
+
+Tune tune_of(const tip_opts* opt) {
+    Tune t;
+    if (opt && opt->tune[0] > 0) t.dense_div = opt->tune[0];
+    if (opt && opt->tune[1] > 0) t.bitmap_max = opt->tune[1];
+    return t;
 }
 
 template <class F>
@@ -441,7 +458,7 @@ tip_status guard(F&& f) {
 
 // Host-pointer decomposition of one graph (side already validated).
 tip_status decompose_host(const tip_edges* g, int32_t side, int64_t* theta, int32_t P, int32_t flags,
-                          int64_t w_dense, tip_stats* st, int32_t* subset, int64_t* init, int64_t* bounds,
+                          const Tune& tune, tip_stats* st, int32_t* subset, int64_t* init, int64_t* bounds,
                           int32_t* n_subsets) {
     const bool a_is_u = side == TIP_SIDE_U;
     const int32_t n_a = a_is_u ? g->n_u : g->n_v;
@@ -477,7 +494,7 @@ tip_status decompose_host(const tip_edges* g, int32_t side, int64_t* theta, int3
     out.bounds = &bvec;
     int32_t ns = 0;
     out.n_subsets = &ns;
-    const tip_status rc = run(w, d_a, d_b, n_a, n_b, m, a_is_u, P, flags, w_dense, true, out, st, s);
+    const tip_status rc = run(w, d_a, d_b, n_a, n_b, m, a_is_u, P, flags, tune, true, out, st, s);
     if (rc != TIP_OK) return rc;
     if (n_a > 0) {
         TIP_HIP_TRY(hipMemcpyAsync(theta, d_theta, sizeof(int64_t) * n_a, hipMemcpyDeviceToHost, s));
@@ -539,7 +556,7 @@ tip_status tip_count_butterflies(const tip_edges* g, int64_t* bfly_u, int64_t* b
         RunOut out;
         out.bfly_a = d_bu;
         out.bfly_b = d_bv;
-        const tip_status rc = run(w, d_a, d_b, n_a, n_b, m, true, 1, 0, 0, false, out, nullptr, s);
+        const tip_status rc = run(w, d_a, d_b, n_a, n_b, m, true, 1, 0, Tune{}, false, out, nullptr, s);
         if (rc != TIP_OK) return rc;
         if (total) {
             k_sum_i64<<<1, 1024, 0, s>>>(w.cb.bfly_a, n_a, w.total);
@@ -565,7 +582,7 @@ tip_status tip_decompose_ex(const tip_edges* g, int32_t side, int64_t* theta, co
         const int32_t P = check_opts(opt);
         const int32_t n_side = side == TIP_SIDE_U ? g->n_u : g->n_v;
         if (n_side > 0 && !theta) throw InvalidArg("theta is NULL");
-        return decompose_host(g, side, theta, P, opt ? opt->flags : 0, opt ? opt->tune[0] : 0, st, subset,
+        return decompose_host(g, side, theta, P, opt ? opt->flags : 0, tune_of(opt), st, subset,
                               init_support, bounds, n_subsets);
     });
 }
@@ -588,7 +605,7 @@ tip_status tip_decompose_batch(int32_t n, const tip_edges* gs, const int32_t* si
         }
         for (int32_t k = 0; k < n; ++k) {
             const tip_status rc = decompose_host(&gs[k], sides[k], thetas[k], P, opt ? opt->flags : 0,
-                                                 opt ? opt->tune[0] : 0, st ? &st[k] : nullptr, nullptr, nullptr,
+                                                 tune_of(opt), st ? &st[k] : nullptr, nullptr, nullptr,
                                                  nullptr, nullptr);
             if (rc != TIP_OK) return rc;
         }
@@ -636,7 +653,7 @@ tip_status tip_decompose_async(const int32_t* d_eu, const int32_t* d_ev, int32_t
         RunOut out;
         out.theta = d_theta;
         return run(w, a_is_u ? d_eu : d_ev, a_is_u ? d_ev : d_eu, n_a, n_b, m, a_is_u, P, opt ? opt->flags : 0,
-                   opt ? opt->tune[0] : 0, true, out, st, s);
+                   tune_of(opt), true, out, st, s);
     });
 }
 

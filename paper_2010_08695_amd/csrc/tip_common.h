@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <algorithm>
 #include <cstdio>
 #include <string>
 
@@ -28,19 +29,36 @@ constexpr int64_t kSmallMaxWedges = 448;   // wave path handles <= this many wed
 constexpr int kBmTile = 1 << 19;           // keys per bitmap-path tile (64 KiB of bits)
 constexpr int kBmRep = 8192;               // bitmap-path repeat slots (64 KiB)
 constexpr int kUnit = 128;                 // consecutive list entries per traversal unit
-constexpr int kDenseThreads = 256;         // threads of the dense (vertex, key tile) kernel
-constexpr int kMinTileKeys = 4096;         // key-tile size range of the dense kernel; the
-constexpr int kMaxTileKeys = 65536;        //   per-list tile-bound table uses the same tiles
-constexpr int64_t kDense8MaxDegree = 255;      // 8-bit counters: c(u, w) <= d_u
-constexpr int64_t kDense16MaxDegree = 65535;   // 16-bit counters
-constexpr int kBins = 4;
-constexpr int kBinWave = 0, kBinBitmap = 1, kBinDense8 = 2, kBinDense16 = 3;
+constexpr int kDenseThreads = 256;         // threads of the dense (vertex, key range) kernel
+constexpr int kDenseLdsBytes = 32768;      // counter bytes per dense workgroup (four per CU)
+constexpr int kBins = 6;
+constexpr int kBinWave = 0, kBinBitmap = 1, kBinDense2 = 2, kBinDense4 = 3, kBinDense8 = 4, kBinDense16 = 5;
+constexpr int kDefaultDenseDiv = 64;       // dense needs w[u] > n * bits / div (tip_opts.tune[0])
+constexpr int64_t kDefaultBitmapMax = 32768;  // bitmap path up to this many wedges (tip_opts.tune[1])
+constexpr int kApplyBatch = 4;             // (key, c) pairs a lane gathers before applying them
 
-// Key-tile size of the dense kernel for a side of n keys: about 64 tiles.
+// Counter width (bits) of the dense kernel for a vertex of degree d: c(u, w)
+// <= d_u must fit; 0 = too wide for the dense kernel.
+__host__ __device__ inline int dense_bits(int64_t d) {
+    return d <= 3 ? 2 : d <= 15 ? 4 : d <= 255 ? 8 : d <= 65535 ? 16 : 0;
+}
+__host__ __device__ inline int dense_bin(int bits) {
+    return bits == 2 ? kBinDense2 : bits == 4 ? kBinDense4 : bits == 8 ? kBinDense8 : kBinDense16;
+}
+
+// Granularity (keys) of the per-list tile-bound table for a side of n keys:
+// 16K keys, or coarser so that there are at most 512 tiles.
 inline int32_t dense_tile_keys(int64_t n) {
-    int64_t t = kMinTileKeys;
-    while (t < kMaxTileKeys && t * 64 < n) t <<= 1;
+    int64_t t = 16384;
+    while (t * 512 < n) t <<= 1;
     return (int32_t)t;
+}
+
+// Keys covered by one dense work item of a given counter width: the keys
+// whose counters fill kDenseLdsBytes, at least one table tile.
+inline int64_t dense_item_keys(int bits, int32_t tk) {
+    const int64_t k = (int64_t)kDenseLdsBytes * 8 / bits;
+    return std::max<int64_t>(tk, k / tk * tk);
 }
 
 // Fine-grained kernel (see fd.hip).

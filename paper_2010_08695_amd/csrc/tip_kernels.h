@@ -32,6 +32,7 @@ struct Ctl {
     unsigned long long big_wedges;   // workgroup peeling kernel only
     unsigned long long big_edges;
     unsigned long long big_pairs;
+    unsigned long long head[kBins];  // next work item of each update kernel in the current round
 };
 
 struct CountBuffers {
@@ -74,11 +75,17 @@ struct FdBuffers {
     int64_t* theta;      // [n_a] by rank
 };
 
+// Update-kernel selection thresholds (tip_opts.tune[0], tune[1]).
+struct Tune {
+    int64_t dense_div = kDefaultDenseDiv;
+    int64_t bitmap_max = kDefaultBitmapMax;
+};
+
 // counting
 void launch_count(const DevGraph& g, CountBuffers& cb, Ctl* ctl, const SpillArena& spill, int big_grid,
                   hipStream_t s);
 // CD
-void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers& pb, int64_t w_dense,
+void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers& pb, const Tune& tune,
                        hipStream_t s);
 void launch_range_start(PeelBuffers& pb, int cur_live, int32_t n_live, Ctl* ctl, hipStream_t s);
 void launch_select(PeelBuffers& pb, int cur_live, int32_t n_live, uint64_t max_supp, int64_t tgt, Ctl* ctl,

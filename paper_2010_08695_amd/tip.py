@@ -128,11 +128,14 @@ def _edges(g) -> tuple[Edges, tuple]:
     return e, (eu, ev)
 
 
-def _opts(P: int = 0, flags: int = 0, dense_threshold: int = 0) -> Opts:
+def _opts(P: int = 0, flags: int = 0, dense_threshold: int = 0, tune=None) -> Opts:
     o = Opts()
     o.P = int(P)
     o.flags = int(flags)
-    o.tune[0] = int(dense_threshold)
+    for i, t in enumerate(tune or ()):
+        o.tune[i] = int(t)
+    if dense_threshold:
+        o.tune[0] = int(dense_threshold)
     return o
 
 
@@ -148,15 +151,16 @@ def count_butterflies(g):
 
 
 def decompose(g, side: int = SIDE_U, P: int = 0, with_stats: bool = False, flags: int = 0,
-              dense_threshold: int = 0):
+              dense_threshold: int = 0, tune=None):
     """Tip numbers int64[n_side] of ``side``; with_stats adds a stats dict.
-    dense_threshold: tip_opts.tune[0] (0 = library default)."""
+    tune: tip_opts.tune values (0 = library default); dense_threshold is
+    tune[0]."""
     lib = load()
     e, keep = _edges(g)
     n = g.n_u if side == SIDE_U else g.n_v
     theta = np.zeros(max(n, 0), np.int64)
     st = Stats()
-    o = _opts(P, flags, dense_threshold)
+    o = _opts(P, flags, dense_threshold, tune)
     _check(lib, lib.tip_decompose(ctypes.byref(e), int(side), _ptr(theta), ctypes.byref(o), ctypes.byref(st)))
     return (theta, st.to_dict()) if with_stats else theta
 
@@ -213,7 +217,7 @@ def workspace_size(n_u: int, n_v: int, m: int, side: int = SIDE_U, P: int = 0) -
 
 
 def decompose_async(d_eu, d_ev, n_u: int, n_v: int, side: int, d_theta, workspace, stream=None,
-                    P: int = 0, flags: int = 0, dense_threshold: int = 0) -> dict:
+                    P: int = 0, flags: int = 0, dense_threshold: int = 0, tune=None) -> dict:
     """Device-resident decomposition.  d_eu/d_ev/d_theta/workspace are torch
     CUDA(HIP) tensors (only their device pointers are passed); stream is a
     torch.cuda.Stream or None for the current stream.  Returns the stats."""
@@ -228,7 +232,7 @@ def decompose_async(d_eu, d_ev, n_u: int, n_v: int, side: int, d_theta, workspac
         import torch
         s = torch.cuda.current_stream().cuda_stream
     st = Stats()
-    o = _opts(P, flags, dense_threshold)
+    o = _opts(P, flags, dense_threshold, tune)
     _check(lib, lib.tip_decompose_async(
         ctypes.c_void_p(d_eu.data_ptr()), ctypes.c_void_p(d_ev.data_ptr()), int(n_u), int(n_v), m, int(side),
         ctypes.c_void_p(d_theta.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
