@@ -7,6 +7,12 @@
 // raw support is exactly its butterflies with the other live vertices, so it
 // never underflows.
 //
+// Every live vertex starts a round with support >= the range's upper bound
+// (those below it form the round's activeSet), so the next activeSet is the
+// set of live vertices whose support is below the bound after the round: it
+// is found by one scan of the live list, and the update kernels decrement
+// without waiting for the atomics' old values.
+//
 // A peeled vertex u's update aggregates c(u, w) over its 2-hop neighbourhood
 // (Alg. 2, update).  Three kernels share the work by the size of that
 // neighbourhood (w[u], the wedges of u in the original graph):
@@ -20,6 +26,8 @@
 // All lists of the other side are sorted, so the part of N_v inside a key
 // tile is a contiguous run whose bounds come from a per-list table.
 #include "kern_util.h"
+
+#include <type_traits>
 
 namespace tip {
 namespace {
@@ -77,43 +85,43 @@ __device__ inline int32_t stage_units(Stage<NT>& S, int gs, int64_t s0, int32_t 
 
 // Every wave takes units in turn (k = wave, wave + NW, ...); a unit is read
 // with coalesced loads.  A wave's unit indices only grow, so the run holding
-// a unit is found by stepping forward from the previous one; two units are
-// loaded before either is consumed, so four loads per lane are in flight.
+// a unit is found by stepping forward from the previous one.  kUnitsInFlight
+// units are loaded before any is consumed, so 2 * kUnitsInFlight loads per
+// lane are in flight together.
 template <int NT>
 __device__ inline int advance_run(const Stage<NT>& S, int j, int gs, int32_t k) {
     while (j + 1 < gs && S.upre[j + 1] <= k) ++j;
     return j;
 }
 
+constexpr int kUnitsInFlight = 4;
+
 template <int NT, class F>
 __device__ inline void traverse_units(const Stage<NT>& S, int gs, int32_t nunits, const int32_t* __restrict__ adj,
                                       F&& f) {
     constexpr int NW = NT / kWave;
+    constexpr int R = kUnitsInFlight;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     int j = 0;
-    for (int32_t k = wid; k < nunits; k += 2 * NW) {
-        const int32_t k2 = k + NW;
-        j = advance_run(S, j, gs, k);
-        const int32_t off = (k - S.upre[j]) * kUnit;
-        const int32_t n = min(kUnit, S.len[j] - off);
-        const int32_t* p = adj + S.sbeg[j] + off;
-        int32_t n2 = 0;
-        const int32_t* p2 = p;
-        if (k2 < nunits) {
-            const int j2 = advance_run(S, j, gs, k2);
-            const int32_t off2 = (k2 - S.upre[j2]) * kUnit;
-            n2 = min(kUnit, S.len[j2] - off2);
-            p2 = adj + S.sbeg[j2] + off2;
-            j = j2;
+    for (int32_t k0 = wid; k0 < nunits; k0 += R * NW) {
+        int32_t x[2 * R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int32_t k = k0 + r * NW;
+            int32_t n = 0;
+            const int32_t* p = adj;
+            if (k < nunits) {
+                j = advance_run(S, j, gs, k);
+                const int32_t off = (k - S.upre[j]) * kUnit;
+                n = min(kUnit, S.len[j] - off);
+                p = adj + S.sbeg[j] + off;
+            }
+            x[2 * r] = lane < n ? p[lane] : -1;
+            x[2 * r + 1] = lane + kWave < n ? p[lane + kWave] : -1;
         }
-        const int32_t x0 = lane < n ? p[lane] : -1;
-        const int32_t x1 = lane + kWave < n ? p[lane + kWave] : -1;
-        const int32_t y0 = lane < n2 ? p2[lane] : -1;
-        const int32_t y1 = lane + kWave < n2 ? p2[lane + kWave] : -1;
-        if (x0 >= 0) f(x0);
-        if (x1 >= 0) f(x1);
-        if (y0 >= 0) f(y0);
-        if (y1 >= 0) f(y1);
+#pragma unroll
+        for (int r = 0; r < 2 * R; ++r)
+            if (x[r] >= 0) f(x[r]);
     }
 }
 
@@ -135,16 +143,26 @@ __global__ void k_wproxy(DevGraph g, const int32_t* __restrict__ deg_b, int64_t*
 // (a few percent of the wedges) fit its LDS table, i.e. up to bm_max wedges;
 // above that the dense kernel, unless its counter bytes (n_a * bits / 8,
 // bits from the degree so that c(u, w) <= d_u fits) are large against the
-// wedges (w <= n_a * bits / dense_div).
+// wedges (w <= n_a * bits / dense_div).  A dense vertex is heavy when a
+// light-sized item (item_keys[kind] keys) would hold more than kItemWedges
+// of its wedges.
+struct ItemKeys {
+    int64_t k[kDenseKinds];
+};
+
 __global__ void k_peel_bins(const int64_t* __restrict__ a_off, const int64_t* __restrict__ wprox, int32_t n_a,
-                            int64_t dense_div, int64_t bm_max, uint8_t* bin) {
+                            int64_t dense_div, int64_t bm_max, ItemKeys ik, uint8_t* bin) {
     GRID_STRIDE(u, (int64_t)n_a) {
         const int64_t w = wprox[u];
         const int64_t d = a_off[u + 1] - a_off[u];
         const int bits = dense_bits(d);
         uint8_t b = kBinBitmap;
-        if (w <= kSmallMaxWedges) b = kBinWave;
-        else if (bits && w > max<int64_t>(bm_max, (int64_t)n_a * bits / dense_div)) b = (uint8_t)dense_bin(bits);
+        if (w <= kSmallMaxWedges) {
+            b = kBinWave;
+        } else if (bits && w > max<int64_t>(bm_max, (int64_t)n_a * bits / dense_div)) {
+            const bool heavy = (double)w * (double)ik.k[dense_kind(bits)] > (double)kItemWedges * (double)n_a;
+            b = (uint8_t)dense_bin(bits, heavy);
+        }
         bin[u] = b;
     }
 }
@@ -285,9 +303,10 @@ __device__ inline void append_binned(bool pred, int32_t u, uint8_t b, const Fron
     for (int k = 0; k < kBins; ++k) wave_append(pred && b == k, u, f.list[k], &f.count[k]);
 }
 
-// First activeSet of a range: live vertices with support below the upper
-// bound.  They are assigned to the subset here; vertices with zero support
-// share no butterfly with any live vertex and need no update.
+// activeSet of a round: live vertices with support below the upper bound.
+// They are assigned to the subset here (before any of them is peeled);
+// vertices with zero support share no butterfly with any live vertex and
+// need no update.
 __global__ void k_frontier_init(const int32_t* __restrict__ live, int32_t n_live, const int64_t* __restrict__ supp,
                                 int32_t* state, const int64_t* __restrict__ wprox, const uint8_t* __restrict__ bin,
                                 long long hi, int32_t label, Fronts fr, Ctl* ctl) {
@@ -301,7 +320,7 @@ __global__ void k_frontier_init(const int32_t* __restrict__ live, int32_t n_live
         if (j < n_live) {
             u = live[j];
             const int64_t su = supp[u];
-            if (su < hi) {
+            if (su < hi && state[u] == kLive) {
                 state[u] = label;
                 ws += wprox[u];
                 if (su == 0) ++skipped;
@@ -344,80 +363,25 @@ struct PairBuf {
     }
 };
 
-// Appends the keys with cross[i] to the frontier list of their bin: one
-// wave-wide scan and one counter atomic per bin that receives any key.  Must
-// be reached by all lanes of the wave.
-template <int B>
-__device__ inline void append_many(const bool (&cross)[B], const int32_t (&key)[B], const uint8_t (&bn)[B],
-                                   const Fronts& f) {
-    bool any = false;
-#pragma unroll
-    for (int i = 0; i < B; ++i) any = any || cross[i];
-    if (!__ballot(any)) return;
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int k = 0; k < kBins; ++k) {
-        int c = 0;
-#pragma unroll
-        for (int i = 0; i < B; ++i) c += (cross[i] && bn[i] == k) ? 1 : 0;
-        if (!__ballot(c > 0)) continue;
-        int incl = c;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const int y = __shfl_up(incl, d, kWave);
-            if (lane >= d) incl += y;
-        }
-        const int tot = __shfl(incl, kWave - 1, kWave);
-        int base = 0;
-        if (lane == 0) base = atomicAdd(&f.count[k], tot);
-        int pos = __shfl(base, 0, kWave) + incl - c;
-#pragma unroll
-        for (int i = 0; i < B; ++i)
-            if (cross[i] && bn[i] == k) f.list[k][pos++] = key[i];
-    }
-}
-
-// Applies the decrement C(c, 2) of (peeled u, live w) pairs and appends w to
-// the next activeSet when its support crosses below the range's upper bound.
+// Applies the decrement C(c, 2) of (peeled u, w) pairs to the live w.
 struct CdApply {
     int64_t* supp;
     const int32_t* state;
-    const uint8_t* bin;
-    long long hi;
-    Fronts next;
 
     // Applies and empties the lane's buffered pairs (all with c >= 2).  The
-    // state loads of the whole batch are issued together, then its atomics,
-    // so a batch costs two memory round trips however many pairs it holds.
-    // Must be reached by all lanes of the wave.
+    // state loads of the whole batch are issued together; the decrements do
+    // not return a value, so nothing waits on them.
     template <int B>
     __device__ inline void flush(PairBuf<B>& pb, unsigned long long& pairs) const {
         int32_t st[B];
-        uint8_t bn[B];
 #pragma unroll
-        for (int i = 0; i < B; ++i) {
-            st[i] = 0;
-            bn[i] = 0;
-            if (i < pb.n) {
-                st[i] = state[pb.key[i]];
-                bn[i] = bin[pb.key[i]];
+        for (int i = 0; i < B; ++i) st[i] = i < pb.n ? state[pb.key[i]] : 0;
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            if (i < pb.n && st[i] == kLive) {
+                atomic_add_i64(&supp[pb.key[i]], -choose2(pb.cnt[i]));
+                ++pairs;
             }
-        }
-        int64_t old[B];
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-            old[i] = 0;
-            if (i < pb.n && st[i] == kLive) old[i] = atomic_add_i64_ret(&supp[pb.key[i]], -choose2(pb.cnt[i]));
-        }
-        bool cross[B];
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-            const bool live = i < pb.n && st[i] == kLive;
-            const int64_t dec = choose2(pb.cnt[i]);
-            cross[i] = live && old[i] >= hi && old[i] - dec < hi;
-            pairs += live ? 1 : 0;
-        }
-        append_many<B>(cross, pb.key, bn, next);
         pb.n = 0;
     }
 };
@@ -633,22 +597,23 @@ __device__ inline uint32_t ge2_mask(uint32_t x) {
     return (((t & 0x7fff7fffu) + 0x7fff7fffu) | t) & 0x80008000u;
 }
 
-// Dense path: work item k = (frontier vertex k / ng, table tiles
-// [G * (k % ng), G * (k % ng) + G)) with ng = ceil(ntt / G): one workgroup
-// counts the 2-hop keys of one vertex inside a key range of G * tk keys with
-// one BITS-bit LDS counter per key; the bins guarantee c(u, w) <= d_u fits.
-// LDS: G * tk * BITS / 8 counter bytes (dynamic) + staging.
+// Dense path: a work item is (frontier vertex, table tiles [t_begin, t_end)):
+// one workgroup counts the 2-hop keys of one vertex inside that key range
+// with one BITS-bit LDS counter per key; the bins guarantee c(u, w) <= d_u
+// fits.  Heavy vertices come first, in items of gh tiles, then light ones in
+// items of gl tiles (gh <= gl).  LDS: gl * tk * BITS / 8 counter bytes
+// (dynamic) + staging.
 template <int BITS>
 __global__ void __launch_bounds__(kDenseThreads)
-k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, int32_t G,
-             const int32_t* __restrict__ front, const int32_t* n_front_p, unsigned long long* head, CdApply ap,
-             Ctl* ctl) {
+k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, const int32_t* __restrict__ front_h,
+             const int32_t* n_h_p, int32_t gh, const int32_t* __restrict__ front_l, const int32_t* n_l_p, int32_t gl,
+             unsigned long long* head, CdApply ap, Ctl* ctl) {
     constexpr int NT = kDenseThreads;
     constexpr int PER_WORD = 32 / BITS;          // counters per 32-bit word
     constexpr uint32_t FMASK = BITS == 16 ? 0xffffu : ((1u << BITS) - 1);
     extern __shared__ __align__(16) uint32_t dyn[];
     uint32_t* cnt = dyn;
-    const int64_t max_keys = (int64_t)G * tk;
+    const int64_t max_keys = (int64_t)gl * tk;
     Stage<NT>& S = *reinterpret_cast<Stage<NT>*>(dyn + max_keys / PER_WORD);
     uint4* cnt4 = reinterpret_cast<uint4*>(cnt);
     const int tid = threadIdx.x;
@@ -657,15 +622,24 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
         for (int w = tid; w < n4; w += NT) cnt4[w] = make_uint4(0, 0, 0, 0);
     }
     __syncthreads();
-    const int32_t ng = (ntt + G - 1) / G;
-    const int64_t n_items = (int64_t)(*n_front_p) * ng;
+    const int32_t ngh = (ntt + gh - 1) / gh, ngl = (ntt + gl - 1) / gl;
+    const int64_t n_heavy_items = (int64_t)(*n_h_p) * ngh;
+    const int64_t n_items = n_heavy_items + (int64_t)(*n_l_p) * ngl;
     PeelCounters pc;
     for (;;) {
         const int64_t it = next_item(S, head);
         if (it >= n_items) break;
-        const int32_t u = front[it / ng];
-        const int32_t t_begin = (int32_t)(it % ng) * G;
-        const int32_t t_end = min(ntt, t_begin + G);
+        int32_t u, t_begin, t_end;
+        if (it < n_heavy_items) {
+            u = front_h[it / ngh];
+            t_begin = (int32_t)(it % ngh) * gh;
+            t_end = min(ntt, t_begin + gh);
+        } else {
+            const int64_t r = it - n_heavy_items;
+            u = front_l[r / ngl];
+            t_begin = (int32_t)(r % ngl) * gl;
+            t_end = min(ntt, t_begin + gl);
+        }
         if (ap.supp[u] == 0) {
             pc.skipped += (tid == 0 && t_begin == 0);
             continue;
@@ -699,7 +673,7 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
         // keys with c >= 2 are gathered per lane in registers and applied in
         // batches; counters are cleared as they are read
         const int32_t n4 = (int32_t)((int64_t)(t_end - t_begin) * tk / PER_WORD / 4);
-        PairBuf<kApplyBatch> pbuf;
+        PairBuf<kDenseBatch> pbuf;
         for (int32_t base = 0; base < n4; base += NT) {
             const int32_t w4 = base + tid;
             uint4 x = make_uint4(0, 0, 0, 0);
@@ -715,7 +689,7 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
             for (;;) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    while (msk[q] && pbuf.n < kApplyBatch) {
+                    while (msk[q] && pbuf.n < kDenseBatch) {
                         const int bit = __ffs(msk[q]) - 1;
                         msk[q] &= msk[q] - 1;
                         const int f = bit / BITS;
@@ -735,55 +709,34 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
 size_t dense_lds_bytes(int64_t keys, int bits) { return (size_t)(keys * bits / 8) + sizeof(Stage<kDenseThreads>); }
 
 template <int BITS>
-void launch_dense(const DevGraph& g, PeelBuffers& pb, int cur_front, int32_t n, CdApply ap, Ctl* ctl,
-                  hipStream_t s) {
+void launch_dense(const DevGraph& g, PeelBuffers& pb, int cur_front, int32_t n_light, int32_t n_heavy, CdApply ap,
+                  Ctl* ctl, hipStream_t s) {
     static int cus = 0;
     if (!cus) {
         int dev = 0;
         TIP_HIP_TRY(hipGetDevice(&dev));
         TIP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     }
-    const int bin = dense_bin(BITS);
+    const int bl = dense_bin(BITS, false), bh = dense_bin(BITS, true);
     // widest key range per item the LDS allows, narrowed while there would
     // be fewer than about four items per resident workgroup
-    const int32_t g_max = (int32_t)std::min<int64_t>(pb.ntt, dense_item_keys(BITS, pb.tk) / pb.tk);
+    const int32_t g_max = dense_item_tiles(BITS, pb.tk, pb.ntt);
     const size_t lds = dense_lds_bytes((int64_t)g_max * pb.tk, BITS);
     int occ = 0;
     TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel_dense<BITS>, kDenseThreads, lds));
     const int64_t slots = (int64_t)cus * std::max(1, occ);
-    int32_t G = g_max;
-    while (G > 1 && (int64_t)n * ((pb.ntt + G - 1) / G) < 4 * slots) G = (G + 1) / 2;
-    const int64_t items = (int64_t)n * ((pb.ntt + G - 1) / G);
-    const int grid = (int)std::min<int64_t>(items, slots);
-    k_peel_dense<BITS><<<grid, kDenseThreads, dense_lds_bytes((int64_t)G * pb.tk, BITS), s>>>(
-        g, pb.tb, pb.tk, pb.ntt, G, pb.front[cur_front][bin], &ctl->n_front[bin], &ctl->head[bin], ap, ctl);
+    auto items = [&](int32_t gl) {
+        const int32_t gh = std::max(1, gl / kHeavySplit);
+        return (int64_t)n_light * ((pb.ntt + gl - 1) / gl) + (int64_t)n_heavy * ((pb.ntt + gh - 1) / gh);
+    };
+    int32_t gl = g_max;
+    while (gl > 1 && items(gl) < 4 * slots) gl = (gl + 1) / 2;
+    const int32_t gh = std::max(1, gl / kHeavySplit);
+    const int grid = (int)std::min<int64_t>(items(gl), slots);
+    k_peel_dense<BITS><<<grid, kDenseThreads, dense_lds_bytes((int64_t)gl * pb.tk, BITS), s>>>(
+        g, pb.tb, pb.tk, pb.ntt, pb.front[cur_front][bh], &ctl->n_front[bh], gh, pb.front[cur_front][bl],
+        &ctl->n_front[bl], gl, &ctl->head[bl], ap, ctl);
     TIP_HIP_TRY(hipGetLastError());
-}
-
-// Vertices that crossed below the upper bound during the round become the
-// next activeSet: assign them to the subset before any of them is peeled.
-__global__ void k_round_end(Fronts nx, int32_t* state, const int64_t* __restrict__ wprox, int32_t label, Ctl* ctl) {
-    int64_t n[kBins], tot = 0;
-#pragma unroll
-    for (int b = 0; b < kBins; ++b) {
-        n[b] = nx.count[b];
-        tot += n[b];
-    }
-    long long ws = 0;
-    GRID_STRIDE(j, tot) {
-        int64_t r = j;
-        int b = 0;
-        while (r >= n[b]) {
-            r -= n[b];
-            ++b;
-        }
-        const int32_t u = nx.list[b][r];
-        state[u] = label;
-        ws += wprox[u];
-    }
-    ws = wave_sum_i64(ws);
-    if ((threadIdx.x & (kWave - 1)) == 0 && ws)
-        atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->w_range), (unsigned long long)ws);
 }
 
 __global__ void k_ctl_swap_front(Ctl* ctl) {
@@ -821,7 +774,10 @@ void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers
         TIP_HIP_TRY(hipGetLastError());
     }
     if (g.n_a > 0) {
-        k_peel_bins<<<grid1(g.n_a), kT, 0, s>>>(g.a_off, pb.wprox, g.n_a, tune.dense_div, tune.bitmap_max,
+        ItemKeys ik;
+        for (int k = 0; k < kDenseKinds; ++k)
+            ik.k[k] = (int64_t)dense_item_tiles(2 << k, pb.tk, pb.ntt) * pb.tk;
+        k_peel_bins<<<grid1(g.n_a), kT, 0, s>>>(g.a_off, pb.wprox, g.n_a, tune.dense_div, tune.bitmap_max, ik,
                                                 pb.bin);
         TIP_HIP_TRY(hipGetLastError());
     }
@@ -868,8 +824,7 @@ void launch_frontier_init(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t
 
 void launch_peel_round(const DevGraph& g, PeelBuffers& pb, int cur_front, const int32_t* n_cur, int64_t hi,
                        Ctl* ctl, const SpillArena& spill, int big_grid, hipStream_t s, hipEvent_t* ev_big) {
-    const int nxt = 1 - cur_front;
-    CdApply ap{pb.supp, pb.state, pb.bin, (long long)hi, fronts_of(pb, nxt, ctl->n_next)};
+    CdApply ap{pb.supp, pb.state};
     if (n_cur[kBinWave] > 0) {
         const int nw = kSmallThreads / kWave;
         const int64_t blocks = std::min<int64_t>((n_cur[kBinWave] + nw - 1) / nw, 8192);
@@ -886,18 +841,25 @@ void launch_peel_round(const DevGraph& g, PeelBuffers& pb, int cur_front, const 
                                                    &ctl->n_front[kBinBitmap], ap, spill, ctl);
         TIP_HIP_TRY(hipGetLastError());
     }
-    if (n_cur[kBinDense2] > 0) launch_dense<2>(g, pb, cur_front, n_cur[kBinDense2], ap, ctl, s);
-    if (n_cur[kBinDense4] > 0) launch_dense<4>(g, pb, cur_front, n_cur[kBinDense4], ap, ctl, s);
-    if (n_cur[kBinDense8] > 0) launch_dense<8>(g, pb, cur_front, n_cur[kBinDense8], ap, ctl, s);
-    if (n_cur[kBinDense16] > 0) launch_dense<16>(g, pb, cur_front, n_cur[kBinDense16], ap, ctl, s);
+    // heavier counter widths first: their vertices have the most wedges
+    const auto dense = [&](auto bits_tag) {
+        constexpr int BITS = decltype(bits_tag)::value;
+        const int32_t nl = n_cur[dense_bin(BITS, false)], nh = n_cur[dense_bin(BITS, true)];
+        if (nl + nh > 0) launch_dense<BITS>(g, pb, cur_front, nl, nh, ap, ctl, s);
+    };
+    dense(std::integral_constant<int, 16>{});
+    dense(std::integral_constant<int, 8>{});
+    dense(std::integral_constant<int, 4>{});
+    dense(std::integral_constant<int, 2>{});
     if (big && ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[1], s));
 }
 
-void launch_round_end(PeelBuffers& pb, int next_front, int32_t max_items, int32_t label, Ctl* ctl,
-                      hipStream_t s) {
-    if (max_items > 0) {
-        k_round_end<<<grid1(max_items, 4096), kT, 0, s>>>(fronts_of(pb, next_front, ctl->n_next), pb.state,
-                                                           pb.wprox, label, ctl);
+void launch_round_end(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi, int32_t label, int next_front,
+                      Ctl* ctl, hipStream_t s) {
+    if (n_live > 0) {
+        k_frontier_init<<<grid1(n_live, 4096), kT, 0, s>>>(pb.live[cur_live], n_live, pb.supp, pb.state, pb.wprox,
+                                                            pb.bin, (long long)hi, label,
+                                                            fronts_of(pb, next_front, ctl->n_next), ctl);
         TIP_HIP_TRY(hipGetLastError());
     }
     k_ctl_swap_front<<<1, 1, 0, s>>>(ctl);

@@ -304,7 +304,7 @@ tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int
                 for (int b = kBinBitmap; b < kBins; ++b) nb += n_cur[b];
                 launch_peel_round(g, pb, cur_front, n_cur, hi, w.ctl, w.spill, big_grid, s,
                                   time_kernels && nb > 0 ? kev.e : nullptr);
-                launch_round_end(pb, 1 - cur_front, n_live, label, w.ctl, s);
+                launch_round_end(pb, cur_live, n_live, hi, label, 1 - cur_front, w.ctl, s);
                 if (nb > 0) {
                     ++peel_launches;
                     if (time_kernels) {
@@ -312,9 +312,12 @@ tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int
                         const double ms = kev.ms(0, 1);
                         peel_ms += ms;
                         if (trace_rounds)
-                            std::fprintf(stderr, "tip-round range=%d round=%lld bins=%d,%d,%d,%d,%d,%d ms=%.4f\n",
-                                         label, (long long)rounds, n_cur[0], n_cur[1], n_cur[2], n_cur[3],
-                                         n_cur[4], n_cur[5], ms);
+                        {
+                            std::string bins;
+                            for (int b = 0; b < kBins; ++b) bins += (b ? "," : "") + std::to_string(n_cur[b]);
+                            std::fprintf(stderr, "tip-round range=%d round=%lld bins=%s ms=%.4f\n", label,
+                                         (long long)rounds, bins.c_str(), ms);
+                        }
                     }
                 }
                 cur_front ^= 1;

@@ -31,20 +31,26 @@ constexpr int kBmRep = 8192;               // bitmap-path repeat slots (64 KiB)
 constexpr int kUnit = 128;                 // consecutive list entries per traversal unit
 constexpr int kDenseThreads = 256;         // threads of the dense (vertex, key range) kernel
 constexpr int kDenseLdsBytes = 32768;      // counter bytes per dense workgroup (four per CU)
-constexpr int kBins = 6;
-constexpr int kBinWave = 0, kBinBitmap = 1, kBinDense2 = 2, kBinDense4 = 3, kBinDense8 = 4, kBinDense16 = 5;
+// Update bins: wave path, bitmap path, and the dense path per counter width
+// (2, 4, 8, 16 bits) split into light and heavy vertices; a heavy vertex is
+// cut into kHeavySplit times more (smaller) work items.
+constexpr int kDenseKinds = 4;
+constexpr int kBins = 2 + 2 * kDenseKinds;
+constexpr int kBinWave = 0, kBinBitmap = 1;
 constexpr int kDefaultDenseDiv = 64;       // dense needs w[u] > n * bits / div (tip_opts.tune[0])
 constexpr int64_t kDefaultBitmapMax = 32768;  // bitmap path up to this many wedges (tip_opts.tune[1])
 constexpr int kApplyBatch = 4;             // (key, c) pairs a lane gathers before applying them
+constexpr int kDenseBatch = 8;             // the same in the dense kernel
+constexpr int64_t kItemWedges = 16384;     // a dense item of a light vertex has at most about this many wedges
+constexpr int kHeavySplit = 8;
 
 // Counter width (bits) of the dense kernel for a vertex of degree d: c(u, w)
 // <= d_u must fit; 0 = too wide for the dense kernel.
 __host__ __device__ inline int dense_bits(int64_t d) {
     return d <= 3 ? 2 : d <= 15 ? 4 : d <= 255 ? 8 : d <= 65535 ? 16 : 0;
 }
-__host__ __device__ inline int dense_bin(int bits) {
-    return bits == 2 ? kBinDense2 : bits == 4 ? kBinDense4 : bits == 8 ? kBinDense8 : kBinDense16;
-}
+__host__ __device__ inline int dense_kind(int bits) { return bits == 2 ? 0 : bits == 4 ? 1 : bits == 8 ? 2 : 3; }
+__host__ __device__ inline int dense_bin(int bits, bool heavy) { return 2 + 2 * dense_kind(bits) + (heavy ? 1 : 0); }
 
 // Granularity (keys) of the per-list tile-bound table for a side of n keys:
 // 16K keys, or coarser so that there are at most 512 tiles.
@@ -54,11 +60,11 @@ inline int32_t dense_tile_keys(int64_t n) {
     return (int32_t)t;
 }
 
-// Keys covered by one dense work item of a given counter width: the keys
-// whose counters fill kDenseLdsBytes, at least one table tile.
-inline int64_t dense_item_keys(int bits, int32_t tk) {
+// Table tiles covered by one light dense work item of a given counter width:
+// the keys whose counters fill kDenseLdsBytes, at least one tile, at most all.
+inline int32_t dense_item_tiles(int bits, int32_t tk, int32_t ntt) {
     const int64_t k = (int64_t)kDenseLdsBytes * 8 / bits;
-    return std::max<int64_t>(tk, k / tk * tk);
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(ntt, k / tk));
 }
 
 // Fine-grained kernel (see fd.hip).

@@ -96,7 +96,10 @@ void launch_frontier_init(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t
 // events recorded around the workgroup update kernels.
 void launch_peel_round(const DevGraph& g, PeelBuffers& pb, int cur_front, const int32_t* n_cur, int64_t hi,
                        Ctl* ctl, const SpillArena& spill, int big_grid, hipStream_t s, hipEvent_t* ev_big);
-void launch_round_end(PeelBuffers& pb, int next_front, int32_t max_items, int32_t label, Ctl* ctl, hipStream_t s);
+// Next activeSet (live vertices now below hi) into buffer next_front, then
+// swaps the frontier buffers.
+void launch_round_end(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi, int32_t label, int next_front,
+                      Ctl* ctl, hipStream_t s);
 void launch_assign_live(PeelBuffers& pb, int cur_live, int32_t n_live, int32_t label, hipStream_t s);
 // FD
 void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl, const SpillArena& spill,
