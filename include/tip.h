@@ -59,6 +59,16 @@ typedef struct {
  * call's stream and report it in tip_stats.peel_*. */
 #define TIP_FLAG_TIME_KERNELS 1
 
+/* TIP_FLAG_NO_GRAPH: launch every coarse-grained round from the host
+ * instead of replaying a HIP graph of several rounds (same results; for
+ * testing and comparison).  TIP_FLAG_TIME_KERNELS implies it. */
+#define TIP_FLAG_NO_GRAPH 2
+
+/* TIP_FLAG_BATCH_PLAIN: tip_decompose_batch runs one full decomposition
+ * after another (the plain per-graph launch sequence) instead of the batched
+ * form; same results, for comparison. */
+#define TIP_FLAG_BATCH_PLAIN 4
+
 /* Options.  Zero-initialised means defaults. */
 typedef struct {
     int32_t P;       /* number of tip-number ranges of the coarse-grained step
@@ -118,7 +128,14 @@ tip_status tip_decompose_ex(const tip_edges* g, int32_t side, int64_t* theta, co
                             int32_t* n_subsets);
 
 /* Decomposes n independent graphs: graph k's side sides[k] into thetas[k].
- * st may be NULL or point to n entries. */
+ * st may be NULL or point to n entries.  Batched form (default): the
+ * graphs' counting and coarse-grained steps run concurrently on several
+ * streams, then the fine-grained subsets of ALL graphs are peeled in one
+ * persistent launch that takes (graph, subset) tasks from one queue ordered
+ * by induced wedges (the workload-aware schedule of the Parallelization
+ * Strategy section, applied across graphs).  Device memory for all graphs is
+ * held until the call returns.  TIP_FLAG_BATCH_PLAIN runs the graphs one
+ * after another instead.  Results are identical either way. */
 tip_status tip_decompose_batch(int32_t n, const tip_edges* gs, const int32_t* sides, int64_t* const* thetas,
                                const tip_opts* opt, tip_stats* st);
 

@@ -183,7 +183,7 @@ __device__ inline void fd_rep_insert(FdLds& L, const Spill& sp, uint32_t k) {
 // ones one per wavefront with a private hash table, heavy ones one at a time
 // with the whole workgroup and a key bitmap.
 __global__ void __launch_bounds__(kFdThreads)
-k_fd_peel(DevGraph g, FdBuffers fb, const int64_t* __restrict__ init, int32_t S, SpillArena spa, Ctl* ctl) {
+k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, int32_t* head, SpillArena spa) {
     __shared__ FdLds L;
     constexpr int NT = kFdThreads;
     constexpr int NW = NT / kWave;
@@ -195,18 +195,24 @@ k_fd_peel(DevGraph g, FdBuffers fb, const int64_t* __restrict__ init, int32_t S,
     if (tid == 0) L.spill_n = 0;
     __syncthreads();
     const Spill sp{spa.dense + (int64_t)blockIdx.x * spa.stride, spa.list + (int64_t)blockIdx.x * spa.stride};
-    unsigned long long wedges = 0, pairs = 0, levels = 0, spills = 0;
     unsigned long long* tab = L.u.wtab[wid];
     for (;;) {
-        if (tid == 0) L.flag = atomicAdd(&ctl->fd_head, 1);
+        if (tid == 0) L.flag = atomicAdd(head, 1);
         __syncthreads();
         const int32_t t = L.flag;
         __syncthreads();
-        if (t >= S) break;
-        const int32_t sub = fb.order[t];
+        if (t >= n_tasks) break;
+        // one task = one subset of one graph: tasks[t] = job << 32 | subset,
+        // or, for a single graph, its own workload-ordered subset list
+        const FdJob& J = tasks ? jobs.list[tasks[t] >> 32] : jobs.one;
+        const DevGraph& g = J.g;
+        const FdBuffers& fb = J.fb;
+        const int64_t* __restrict__ init = J.init;
+        const int32_t sub = tasks ? (int32_t)(tasks[t] & 0xffffffffll) : fb.order[t];
         const int64_t P0 = fb.sub_off[sub];
         const int32_t n_i = (int32_t)(fb.sub_off[sub + 1] - P0);
         if (n_i == 0) continue;
+        unsigned long long wedges = 0, pairs = 0, levels = 0, spills = 0;
         int32_t* lc = fb.lst[0] + P0;
         int32_t* ln = fb.lst[1] + P0;
         int32_t* pl = fb.lst[2] + P0;
@@ -401,16 +407,16 @@ k_fd_peel(DevGraph g, FdBuffers fb, const int64_t* __restrict__ init, int32_t S,
             ln = tmp;
             n_live = n_keep;
         }
-    }
-    wedges = (unsigned long long)wave_sum_i64((int64_t)wedges);
-    pairs = (unsigned long long)wave_sum_i64((int64_t)pairs);
-    levels = (unsigned long long)wave_sum_i64((int64_t)levels);
-    spills = (unsigned long long)wave_sum_i64((int64_t)spills);
-    if (lane == 0) {
-        if (wedges) atomicAdd(&ctl->wedges_fd, wedges);
-        if (pairs) atomicAdd(&ctl->pair_updates, pairs);
-        if (levels) atomicAdd(&ctl->fd_levels, levels);
-        if (spills) atomicAdd(&ctl->spills, spills);
+        wedges = (unsigned long long)wave_sum_i64((int64_t)wedges);
+        pairs = (unsigned long long)wave_sum_i64((int64_t)pairs);
+        levels = (unsigned long long)wave_sum_i64((int64_t)levels);
+        spills = (unsigned long long)wave_sum_i64((int64_t)spills);
+        if (lane == 0) {
+            if (wedges) atomicAdd(&J.ctl->wedges_fd, wedges);
+            if (pairs) atomicAdd(&J.ctl->pair_updates, pairs);
+            if (levels) atomicAdd(&J.ctl->fd_levels, levels);
+            if (spills) atomicAdd(&J.ctl->spills, spills);
+        }
     }
 }
 
@@ -427,10 +433,11 @@ int fd_occupancy() {
     return std::max(1, n);
 }
 
-void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl, const SpillArena& spill,
-               int big_grid, uint64_t* tmp_keys, int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp,
-               uint64_t* keys_scratch, int32_t* vals_scratch, hipStream_t s) {
+void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, uint64_t* tmp_keys,
+                     int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp, uint64_t* keys_scratch,
+                     int32_t* vals_scratch, hipStream_t s) {
     const int32_t n_a = g.n_a;
+    fill_i64(fb.task_w, 0, S, s);
     if (n_a <= 0) return;
     // vertices grouped by subset, ascending rank inside each subset
     fill_i64(fb.sub_cnt, 0, (int64_t)S + 1, s);
@@ -440,7 +447,6 @@ void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl
     scan_exclusive_i64(fb.sub_cnt, fb.sub_off, (int64_t)S + 1, scan_tmp, s);
     k_fd_positions<<<grid1(n_a), kT, 0, s>>>(fb.fd_vert, n_a, fb.fd_pos);
     TIP_HIP_TRY(hipGetLastError());
-    fill_i64(fb.task_w, 0, S, s);
     fill_i64(fb.fd_w, 0, n_a, s);
     if (g.m > 0) {
         k_fd_csc_keys<<<grid1(g.m), kT, 0, s>>>(g, pb.state, fb.fd_pos, fb.sub_off, S, fb.pkeys, fb.pcsc);
@@ -453,10 +459,30 @@ void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl
     }
     k_fd_order<<<1, 1024, 0, s>>>(fb.task_w, S, fb.order);
     TIP_HIP_TRY(hipGetLastError());
+}
+
+void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl, const SpillArena& spill,
+               int big_grid, uint64_t* tmp_keys, int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp,
+               uint64_t* keys_scratch, int32_t* vals_scratch, hipStream_t s) {
+    if (g.n_a <= 0) return;
+    launch_fd_setup(g, pb, fb, S, tmp_keys, tmp_vals, hist, scan_tmp, keys_scratch, vals_scratch, s);
     k_fd_reset_head<<<1, 1, 0, s>>>(ctl);
     TIP_HIP_TRY(hipGetLastError());
+    FdJobs jobs{};
+    jobs.one = FdJob{g, fb, pb.init, ctl};
     const int grid = std::max(1, std::min<int>(S, big_grid));
-    k_fd_peel<<<grid, kFdThreads, 0, s>>>(g, fb, pb.init, S, spill, ctl);
+    k_fd_peel<<<grid, kFdThreads, 0, s>>>(jobs, nullptr, S, &ctl->fd_head, spill);
+    TIP_HIP_TRY(hipGetLastError());
+}
+
+void launch_fd_batch(const FdJob* d_jobs, const int64_t* d_tasks, int32_t n_tasks, int32_t* d_head,
+                     const SpillArena& spill, int big_grid, hipStream_t s) {
+    if (n_tasks <= 0) return;
+    fill_i32(d_head, 0, 1, s);
+    FdJobs jobs{};
+    jobs.list = d_jobs;
+    const int grid = std::max(1, std::min<int>(n_tasks, big_grid));
+    k_fd_peel<<<grid, kFdThreads, 0, s>>>(jobs, d_tasks, n_tasks, d_head, spill);
     TIP_HIP_TRY(hipGetLastError());
 }
 

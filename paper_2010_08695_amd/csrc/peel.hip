@@ -297,19 +297,41 @@ struct Fronts {
     int32_t* count;  // [kBins]
 };
 
+// Both frontier buffers; kernels pick the current one from the control block.
+struct FrontSet {
+    int32_t* list[2][kBins];
+};
+
 // Appends u to the frontier list of its bin; all lanes of the wave must call.
 __device__ inline void append_binned(bool pred, int32_t u, uint8_t b, const Fronts& f) {
 #pragma unroll
     for (int k = 0; k < kBins; ++k) wave_append(pred && b == k, u, f.list[k], &f.count[k]);
 }
 
-// activeSet of a round: live vertices with support below the upper bound.
-// They are assigned to the subset here (before any of them is peeled);
-// vertices with zero support share no butterfly with any live vertex and
-// need no update.
-__global__ void k_frontier_init(const int32_t* __restrict__ live, int32_t n_live, const int64_t* __restrict__ supp,
-                                int32_t* state, const int64_t* __restrict__ wprox, const uint8_t* __restrict__ bin,
-                                long long hi, int32_t label, Fronts fr, Ctl* ctl) {
+// activeSet of a round: live vertices with support below the range's upper
+// bound.  They are assigned to the subset here (before any of them is
+// peeled); vertices with zero support share no butterfly with any live
+// vertex and need no update.  next = 0: the range's first activeSet, into
+// the current buffer; next = 1: after a round, into the other buffer (and
+// nothing to do when the round's activeSet was empty).
+__global__ void k_frontier_scan(FrontSet fs, const int32_t* live0, const int32_t* live1,
+                                const int64_t* __restrict__ supp, int32_t* state, const int64_t* __restrict__ wprox,
+                                const uint8_t* __restrict__ bin, int next, Ctl* ctl) {
+    if (next) {
+        int32_t any = 0;
+#pragma unroll
+        for (int b = 0; b < kBins; ++b) any |= ctl->n_front[b];
+        if (!any) return;
+    }
+    const int32_t* __restrict__ live = ctl->range_live ? live1 : live0;
+    const int32_t n_live = ctl->range_n_live;
+    const long long hi = ctl->range_hi;
+    const int32_t label = ctl->range_label;
+    const int buf = next ? 1 - ctl->front_buf : ctl->front_buf;
+    Fronts fr;
+#pragma unroll
+    for (int b = 0; b < kBins; ++b) fr.list[b] = fs.list[buf][b];
+    fr.count = next ? ctl->n_next : ctl->n_front;
     long long ws = 0;
     unsigned long long skipped = 0;
     UNIFORM_STRIDE(base, (int64_t)n_live) {
@@ -338,6 +360,15 @@ __global__ void k_frontier_init(const int32_t* __restrict__ live, int32_t n_live
         if (ws) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->w_range), (unsigned long long)ws);
         if (skipped) atomicAdd(&ctl->skipped, skipped);
     }
+}
+
+__global__ void k_set_range(Ctl* ctl, long long hi, int32_t label, int32_t live, int32_t n_live) {
+    ctl->range_hi = hi;
+    ctl->range_label = label;
+    ctl->range_live = live;
+    ctl->range_n_live = n_live;
+    ctl->front_buf = 0;
+    for (int b = 0; b < kBins; ++b) ctl->n_front[b] = ctl->n_next[b] = ctl->head[b] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -412,14 +443,15 @@ struct PeelCounters {
 // Wave path: one wavefront per vertex, every 2-hop key in a per-wave LDS hash
 // table sized to the vertex's wedge count.
 __global__ void __launch_bounds__(kSmallThreads)
-k_peel_wave(DevGraph g, const int32_t* __restrict__ front, const int32_t* n_front_p, const int64_t* __restrict__ wprox,
-            CdApply ap, Ctl* ctl) {
+k_peel_wave(DevGraph g, FrontSet fs, const int64_t* __restrict__ wprox, CdApply ap, Ctl* ctl) {
+    const int64_t n_front = ctl->n_front[kBinWave];
+    if (n_front == 0) return;
+    const int32_t* __restrict__ front = fs.list[ctl->front_buf][kBinWave];
     __shared__ WaveLds WL[kSmallThreads / kWave];
     const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     WaveLds& W = WL[wid];
     for (int s = lane; s < kSmallSlots; s += kWave) W.tab[s] = 0;
     wave_sync();
-    const int64_t n_front = *n_front_p;
     const int nw = kSmallThreads / kWave;
     PeelCounters pc;
     for (int64_t it = (int64_t)blockIdx.x * nw + wid; it < n_front; it += (int64_t)gridDim.x * nw) {
@@ -496,8 +528,11 @@ __device__ inline void bm_rep_insert(BmLds& L, const Spill& sp, uint32_t k) {
 }
 
 __global__ void __launch_bounds__(kBigThreads)
-k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, const int32_t* __restrict__ front,
-              const int32_t* n_front_p, CdApply ap, SpillArena spa, Ctl* ctl) {
+k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, FrontSet fs, CdApply ap,
+              SpillArena spa, Ctl* ctl) {
+    const int64_t n_front = ctl->n_front[kBinBitmap];
+    if (n_front == 0) return;
+    const int32_t* __restrict__ front = fs.list[ctl->front_buf][kBinBitmap];
     __shared__ BmLds L;
     constexpr int NT = kBigThreads;
     constexpr int kPer = kBmRep / NT;  // repeat slots scanned by each thread
@@ -508,7 +543,6 @@ k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t nt
     if (tid == 0) L.spill_n = 0;
     __syncthreads();
     const Spill sp{spa.dense + (int64_t)blockIdx.x * spa.stride, spa.list + (int64_t)blockIdx.x * spa.stride};
-    const int64_t n_front = *n_front_p;
     const int32_t sub = kBmTile / tk;  // table tiles per bitmap tile
     PeelCounters pc;
     for (;;) {
@@ -605,12 +639,27 @@ __device__ inline uint32_t ge2_mask(uint32_t x) {
 // (dynamic) + staging.
 template <int BITS>
 __global__ void __launch_bounds__(kDenseThreads)
-k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, const int32_t* __restrict__ front_h,
-             const int32_t* n_h_p, int32_t gh, const int32_t* __restrict__ front_l, const int32_t* n_l_p, int32_t gl,
-             unsigned long long* head, CdApply ap, Ctl* ctl) {
+k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, FrontSet fs, int32_t g_max,
+             int64_t slots, CdApply ap, Ctl* ctl) {
     constexpr int NT = kDenseThreads;
     constexpr int PER_WORD = 32 / BITS;          // counters per 32-bit word
     constexpr uint32_t FMASK = BITS == 16 ? 0xffffu : ((1u << BITS) - 1);
+    constexpr int BL = 2 + 2 * (BITS == 2 ? 0 : BITS == 4 ? 1 : BITS == 8 ? 2 : 3), BH = BL + 1;
+    const int32_t n_l = ctl->n_front[BL], n_h = ctl->n_front[BH];
+    if (n_l + n_h == 0) return;
+    const int32_t* __restrict__ front_l = fs.list[ctl->front_buf][BL];
+    const int32_t* __restrict__ front_h = fs.list[ctl->front_buf][BH];
+    // light items span gl tiles, heavy ones gh = gl / kHeavySplit; gl is
+    // narrowed from g_max while there would be fewer than about four items
+    // per resident workgroup
+    const auto n_items_of = [&](int32_t l) {
+        const int32_t h = max(1, l / kHeavySplit);
+        return (int64_t)n_l * ((ntt + l - 1) / l) + (int64_t)n_h * ((ntt + h - 1) / h);
+    };
+    int32_t gl = g_max;
+    while (gl > 1 && n_items_of(gl) < 4 * slots) gl = (gl + 1) / 2;
+    const int32_t gh = max(1, gl / kHeavySplit);
+    unsigned long long* head = &ctl->head[BL];
     extern __shared__ __align__(16) uint32_t dyn[];
     uint32_t* cnt = dyn;
     const int64_t max_keys = (int64_t)gl * tk;
@@ -623,8 +672,8 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
     }
     __syncthreads();
     const int32_t ngh = (ntt + gh - 1) / gh, ngl = (ntt + gl - 1) / gl;
-    const int64_t n_heavy_items = (int64_t)(*n_h_p) * ngh;
-    const int64_t n_items = n_heavy_items + (int64_t)(*n_l_p) * ngl;
+    const int64_t n_heavy_items = (int64_t)n_h * ngh;
+    const int64_t n_items = n_heavy_items + (int64_t)n_l * ngl;
     PeelCounters pc;
     for (;;) {
         const int64_t it = next_item(S, head);
@@ -709,41 +758,31 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
 size_t dense_lds_bytes(int64_t keys, int bits) { return (size_t)(keys * bits / 8) + sizeof(Stage<kDenseThreads>); }
 
 template <int BITS>
-void launch_dense(const DevGraph& g, PeelBuffers& pb, int cur_front, int32_t n_light, int32_t n_heavy, CdApply ap,
-                  Ctl* ctl, hipStream_t s) {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        TIP_HIP_TRY(hipGetDevice(&dev));
-        TIP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    }
-    const int bl = dense_bin(BITS, false), bh = dense_bin(BITS, true);
-    // widest key range per item the LDS allows, narrowed while there would
-    // be fewer than about four items per resident workgroup
+void launch_dense(const DevGraph& g, PeelBuffers& pb, const FrontSet& fs, CdApply ap, Ctl* ctl, hipStream_t s) {
+    int dev = 0, cus = 0;
+    TIP_HIP_TRY(hipGetDevice(&dev));
+    TIP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const int32_t g_max = dense_item_tiles(BITS, pb.tk, pb.ntt);
     const size_t lds = dense_lds_bytes((int64_t)g_max * pb.tk, BITS);
     int occ = 0;
     TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel_dense<BITS>, kDenseThreads, lds));
     const int64_t slots = (int64_t)cus * std::max(1, occ);
-    auto items = [&](int32_t gl) {
-        const int32_t gh = std::max(1, gl / kHeavySplit);
-        return (int64_t)n_light * ((pb.ntt + gl - 1) / gl) + (int64_t)n_heavy * ((pb.ntt + gh - 1) / gh);
-    };
-    int32_t gl = g_max;
-    while (gl > 1 && items(gl) < 4 * slots) gl = (gl + 1) / 2;
-    const int32_t gh = std::max(1, gl / kHeavySplit);
-    const int grid = (int)std::min<int64_t>(items(gl), slots);
-    k_peel_dense<BITS><<<grid, kDenseThreads, dense_lds_bytes((int64_t)gl * pb.tk, BITS), s>>>(
-        g, pb.tb, pb.tk, pb.ntt, pb.front[cur_front][bh], &ctl->n_front[bh], gh, pb.front[cur_front][bl],
-        &ctl->n_front[bl], gl, &ctl->head[bl], ap, ctl);
+    k_peel_dense<BITS><<<(unsigned)slots, kDenseThreads, lds, s>>>(g, pb.tb, pb.tk, pb.ntt, fs, g_max, slots, ap,
+                                                                  ctl);
     TIP_HIP_TRY(hipGetLastError());
 }
 
 __global__ void k_ctl_swap_front(Ctl* ctl) {
+    int32_t any = 0;
     for (int b = 0; b < kBins; ++b) {
+        any |= ctl->n_front[b];
         ctl->n_front[b] = ctl->n_next[b];
         ctl->n_next[b] = 0;
         ctl->head[b] = 0;
+    }
+    if (any) {
+        ++ctl->rounds_done;
+        ctl->front_buf ^= 1;
     }
 }
 
@@ -751,10 +790,10 @@ __global__ void k_assign_live(const int32_t* __restrict__ live, int32_t n_live, 
     GRID_STRIDE(j, (int64_t)n_live) state[live[j]] = label;
 }
 
-Fronts fronts_of(PeelBuffers& pb, int buf, int32_t* counts) {
-    Fronts f;
-    for (int b = 0; b < kBins; ++b) f.list[b] = pb.front[buf][b];
-    f.count = counts;
+FrontSet front_set(PeelBuffers& pb) {
+    FrontSet f;
+    for (int i = 0; i < 2; ++i)
+        for (int b = 0; b < kBins; ++b) f.list[i][b] = pb.front[i][b];
     return f;
 }
 
@@ -769,6 +808,8 @@ int peel_occupancy() {
 void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers& pb, const Tune& tune,
                        hipStream_t s) {
     fill_i64(pb.wprox, 0, g.n_a, s);
+    // the select histogram is cleared after every use, so it starts cleared
+    fill_i64(pb.sel_hist, 0, 256, s);
     if (g.m > 0) {
         k_wproxy<<<grid1(g.m), kT, 0, s>>>(g, deg_b_rank, pb.wprox);
         TIP_HIP_TRY(hipGetLastError());
@@ -813,55 +854,38 @@ void launch_select(PeelBuffers& pb, int cur_live, int32_t n_live, uint64_t max_s
     }
 }
 
-void launch_frontier_init(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi, int32_t label, int cur_front,
-                          Ctl* ctl, hipStream_t s) {
+void launch_range_begin(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi, int32_t label, Ctl* ctl,
+                        hipStream_t s) {
+    k_set_range<<<1, 1, 0, s>>>(ctl, (long long)hi, label, cur_live, n_live);
+    TIP_HIP_TRY(hipGetLastError());
     if (n_live <= 0) return;
-    k_frontier_init<<<grid1(n_live, 4096), kT, 0, s>>>(pb.live[cur_live], n_live, pb.supp, pb.state, pb.wprox,
-                                                        pb.bin, (long long)hi, label,
-                                                        fronts_of(pb, cur_front, ctl->n_front), ctl);
+    k_frontier_scan<<<grid1(n_live, 4096), kT, 0, s>>>(front_set(pb), pb.live[0], pb.live[1], pb.supp, pb.state,
+                                                        pb.wprox, pb.bin, 0, ctl);
     TIP_HIP_TRY(hipGetLastError());
 }
 
-void launch_peel_round(const DevGraph& g, PeelBuffers& pb, int cur_front, const int32_t* n_cur, int64_t hi,
-                       Ctl* ctl, const SpillArena& spill, int big_grid, hipStream_t s, hipEvent_t* ev_big) {
-    CdApply ap{pb.supp, pb.state};
-    if (n_cur[kBinWave] > 0) {
-        const int nw = kSmallThreads / kWave;
-        const int64_t blocks = std::min<int64_t>((n_cur[kBinWave] + nw - 1) / nw, 8192);
-        k_peel_wave<<<(unsigned)blocks, kSmallThreads, 0, s>>>(g, pb.front[cur_front][kBinWave],
-                                                               &ctl->n_front[kBinWave], pb.wprox, ap, ctl);
-        TIP_HIP_TRY(hipGetLastError());
-    }
-    bool big = false;
-    for (int b = kBinBitmap; b < kBins; ++b) big = big || n_cur[b] > 0;
-    if (big && ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[0], s));
-    if (n_cur[kBinBitmap] > 0) {
-        const int grid = (int)std::min<int64_t>(n_cur[kBinBitmap], std::min(big_grid, spill.slots));
-        k_peel_bitmap<<<grid, kBigThreads, 0, s>>>(g, pb.tb, pb.tk, pb.ntt, pb.front[cur_front][kBinBitmap],
-                                                   &ctl->n_front[kBinBitmap], ap, spill, ctl);
-        TIP_HIP_TRY(hipGetLastError());
-    }
+void launch_round(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena& spill, int big_grid,
+                  hipStream_t s, hipEvent_t* ev_big) {
+    const CdApply ap{pb.supp, pb.state};
+    const FrontSet fs = front_set(pb);
+    if (g.n_a <= 0) return;
+    // grids are fixed; every kernel reads its work from the control block and
+    // returns at once when it has none
+    k_peel_wave<<<2048, kSmallThreads, 0, s>>>(g, fs, pb.wprox, ap, ctl);
+    TIP_HIP_TRY(hipGetLastError());
+    if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[0], s));
+    k_peel_bitmap<<<std::min(big_grid, spill.slots), kBigThreads, 0, s>>>(g, pb.tb, pb.tk, pb.ntt, fs, ap, spill,
+                                                                           ctl);
+    TIP_HIP_TRY(hipGetLastError());
     // heavier counter widths first: their vertices have the most wedges
-    const auto dense = [&](auto bits_tag) {
-        constexpr int BITS = decltype(bits_tag)::value;
-        const int32_t nl = n_cur[dense_bin(BITS, false)], nh = n_cur[dense_bin(BITS, true)];
-        if (nl + nh > 0) launch_dense<BITS>(g, pb, cur_front, nl, nh, ap, ctl, s);
-    };
-    dense(std::integral_constant<int, 16>{});
-    dense(std::integral_constant<int, 8>{});
-    dense(std::integral_constant<int, 4>{});
-    dense(std::integral_constant<int, 2>{});
-    if (big && ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[1], s));
-}
-
-void launch_round_end(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi, int32_t label, int next_front,
-                      Ctl* ctl, hipStream_t s) {
-    if (n_live > 0) {
-        k_frontier_init<<<grid1(n_live, 4096), kT, 0, s>>>(pb.live[cur_live], n_live, pb.supp, pb.state, pb.wprox,
-                                                            pb.bin, (long long)hi, label,
-                                                            fronts_of(pb, next_front, ctl->n_next), ctl);
-        TIP_HIP_TRY(hipGetLastError());
-    }
+    launch_dense<16>(g, pb, fs, ap, ctl, s);
+    launch_dense<8>(g, pb, fs, ap, ctl, s);
+    launch_dense<4>(g, pb, fs, ap, ctl, s);
+    launch_dense<2>(g, pb, fs, ap, ctl, s);
+    if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[1], s));
+    k_frontier_scan<<<grid1(g.n_a, 4096), kT, 0, s>>>(fs, pb.live[0], pb.live[1], pb.supp, pb.state, pb.wprox,
+                                                       pb.bin, 1, ctl);
+    TIP_HIP_TRY(hipGetLastError());
     k_ctl_swap_front<<<1, 1, 0, s>>>(ctl);
     TIP_HIP_TRY(hipGetLastError());
 }

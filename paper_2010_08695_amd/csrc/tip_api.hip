@@ -4,8 +4,11 @@
 // sequences launches and reads a small control block between CD rounds.
 #include <cmath>
 #include <cstdlib>
+#include <atomic>
 #include <cstring>
+#include <memory>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "../../include/tip.h"
@@ -104,14 +107,21 @@ void plan(Arena& ar, int32_t n_a, int32_t n_b, int64_t m, int32_t P, int slots, 
 }
 
 // Pinned host mirror of the control block, one per host thread.
+struct PinnedCtl {
+    Ctl* h = nullptr;
+    ~PinnedCtl() {
+        if (h) (void)hipHostFree(h);
+    }
+};
+
 Ctl* host_ctl() {
-    thread_local Ctl* h = nullptr;
-    if (!h) {
+    thread_local PinnedCtl pc;
+    if (!pc.h) {
         void* p = nullptr;
         TIP_HIP_TRY(hipHostMalloc(&p, sizeof(Ctl), hipHostMallocDefault));
-        h = static_cast<Ctl*>(p);
+        pc.h = static_cast<Ctl*>(p);
     }
-    return h;
+    return pc.h;
 }
 
 const Ctl& read_ctl(const Work& w, hipStream_t s) {
@@ -120,6 +130,39 @@ const Ctl& read_ctl(const Work& w, hipStream_t s) {
     TIP_HIP_TRY(hipStreamSynchronize(s));
     return *h;
 }
+
+// K coarse-grained rounds captured once into a HIP graph and replayed; the
+// rounds take all their state from the device control block, and rounds
+// past the end of a range do nothing, so the host reads one flag per replay
+// instead of one per round.
+constexpr int kRoundsPerGraph = 4;
+
+struct RoundGraph {
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    void build(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena& spill, int big_grid) {
+        TIP_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        TIP_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < kRoundsPerGraph; ++k) launch_round(g, pb, ctl, spill, big_grid, cs, nullptr);
+        TIP_HIP_TRY(hipStreamEndCapture(cs, &graph));
+        TIP_HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    ~RoundGraph() {
+        if (cs) {
+            hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(cs, &st) == hipSuccess && st == hipStreamCaptureStatusActive) {
+                hipGraph_t partial = nullptr;
+                if (hipStreamEndCapture(cs, &partial) == hipSuccess && partial) (void)hipGraphDestroy(partial);
+            }
+            (void)hipGetLastError();
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+};
 
 struct Events {
     hipEvent_t e[6] = {};
@@ -220,11 +263,25 @@ __global__ void k_scatter_i32(const int32_t* by_rank, const int32_t* orig, int32
 
 // Ingest + count (+ CD + FD when decomposing).  Returns TIP_OK or an error
 // status (EINVAL for out-of-range ids found on the device).
-tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int32_t n_b, int64_t m, bool a_is_u,
-               int32_t P, int32_t flags, const Tune& tune, bool decompose, RunOut& out, tip_stats* st,
-               hipStream_t s) {
+// State carried from the first part of a run (ingest, count, CD, FD set-up
+// or all of FD) to the second (outputs and statistics).
+struct RunState {
     Events ev;
-    Events kev;  // [0], [1]: around one workgroup peeling launch
+    Events kev;  // [0], [1]: around the workgroup update kernels of one round
+    double peel_ms = 0.0;
+    int64_t peel_launches = 0;
+    int32_t S = 0;
+    std::vector<int64_t> bounds;
+};
+
+// fd_inline = false stops after the set-up of FD (Alg. 4): the caller then
+// peels the subsets, possibly together with other graphs', and calls
+// run_back.
+tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int32_t n_b, int64_t m,
+                     bool a_is_u, int32_t P, int32_t flags, const Tune& tune, bool decompose, bool fd_inline,
+                     RunState& rs, hipStream_t s) {
+    Events& ev = rs.ev;
+    Events& kev = rs.kev;
     const bool time_kernels = (flags & TIP_FLAG_TIME_KERNELS) != 0;
     // diagnostic: with kernel timing on, TIP_TRACE_ROUNDS=1 prints every
     // coarse-grained round's frontier sizes and update time to stderr
@@ -232,8 +289,12 @@ tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int
         const char* e = std::getenv("TIP_TRACE_ROUNDS");
         return e && e[0] == '1';
     }();
-    double peel_ms = 0.0;
-    int64_t peel_launches = 0;
+    double& peel_ms = rs.peel_ms;
+    int64_t& peel_launches = rs.peel_launches;
+    // rounds run eagerly (one launch sequence per round, host-timed) when
+    // kernels are timed or graphs are disabled, else from a replayed graph
+    const bool eager = time_kernels || (flags & TIP_FLAG_NO_GRAPH) != 0;
+    std::unique_ptr<RoundGraph> rg;
     TIP_HIP_TRY(hipEventRecord(ev.e[0], s));
     TIP_HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s));
     if (!ingest(d_a, d_b, n_a, n_b, m, a_is_u, w.ib, w.g, w.aux, s)) {
@@ -252,11 +313,8 @@ tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int
     launch_count(g, w.cb, w.ctl, w.spill, big_grid, s);
     TIP_HIP_TRY(hipEventRecord(ev.e[2], s));
 
-    int64_t rounds = 0;
-    int32_t S = 0;
+    int32_t& S = rs.S;
     if (!decompose) {
-        if (out.bfly_a) launch_scatter_i64(w.cb.bfly_a, g.a_orig, n_a, out.bfly_a, s);
-        if (out.bfly_b) launch_scatter_i64(w.cb.bfly_b, g.b_orig, n_b, out.bfly_b, s);
         TIP_HIP_TRY(hipEventRecord(ev.e[3], s));
         TIP_HIP_TRY(hipEventRecord(ev.e[4], s));
     } else {
@@ -269,7 +327,8 @@ tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int
         int32_t n_live = n_a;
         double scale = 1.0;
         int64_t lo = 0;
-        std::vector<int64_t> bounds{0};
+        std::vector<int64_t>& bounds = rs.bounds;
+        bounds.assign(1, 0);
         int32_t label = 0;
         for (; label < P && n_live > 0; ++label) {
             launch_range_start(pb, cur_live, n_live, w.ctl, s);
@@ -292,36 +351,37 @@ tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int
                 hi = c1.sel_found ? (int64_t)c1.sel_prefix + 1 : (int64_t)max_supp + 1;
             }
             bounds.push_back(hi);
-            int cur_front = 0;
-            launch_frontier_init(pb, cur_live, n_live, hi, label, cur_front, w.ctl, s);
+            launch_range_begin(pb, cur_live, n_live, hi, label, w.ctl, s);
             for (;;) {
                 const Ctl& c2 = read_ctl(w, s);
                 int32_t n_cur[kBins];
                 int64_t n_tot = 0;
                 for (int b = 0; b < kBins; ++b) n_tot += (n_cur[b] = c2.n_front[b]);
                 if (n_tot == 0) break;
+                if (!eager) {
+                    if (!rg) {
+                        rg.reset(new RoundGraph);
+                        rg->build(g, pb, w.ctl, w.spill, big_grid);
+                    }
+                    TIP_HIP_TRY(hipGraphLaunch(rg->exec, s));
+                    continue;
+                }
                 int32_t nb = 0;
                 for (int b = kBinBitmap; b < kBins; ++b) nb += n_cur[b];
-                launch_peel_round(g, pb, cur_front, n_cur, hi, w.ctl, w.spill, big_grid, s,
-                                  time_kernels && nb > 0 ? kev.e : nullptr);
-                launch_round_end(pb, cur_live, n_live, hi, label, 1 - cur_front, w.ctl, s);
+                launch_round(g, pb, w.ctl, w.spill, big_grid, s, time_kernels && nb > 0 ? kev.e : nullptr);
                 if (nb > 0) {
                     ++peel_launches;
                     if (time_kernels) {
                         TIP_HIP_TRY(hipEventSynchronize(kev.e[1]));
                         const double ms = kev.ms(0, 1);
                         peel_ms += ms;
-                        if (trace_rounds)
-                        {
+                        if (trace_rounds) {
                             std::string bins;
                             for (int b = 0; b < kBins; ++b) bins += (b ? "," : "") + std::to_string(n_cur[b]);
-                            std::fprintf(stderr, "tip-round range=%d round=%lld bins=%s ms=%.4f\n", label,
-                                         (long long)rounds, bins.c_str(), ms);
+                            std::fprintf(stderr, "tip-round range=%d bins=%s ms=%.4f\n", label, bins.c_str(), ms);
                         }
                     }
                 }
-                cur_front ^= 1;
-                ++rounds;
             }
             const Ctl& c3 = read_ctl(w, s);
             if (c3.w_range > 0) scale = std::min(1.0, (double)tgt / (double)c3.w_range);
@@ -342,18 +402,37 @@ tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int
         }
         TIP_HIP_TRY(hipEventRecord(ev.e[3], s));
         // Fine-grained decomposition (Alg. 4).
-        if (S > 0) {
-            launch_fd(g, pb, w.fb, S, w.ctl, w.spill, big_grid, w.ib.keys2, w.ib.vals2, w.ib.hist, w.ib.scan_tmp,
-                      w.ib.keys, w.ib.vals, s);
+        if (fd_inline) {
+            if (S > 0)
+                launch_fd(g, pb, w.fb, S, w.ctl, w.spill, big_grid, w.ib.keys2, w.ib.vals2, w.ib.hist,
+                          w.ib.scan_tmp, w.ib.keys, w.ib.vals, s);
+            TIP_HIP_TRY(hipEventRecord(ev.e[4], s));
+        } else {
+            launch_fd_setup(g, pb, w.fb, S, w.ib.keys2, w.ib.vals2, w.ib.hist, w.ib.scan_tmp, w.ib.keys, w.ib.vals,
+                            s);
         }
-        TIP_HIP_TRY(hipEventRecord(ev.e[4], s));
+    }
+    return TIP_OK;
+}
+
+// Outputs and statistics of a run whose FD has completed on stream s.
+void run_back(Work& w, int32_t n_a, int32_t n_b, bool decompose, RunOut& out, RunState& rs, tip_stats* st,
+              hipStream_t s) {
+    Events& ev = rs.ev;
+    const DevGraph& g = w.g;
+    PeelBuffers& pb = w.pb;
+    const int32_t S = rs.S;
+    if (!decompose) {
+        if (out.bfly_a) launch_scatter_i64(w.cb.bfly_a, g.a_orig, n_a, out.bfly_a, s);
+        if (out.bfly_b) launch_scatter_i64(w.cb.bfly_b, g.b_orig, n_b, out.bfly_b, s);
+    } else {
         launch_scatter_i64(w.fb.theta, g.a_orig, n_a, out.theta, s);
         if (out.subset && n_a > 0) {
             k_scatter_i32<<<(n_a + 255) / 256, 256, 0, s>>>(pb.state, g.a_orig, n_a, out.subset);
             TIP_HIP_TRY(hipGetLastError());
         }
         if (out.init) launch_scatter_i64(pb.init, g.a_orig, n_a, out.init, s);
-        if (out.bounds) *out.bounds = bounds;
+        if (out.bounds) *out.bounds = rs.bounds;
         if (out.n_subsets) *out.n_subsets = S;
     }
     TIP_HIP_TRY(hipEventRecord(ev.e[5], s));
@@ -364,23 +443,32 @@ tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int
         st->wedges_cd = (int64_t)cf.wedges_cd;
         st->wedges_fd = (int64_t)cf.wedges_fd;
         st->pair_updates = (int64_t)cf.pair_updates;
-        st->rounds = rounds;
+        st->rounds = (int64_t)cf.rounds_done;
         st->subsets = S;
         st->fd_levels = (int64_t)cf.fd_levels;
         st->spills = (int64_t)cf.spills;
         st->skipped = (int64_t)cf.skipped;
         st->m_unique = g.m;
-        st->peel_launches = peel_launches;
+        st->peel_launches = rs.peel_launches;
         st->peel_wedges = (int64_t)cf.big_wedges;
         st->peel_edges = (int64_t)cf.big_edges;
         st->peel_pairs = (int64_t)cf.big_pairs;
-        st->peel_ms = peel_ms;
+        st->peel_ms = rs.peel_ms;
         st->t_ingest_ms = ev.ms(0, 1);
         st->t_count_ms = ev.ms(1, 2);
         st->t_cd_ms = ev.ms(2, 3);
         st->t_fd_ms = ev.ms(3, 4);
         st->t_total_ms = ev.ms(0, 5);
     }
+}
+
+tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int32_t n_b, int64_t m, bool a_is_u,
+               int32_t P, int32_t flags, const Tune& tune, bool decompose, RunOut& out, tip_stats* st,
+               hipStream_t s) {
+    RunState rs;
+    const tip_status rc = run_front(w, d_a, d_b, n_a, n_b, m, a_is_u, P, flags, tune, decompose, true, rs, s);
+    if (rc != TIP_OK) return rc;
+    run_back(w, n_a, n_b, decompose, out, rs, st, s);
     return TIP_OK;
 }
 
@@ -421,7 +509,8 @@ void check_edges(const tip_edges* g) {
 int32_t check_opts(const tip_opts* opt) {
     if (!opt) return kDefaultP;
     if (opt->P < 0 || opt->P > kMaxP) throw InvalidArg("P must be in [0, 65535]");
-    if (opt->flags & ~TIP_FLAG_TIME_KERNELS) throw InvalidArg("unknown flag bits");
+    if (opt->flags & ~(TIP_FLAG_TIME_KERNELS | TIP_FLAG_NO_GRAPH | TIP_FLAG_BATCH_PLAIN))
+        throw InvalidArg("unknown flag bits");
     if (opt->tune[0] < 0) throw InvalidArg("tune[0] must be >= 0");
     if (opt->tune[1] < 0) throw InvalidArg("tune[1] must be >= 0");
     for (int i = 2; i < 8; ++i)
@@ -509,6 +598,169 @@ tip_status decompose_host(const tip_edges* g, int32_t side, int64_t* theta, int3
         for (size_t i = 0; i < bvec.size(); ++i) bounds[i] = bvec[i];
     }
     if (n_subsets) *n_subsets = ns;
+    return TIP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batch: every graph's ingest, counting and CD run concurrently on worker
+// streams (the GPU overlaps the kernels of different graphs); then the FD
+// subsets of all graphs are peeled in ONE persistent launch that takes tasks
+// from a single queue ordered by induced wedges across the whole batch
+// (workload-aware scheduling of Alg. 4 over all graphs).
+// ---------------------------------------------------------------------------
+constexpr int kBatchWorkers = 8;
+
+struct BatchItem {
+    int32_t n_a = 0, n_b = 0;
+    int64_t m = 0;
+    bool a_is_u = true;
+    Work w;
+    DeviceBuffer buf;
+    RunState rs;
+    int64_t* d_theta = nullptr;
+    tip_status rc = TIP_OK;
+    std::string err;
+};
+
+tip_status decompose_batched(int32_t n, const tip_edges* gs, const int32_t* sides, int64_t* const* thetas, int32_t P,
+                             int32_t flags, const Tune& tune, tip_stats* st) {
+    if (n == 0) return TIP_OK;
+    int dev = 0;
+    TIP_HIP_TRY(hipGetDevice(&dev));
+    const int slots = resident_workgroups();
+    std::vector<std::unique_ptr<BatchItem>> items(n);
+    std::vector<int32_t> order(n);
+    for (int32_t k = 0; k < n; ++k) order[k] = k;
+    // largest graphs first, so the tail of the concurrent phase is short
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return gs[a].m > gs[b].m; });
+    std::atomic<int32_t> next{0};
+    auto worker = [&]() {
+        hipStream_t s = nullptr;
+        try {
+            TIP_HIP_TRY(hipSetDevice(dev));
+            TIP_HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        } catch (const HipFailure&) {
+            return;  // the items this worker would have taken are picked up by others
+        }
+        for (;;) {
+            const int32_t i = next.fetch_add(1);
+            if (i >= n) break;
+            const int32_t k = order[i];
+            std::unique_ptr<BatchItem> it(new BatchItem);
+            BatchItem& b = *it;
+            try {
+                const tip_edges* g = &gs[k];
+                b.a_is_u = sides[k] == TIP_SIDE_U;
+                b.n_a = b.a_is_u ? g->n_u : g->n_v;
+                b.n_b = b.a_is_u ? g->n_v : g->n_u;
+                b.m = g->m;
+                Arena sizer;
+                plan(sizer, b.n_a, b.n_b, b.m, P, slots, b.w);
+                const size_t extra = sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(b.m, 1) +
+                                     sizeof(int64_t) * (size_t)std::max<int32_t>(b.n_a, 1) + 4096;
+                b.buf.alloc(sizer.off + extra);
+                Arena ar{static_cast<char*>(b.buf.p), sizer.off + extra, 0};
+                plan(ar, b.n_a, b.n_b, b.m, P, slots, b.w);
+                int32_t* d_a = ar.take<int32_t>(std::max<int64_t>(b.m, 1));
+                int32_t* d_b = ar.take<int32_t>(std::max<int64_t>(b.m, 1));
+                b.d_theta = ar.take<int64_t>(std::max<int32_t>(b.n_a, 1));
+                TIP_HIP_TRY(hipMemsetAsync(b.w.spill.dense, 0, sizeof(int32_t) * b.w.spill.stride * b.w.spill.slots, s));
+                if (b.m > 0) {
+                    TIP_HIP_TRY(hipMemcpyAsync(d_a, b.a_is_u ? g->eu : g->ev, sizeof(int32_t) * b.m,
+                                               hipMemcpyHostToDevice, s));
+                    TIP_HIP_TRY(hipMemcpyAsync(d_b, b.a_is_u ? g->ev : g->eu, sizeof(int32_t) * b.m,
+                                               hipMemcpyHostToDevice, s));
+                }
+                b.rc = run_front(b.w, d_a, d_b, b.n_a, b.n_b, b.m, b.a_is_u, P, flags, tune, true, false, b.rs, s);
+                if (b.rc != TIP_OK) b.err = last_error();
+                TIP_HIP_TRY(hipStreamSynchronize(s));
+            } catch (const AllocFailure& e) {
+                b.rc = TIP_ENOMEM;
+                b.err = e.msg;
+            } catch (const HipFailure& e) {
+                b.rc = TIP_EDEVICE;
+                b.err = e.msg;
+            } catch (const std::bad_alloc&) {
+                b.rc = TIP_ENOMEM;
+                b.err = "host allocation failed";
+            } catch (...) {
+                b.rc = TIP_EDEVICE;
+                b.err = "unexpected internal error";
+            }
+            items[k] = std::move(it);
+        }
+        (void)hipStreamDestroy(s);
+    };
+    {
+        std::vector<std::thread> pool;
+        const int nw = std::min<int>(n, kBatchWorkers);
+        for (int t = 0; t < nw; ++t) pool.emplace_back(worker);
+        for (auto& t : pool) t.join();
+    }
+    for (int32_t k = 0; k < n; ++k) {
+        if (!items[k]) {
+            set_error("batch worker could not start");
+            return TIP_EDEVICE;
+        }
+        if (items[k]->rc != TIP_OK) {
+            set_error("graph " + std::to_string(k) + ": " + items[k]->err);
+            return items[k]->rc;
+        }
+    }
+    // one task list over all graphs, heaviest induced subgraph first
+    StreamHolder sh;
+    const hipStream_t s = sh.s;
+    std::vector<FdJob> jobs;
+    std::vector<std::pair<int64_t, int64_t>> tasks;  // (weight, job << 32 | subset)
+    std::vector<int64_t> tw;
+    int64_t stride = 64;
+    for (int32_t k = 0; k < n; ++k) {
+        BatchItem& b = *items[k];
+        if (b.rs.S <= 0 || b.n_a <= 0) continue;
+        tw.resize(b.rs.S);
+        TIP_HIP_TRY(hipMemcpyAsync(tw.data(), b.w.fb.task_w, sizeof(int64_t) * b.rs.S, hipMemcpyDeviceToHost, s));
+        TIP_HIP_TRY(hipStreamSynchronize(s));
+        const int64_t j = (int64_t)jobs.size();
+        jobs.push_back(FdJob{b.w.g, b.w.fb, b.w.pb.init, b.w.ctl});
+        for (int32_t i = 0; i < b.rs.S; ++i) tasks.emplace_back(tw[i], (j << 32) | i);
+        stride = std::max(stride, b.w.spill.stride);
+    }
+    std::stable_sort(tasks.begin(), tasks.end(),
+                     [](const std::pair<int64_t, int64_t>& a, const std::pair<int64_t, int64_t>& b) {
+                         return a.first > b.first;
+                     });
+    DeviceBuffer fdbuf;
+    if (!tasks.empty()) {
+        // five sub-allocations, each aligned by the arena
+        const size_t bytes = sizeof(FdJob) * jobs.size() + sizeof(int64_t) * tasks.size() + sizeof(int32_t) +
+                             2 * sizeof(int32_t) * (size_t)stride * slots + 4096;
+        fdbuf.alloc(bytes);
+        Arena ar{static_cast<char*>(fdbuf.p), bytes, 0};
+        FdJob* d_jobs = ar.take<FdJob>(jobs.size());
+        int64_t* d_tasks = ar.take<int64_t>(tasks.size());
+        int32_t* d_head = ar.take<int32_t>(1);
+        SpillArena spill;
+        spill.stride = stride;
+        spill.slots = slots;
+        spill.dense = ar.take<int32_t>(stride * slots);
+        spill.list = ar.take<int32_t>(stride * slots);
+        std::vector<int64_t> tv(tasks.size());
+        for (size_t i = 0; i < tasks.size(); ++i) tv[i] = tasks[i].second;
+        TIP_HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(FdJob) * jobs.size(), hipMemcpyHostToDevice, s));
+        TIP_HIP_TRY(hipMemcpyAsync(d_tasks, tv.data(), sizeof(int64_t) * tv.size(), hipMemcpyHostToDevice, s));
+        TIP_HIP_TRY(hipMemsetAsync(spill.dense, 0, sizeof(int32_t) * stride * slots, s));
+        launch_fd_batch(d_jobs, d_tasks, (int32_t)tasks.size(), d_head, spill, slots, s);
+    }
+    for (int32_t k = 0; k < n; ++k) TIP_HIP_TRY(hipEventRecord(items[k]->rs.ev.e[4], s));
+    for (int32_t k = 0; k < n; ++k) {
+        BatchItem& b = *items[k];
+        RunOut out;
+        out.theta = b.d_theta;
+        run_back(b.w, b.n_a, b.n_b, true, out, b.rs, st ? &st[k] : nullptr, s);
+        if (b.n_a > 0)
+            TIP_HIP_TRY(hipMemcpyAsync(thetas[k], b.d_theta, sizeof(int64_t) * b.n_a, hipMemcpyDeviceToHost, s));
+    }
+    TIP_HIP_TRY(hipStreamSynchronize(s));
     return TIP_OK;
 }
 
@@ -606,10 +858,13 @@ tip_status tip_decompose_batch(int32_t n, const tip_edges* gs, const int32_t* si
             const int32_t n_side = sides[k] == TIP_SIDE_U ? gs[k].n_u : gs[k].n_v;
             if (n_side > 0 && !thetas[k]) throw InvalidArg("theta is NULL");
         }
+        const int32_t flags = opt ? opt->flags : 0;
+        if (!(flags & TIP_FLAG_BATCH_PLAIN))
+            return decompose_batched(n, gs, sides, thetas, P, flags, tune_of(opt), st);
+        // the plain form: one full decomposition after another
         for (int32_t k = 0; k < n; ++k) {
-            const tip_status rc = decompose_host(&gs[k], sides[k], thetas[k], P, opt ? opt->flags : 0,
-                                                 tune_of(opt), st ? &st[k] : nullptr, nullptr, nullptr,
-                                                 nullptr, nullptr);
+            const tip_status rc = decompose_host(&gs[k], sides[k], thetas[k], P, flags, tune_of(opt),
+                                                 st ? &st[k] : nullptr, nullptr, nullptr, nullptr, nullptr);
             if (rc != TIP_OK) return rc;
         }
         return TIP_OK;

@@ -33,6 +33,14 @@ struct Ctl {
     unsigned long long big_edges;
     unsigned long long big_pairs;
     unsigned long long head[kBins];  // next work item of each update kernel in the current round
+    // Range state read by the round kernels, so that a sequence of rounds
+    // can be launched (or replayed from a graph) without host arguments.
+    long long range_hi;      // upper bound of the current range
+    int32_t range_label;     // subset id of the current range
+    int32_t range_live;      // which live list holds the range's live vertices
+    int32_t range_n_live;    // its length
+    int32_t front_buf;       // which frontier buffer is current
+    unsigned long long rounds_done;  // rounds with a non-empty activeSet
 };
 
 struct CountBuffers {
@@ -90,18 +98,43 @@ void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers
 void launch_range_start(PeelBuffers& pb, int cur_live, int32_t n_live, Ctl* ctl, hipStream_t s);
 void launch_select(PeelBuffers& pb, int cur_live, int32_t n_live, uint64_t max_supp, int64_t tgt, Ctl* ctl,
                    hipStream_t s);
-void launch_frontier_init(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi, int32_t label, int cur_front,
-                          Ctl* ctl, hipStream_t s);
-// n_cur: host copy of the current frontier sizes; ev_big: optional pair of
-// events recorded around the workgroup update kernels.
-void launch_peel_round(const DevGraph& g, PeelBuffers& pb, int cur_front, const int32_t* n_cur, int64_t hi,
-                       Ctl* ctl, const SpillArena& spill, int big_grid, hipStream_t s, hipEvent_t* ev_big);
-// Next activeSet (live vertices now below hi) into buffer next_front, then
-// swaps the frontier buffers.
-void launch_round_end(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi, int32_t label, int next_front,
-                      Ctl* ctl, hipStream_t s);
+// Sets the range state and builds the range's first activeSet.
+void launch_range_begin(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi, int32_t label, Ctl* ctl,
+                        hipStream_t s);
+// One coarse-grained round, driven entirely by the control block: update
+// kernels over the current activeSet, then the next activeSet and the buffer
+// swap.  Fixed grids, no host synchronisation, so it can be graph-captured.
+// ev_big: optional pair of events recorded around the workgroup update
+// kernels (not while capturing).
+void launch_round(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena& spill, int big_grid,
+                  hipStream_t s, hipEvent_t* ev_big);
 void launch_assign_live(PeelBuffers& pb, int cur_live, int32_t n_live, int32_t label, hipStream_t s);
+// One graph's part of a fine-grained launch.
+struct FdJob {
+    DevGraph g;
+    FdBuffers fb;
+    const int64_t* init;  // [n_a] support at the start of each vertex's range
+    Ctl* ctl;             // receives the job's work counters
+};
+
+// The jobs of one launch: a device array, or (list == nullptr) one job
+// passed by value.
+struct FdJobs {
+    const FdJob* list;
+    FdJob one;
+};
+
 // FD
+// Subset grouping, partitioned CSC and workload order of one graph (up to,
+// not including, the peeling launch); fb.task_w holds the induced wedges.
+void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, uint64_t* tmp_keys,
+                     int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp, uint64_t* keys_scratch,
+                     int32_t* vals_scratch, hipStream_t s);
+// Persistent peeling of the subsets of many graphs in one launch: tasks[t] =
+// job << 32 | subset, in the order they are to be taken; *head is the queue
+// head (reset here).
+void launch_fd_batch(const FdJob* d_jobs, const int64_t* d_tasks, int32_t n_tasks, int32_t* d_head,
+                     const SpillArena& spill, int big_grid, hipStream_t s);
 void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl, const SpillArena& spill,
                int big_grid, uint64_t* tmp_keys, int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp,
                uint64_t* keys_scratch, int32_t* vals_scratch, hipStream_t s);

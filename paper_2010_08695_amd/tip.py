@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libtip.so")
 
 TIP_OK, TIP_EINVAL, TIP_ENOMEM, TIP_EDEVICE, TIP_EOVERFLOW, TIP_EBUSY = 0, -1, -2, -3, -4, -5
 TIP_FLAG_TIME_KERNELS = 1
+TIP_FLAG_NO_GRAPH = 2
+TIP_FLAG_BATCH_PLAIN = 4
 SIDE_U, SIDE_V = 0, 1
 STATUS_NAMES = {0: "TIP_OK", -1: "TIP_EINVAL", -2: "TIP_ENOMEM", -3: "TIP_EDEVICE",
                 -4: "TIP_EOVERFLOW", -5: "TIP_EBUSY"}
@@ -165,7 +167,7 @@ def decompose(g, side: int = SIDE_U, P: int = 0, with_stats: bool = False, flags
     return (theta, st.to_dict()) if with_stats else theta
 
 
-def decompose_ex(g, side: int = SIDE_U, P: int = 0) -> dict:
+def decompose_ex(g, side: int = SIDE_U, P: int = 0, flags: int = 0) -> dict:
     """Tip numbers plus the coarse-grained state (subsets, initial supports, bounds)."""
     lib = load()
     e, keep = _edges(g)
@@ -177,7 +179,7 @@ def decompose_ex(g, side: int = SIDE_U, P: int = 0) -> dict:
     bounds = np.zeros(Pe + 2, np.int64)
     ns = np.zeros(1, np.int32)
     st = Stats()
-    o = _opts(P)
+    o = _opts(P, flags)
     _check(lib, lib.tip_decompose_ex(ctypes.byref(e), int(side), _ptr(theta), ctypes.byref(o),
                                      ctypes.byref(st), _ptr(subset), _ptr(init), _ptr(bounds), _ptr(ns)))
     k = int(ns[0])
@@ -185,8 +187,9 @@ def decompose_ex(g, side: int = SIDE_U, P: int = 0) -> dict:
             "n_subsets": k, "stats": st.to_dict()}
 
 
-def decompose_batch(graphs, sides=None, P: int = 0, with_stats: bool = False):
-    """Tip numbers of many graphs in one call."""
+def decompose_batch(graphs, sides=None, P: int = 0, with_stats: bool = False, flags: int = 0):
+    """Tip numbers of many graphs in one call (batched form unless flags has
+    TIP_FLAG_BATCH_PLAIN)."""
     lib = load()
     n = len(graphs)
     sides = [SIDE_U] * n if sides is None else list(sides)
@@ -200,7 +203,7 @@ def decompose_batch(graphs, sides=None, P: int = 0, with_stats: bool = False):
     sides_a = np.ascontiguousarray(sides, dtype=np.int32)
     ptrs = (ctypes.c_void_p * max(n, 1))(*[t.ctypes.data for t in thetas])
     sts = (Stats * max(n, 1))()
-    o = _opts(P)
+    o = _opts(P, flags)
     _check(lib, lib.tip_decompose_batch(n, es, _ptr(sides_a), ctypes.cast(ptrs, ctypes.c_void_p),
                                         ctypes.byref(o), sts))
     if with_stats:

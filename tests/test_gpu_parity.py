@@ -157,11 +157,56 @@ def test_repeatable(gpu_lib):
         assert sa[k] == sb[k], k
 
 
+@pytest.mark.parametrize("P", [3, 150])
+def test_graph_rounds_match_eager(gpu_lib, P):
+    """Coarse-grained rounds replayed from a captured HIP graph (several
+    rounds per replay) give the same tip numbers, subsets and work as rounds
+    launched one by one from the host."""
+    g = gg.chung_lu(6000, 1200, 60000, 2.2, 2.0, seed=19)
+    th = oracle.bup(g, 0)[0]
+    runs = [tip.decompose(g, 0, P=P, with_stats=True, flags=f)
+            for f in (0, tip.TIP_FLAG_NO_GRAPH, tip.TIP_FLAG_TIME_KERNELS)]
+    for t, st in runs:
+        np.testing.assert_array_equal(t, th)
+        assert st["rounds"] > 0
+    for k in ("wedges_cd", "wedges_fd", "pair_updates", "rounds", "subsets", "skipped"):
+        assert runs[0][1][k] == runs[1][1][k] == runs[2][1][k], k
+    ex_graph = tip.decompose_ex(g, 0, P=P)
+    ex_eager = tip.decompose_ex(g, 0, P=P, flags=tip.TIP_FLAG_NO_GRAPH)
+    np.testing.assert_array_equal(ex_graph["subset"], ex_eager["subset"])
+    np.testing.assert_array_equal(ex_graph["bounds"], ex_eager["bounds"])
+
+
 def test_batch_matches_single(gpu_lib):
     gs = [gg.chung_lu(800 + 100 * k, 300, 5000 + 500 * k, 2.2, 2.3, seed=200 + k) for k in range(5)]
     sides = [0, 1, 0, 1, 0]
     out = tip.decompose_batch(gs, sides)
     for g, s, th in zip(gs, sides, out):
+        np.testing.assert_array_equal(th, oracle.bup(g, s)[0])
+
+
+def test_batch_forms_agree(gpu_lib):
+    """The batched form (concurrent graphs, one fine-grained launch over all
+    graphs' subsets) and the plain one-after-another form give the oracle's
+    tip numbers and the same per-graph work."""
+    params = gg.batch_params(12, seed_base=3000, m_lo=2e3, m_hi=4e4)
+    gs = [gg.batch_graph(p) for p in params]
+    sides = [k % 2 for k in range(len(gs))]
+    tb, sb = tip.decompose_batch(gs, sides, with_stats=True)
+    tp, sp = tip.decompose_batch(gs, sides, with_stats=True, flags=tip.TIP_FLAG_BATCH_PLAIN)
+    for g, s, a, b, x, y in zip(gs, sides, tb, tp, sb, sp):
+        th = oracle.bup(g, s)[0]
+        np.testing.assert_array_equal(a, th)
+        np.testing.assert_array_equal(b, th)
+        for k in ("wedges_count", "wedges_cd", "wedges_fd", "pair_updates", "subsets", "fd_levels"):
+            assert x[k] == y[k], k
+
+
+def test_batch_with_empty_and_tiny_graphs(gpu_lib):
+    gs = [gg.Graph(3, 2, np.zeros(0, np.int32), np.zeros(0, np.int32), "empty"),
+          gg.complete_bipartite(4, 3), gg.star(5), gg.chung_lu(900, 300, 6000, 2.2, 2.3, seed=41)]
+    out = tip.decompose_batch(gs, [0, 1, 0, 0])
+    for g, s, th in zip(gs, [0, 1, 0, 0], out):
         np.testing.assert_array_equal(th, oracle.bup(g, s)[0])
 
 
