@@ -8,7 +8,14 @@ of the U side of the cl-10m workload (Chung-Lu |U| = 1e6, |V| = 2e5,
 150), with the edge list already resident in HBM.  Reported value: wedges
 traversed per second (counting + coarse + fine wedges / step time).
 
+After the timed steps, one more step runs with kernel timing on: HIP events
+on the launch stream around every launch of the dominant kernel give the
+roofline figures (the timed steps themselves run uninstrumented, with the
+coarse-grained rounds replayed from a HIP graph).
+
     python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py --steps 0          # only the instrumented step (counter runs)
+    python bench.py --batch            # 64-graph batch: batched vs plain launches
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 exits with a
 message.
@@ -32,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_WEDGE = 4
 BYTES_PER_EDGE = 4
 BYTES_PER_PAIR = 16
-DOMINANT_KERNEL = "k_peel_big"
+DOMINANT_KERNEL = "k_peel_bitmap"
 KERNEL_SOURCES = ["paper_2010_08695_amd/csrc/peel.hip", "paper_2010_08695_amd/csrc/agg.h",
                   "paper_2010_08695_amd/csrc/tip_common.h"]
 
@@ -97,6 +104,42 @@ def cpu_baseline(g, seconds: float) -> dict:
                        f"included, so this overstates the full oracle's rate")}
 
 
+def bench_batch(args) -> int:
+    """64 Chung-Lu graphs (m log-uniform in [1e4, 2e6], |U|:|V| in [1, 8],
+    exponents in [2.0, 2.8], U side): the batched form (graphs overlapped on
+    worker streams, one fine-grained launch over all graphs' subsets) against
+    the plain form (one full decomposition after another), same API call."""
+    import numpy as np
+
+    from paper_2010_08695_amd import graphgen, tip
+    params = graphgen.batch_params(args.batch_graphs)
+    graphs = [graphgen.batch_graph(p) for p in params]
+    sides = [0] * len(graphs)
+    res = {}
+    for name, flags in (("batched", 0), ("plain", tip.TIP_FLAG_BATCH_PLAIN)):
+        tip.decompose_batch(graphs, sides, P=args.P, flags=flags)  # warm-up
+        best, out, sts = None, None, None
+        for _ in range(max(1, args.steps)):
+            t0 = time.perf_counter()
+            out, sts = tip.decompose_batch(graphs, sides, P=args.P, with_stats=True, flags=flags)
+            dt = time.perf_counter() - t0
+            best = dt if best is None or dt < best else best
+        res[name] = (best, out, sts)
+    same = all(np.array_equal(a, b) for a, b in zip(res["batched"][1], res["plain"][1]))
+    sts = res["batched"][2]
+    wedges = sum(s["wedges_count"] + s["wedges_cd"] + s["wedges_fd"] for s in sts)
+    out = {"metric": "wedges/s (batch of tip decompositions, bit-exact)",
+           "value": wedges / res["batched"][0], "unit": "wedges/s", "n_gpus": 1, "steps": args.steps,
+           "higher_is_better": True, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"batch-{len(graphs)}: Chung-Lu graphs, m log-uniform in [1e4, 2e6], "
+                                  f"sum m = {sum(g.m for g in graphs)}, side U, P={args.P}"},
+           "batched_s": res["batched"][0], "plain_s": res["plain"][0],
+           "speedup_vs_plain": res["plain"][0] / res["batched"][0], "same_results": same,
+           "note": "host edge lists in, host tip numbers out (H2D/D2H and allocation included in both forms)"}
+    print(json.dumps(out))
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,11 +150,15 @@ def main(argv=None) -> int:
     ap.add_argument("--P", type=int, default=150)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", action="store_true", help="batched vs plain launches on the 64-graph batch")
+    ap.add_argument("--batch-graphs", type=int, default=64)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
         return 2
+    if args.batch:
+        return bench_batch(args)
 
     import numpy as np
     import torch
@@ -134,28 +181,33 @@ def main(argv=None) -> int:
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    stats = []
+    st = None
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        stats.append(step(tip.TIP_FLAG_TIME_KERNELS))
+        st = step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    sec_per_step = elapsed / max(args.steps, 1)
-    st = stats[-1]
-    wedges = st["wedges_count"] + st["wedges_cd"] + st["wedges_fd"]
+    sec_per_step = elapsed / args.steps if args.steps > 0 else None
 
-    # dominant kernel: algorithmic bytes per launch over its mean launch time
-    launches = sum(s["peel_launches"] for s in stats)
-    peel_ms = sum(s["peel_ms"] for s in stats)
-    alg_bytes = sum(BYTES_PER_WEDGE * s["peel_wedges"] + BYTES_PER_EDGE * s["peel_edges"] +
-                    BYTES_PER_PAIR * s["peel_pairs"] for s in stats)
+    # one instrumented step: the dominant kernel's launches timed with HIP
+    # events on the launch stream, its algorithmic bytes counted on the device
+    ist = step(tip.TIP_FLAG_TIME_KERNELS)
+    torch.cuda.synchronize()
+    if st is None:
+        st = ist
+    wedges = st["wedges_count"] + st["wedges_cd"] + st["wedges_fd"]
+    launches = ist["peel_launches"]
+    peel_ms = ist["peel_ms"]
+    alg_bytes = (BYTES_PER_WEDGE * ist["peel_wedges"] + BYTES_PER_EDGE * ist["peel_edges"] +
+                 BYTES_PER_PAIR * ist["peel_pairs"])
     achieved = (alg_bytes / (peel_ms / 1e3)) / 1e9 if peel_ms > 0 else None
     traffic = load_traffic(args.workload)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
-                "kernel": DOMINANT_KERNEL, "launches_per_step": launches / max(args.steps, 1),
+                "kernel": DOMINANT_KERNEL, "launches_per_step": launches,
                 "mean_launch_ms": peel_ms / max(launches, 1),
-                "alg_bytes_per_launch": alg_bytes / max(launches, 1)}
+                "alg_bytes_per_launch": alg_bytes / max(launches, 1),
+                "kernel_share_of_step": (peel_ms / 1e3) / sec_per_step if sec_per_step else None}
 
     # bit-exactness against the oracle's stored digest
     theta = d_theta.cpu().numpy()
@@ -171,12 +223,12 @@ def main(argv=None) -> int:
 
     out = {
         "metric": "wedges/s (full tip decomposition, bit-exact)",
-        "value": wedges / sec_per_step,
+        "value": wedges / sec_per_step if sec_per_step else None,
         "unit": "wedges/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": sec_per_step * 1e3,
+        "ms_per_step": sec_per_step * 1e3 if sec_per_step else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -55,8 +55,10 @@ typedef struct {
 } tip_edges;
 
 /* TIP_FLAG_TIME_KERNELS: time every launch of the coarse-grained
- * workgroup peeling kernel (the dominant kernel) with HIP events on the
- * call's stream and report it in tip_stats.peel_*. */
+ * bitmap-path update kernel (k_peel_bitmap: one workgroup per peeled vertex
+ * of up to tune[1] wedges; the single kernel with the most device time on
+ * power-law graphs) with HIP events on the call's stream and report it in
+ * tip_stats.peel_*. */
 #define TIP_FLAG_TIME_KERNELS 1
 
 /* TIP_FLAG_NO_GRAPH: launch every coarse-grained round from the host
@@ -97,7 +99,7 @@ typedef struct {
     int64_t spills;       /* repeat keys that did not fit in LDS (kept in HBM) */
     int64_t skipped;      /* peeled vertices with no butterfly left (no update needed) */
     int64_t m_unique;     /* edges after duplicate merging */
-    /* the coarse-grained workgroup peeling kernel alone */
+    /* the coarse-grained bitmap-path update kernel alone (k_peel_bitmap) */
     int64_t peel_launches; /* launches */
     int64_t peel_wedges;   /* wedges it traversed */
     int64_t peel_edges;    /* first-hop edges (u, v) it read */

@@ -36,11 +36,13 @@ namespace {
 // Shared staging of neighbour-list runs and unit-wise traversal
 // ---------------------------------------------------------------------------
 
-template <int NT>
+// Staging of up to NR runs (one per thread j < NR) for a workgroup of NT
+// threads.
+template <int NT, int NR = NT>
 struct Stage {
-    int64_t sbeg[NT];
-    int32_t len[NT];
-    int32_t upre[NT + 1];
+    int64_t sbeg[NR];
+    int32_t len[NR];
+    int32_t upre[NR + 1];
     int64_t red[NT / kWave];
     int64_t item;
 };
@@ -48,18 +50,19 @@ struct Stage {
 // Work items of a round are taken from a per-kernel counter, so workgroups
 // that drew cheap items go on to the next instead of idling behind one that
 // drew an expensive one.  All threads of the workgroup must call.
-template <int NT>
-__device__ inline int64_t next_item(Stage<NT>& S, unsigned long long* head) {
+template <int NT, int NR>
+__device__ inline int64_t next_item(Stage<NT, NR>& S, unsigned long long* head) {
     __syncthreads();
     if (threadIdx.x == 0) S.item = (int64_t)atomicAdd(head, 1ull);
     __syncthreads();
     return S.item;
 }
 
-// Stages the runs held by threads j < gs (one run per thread: start, length)
-// and returns the number of traversal units (kUnit entries of one run).
-template <int NT>
-__device__ inline int32_t stage_units(Stage<NT>& S, int gs, int64_t s0, int32_t len) {
+// Stages the runs held by threads j < gs <= NR (one run per thread: start,
+// length) and returns the number of traversal units (kUnit entries of one
+// run).
+template <int NT, int NR>
+__device__ inline int32_t stage_units(Stage<NT, NR>& S, int gs, int64_t s0, int32_t len) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const int32_t units = tid < gs ? (len + kUnit - 1) / kUnit : 0;
     if (tid < gs) {
@@ -88,17 +91,17 @@ __device__ inline int32_t stage_units(Stage<NT>& S, int gs, int64_t s0, int32_t 
 // a unit is found by stepping forward from the previous one.  kUnitsInFlight
 // units are loaded before any is consumed, so 2 * kUnitsInFlight loads per
 // lane are in flight together.
-template <int NT>
-__device__ inline int advance_run(const Stage<NT>& S, int j, int gs, int32_t k) {
+template <int NT, int NR>
+__device__ inline int advance_run(const Stage<NT, NR>& S, int j, int gs, int32_t k) {
     while (j + 1 < gs && S.upre[j + 1] <= k) ++j;
     return j;
 }
 
 constexpr int kUnitsInFlight = 4;
 
-template <int NT, class F>
-__device__ inline void traverse_units(const Stage<NT>& S, int gs, int32_t nunits, const int32_t* __restrict__ adj,
-                                      F&& f) {
+template <int NT, int NR, class F>
+__device__ inline void traverse_units(const Stage<NT, NR>& S, int gs, int32_t nunits,
+                                      const int32_t* __restrict__ adj, F&& f) {
     constexpr int NW = NT / kWave;
     constexpr int R = kUnitsInFlight;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -500,7 +503,7 @@ k_peel_wave(DevGraph g, FrontSet fs, const int64_t* __restrict__ wprox, CdApply 
 struct BmLds {
     uint32_t bm[kBmTile / 32];
     unsigned long long rep[kBmRep];
-    Stage<kBigThreads> st;
+    Stage<kBigThreads, kBmRuns> st;
     int32_t spill_n;
 };
 
@@ -536,7 +539,7 @@ k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t nt
     __shared__ BmLds L;
     constexpr int NT = kBigThreads;
     constexpr int kPer = kBmRep / NT;  // repeat slots scanned by each thread
-    static_assert(kBmRep % NT == 0 && kPer <= 32, "repeat slots per thread");
+    static_assert(kBmRep % NT == 0 && kPer >= 1 && kPer <= 32, "repeat slots per thread");
     const int tid = threadIdx.x;
     for (int w = tid; w < kBmTile / 32; w += NT) L.bm[w] = 0;
     for (int s = tid; s < kBmRep; s += NT) L.rep[s] = 0;
@@ -558,8 +561,8 @@ k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t nt
         for (int32_t klo = 0; klo < g.n_a; klo += kBmTile) {
             const int32_t khi = (int32_t)min<int64_t>(g.n_a, (int64_t)klo + kBmTile);
             const int32_t t0 = klo / tk, t1 = min(t0 + sub, ntt);
-            for (int64_t g0 = 0; g0 < d; g0 += NT) {
-                const int gs = (int)min<int64_t>(NT, d - g0);
+            for (int64_t g0 = 0; g0 < d; g0 += kBmRuns) {
+                const int gs = (int)min<int64_t>(kBmRuns, d - g0);
                 int64_t s0 = 0;
                 int32_t len = 0;
                 if (tid < gs) {
@@ -569,9 +572,9 @@ k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t nt
                     s0 = g.b_off[v] + a;
                     len = row[t1] - a;
                 }
-                const int32_t nu = stage_units<NT>(L.st, gs, s0, len);
+                const int32_t nu = stage_units(L.st, gs, s0, len);
                 unsigned long long wl = 0;
-                traverse_units<NT>(L.st, gs, nu, g.b_adj, [&](int32_t w) {
+                traverse_units(L.st, gs, nu, g.b_adj, [&](int32_t w) {
                     if (w != u) {
                         ++wl;
                         const uint32_t k = (uint32_t)(w - klo);
@@ -707,9 +710,9 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
                 s0 = g.b_off[v] + a;
                 len = row[t_end] - a;
             }
-            const int32_t nu = stage_units<NT>(S, gs, s0, len);
+            const int32_t nu = stage_units(S, gs, s0, len);
             unsigned long long wl = 0;
-            traverse_units<NT>(S, gs, nu, g.b_adj, [&](int32_t w) {
+            traverse_units(S, gs, nu, g.b_adj, [&](int32_t w) {
                 if (w != u) {
                     ++wl;
                     const uint32_t k = (uint32_t)(w - klo);
@@ -752,7 +755,7 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
         ap.flush(pbuf, pc.pairs);
         __syncthreads();
     }
-    pc.flush(ctl, true);
+    pc.flush(ctl, false);
 }
 
 size_t dense_lds_bytes(int64_t keys, int bits) { return (size_t)(keys * bits / 8) + sizeof(Stage<kDenseThreads>); }
@@ -865,24 +868,30 @@ void launch_range_begin(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t h
 }
 
 void launch_round(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena& spill, int big_grid,
-                  hipStream_t s, hipEvent_t* ev_big) {
+                  hipStream_t s, hipEvent_t* ev_big, const int32_t* n_cur) {
     const CdApply ap{pb.supp, pb.state};
     const FrontSet fs = front_set(pb);
     if (g.n_a <= 0) return;
     // grids are fixed; every kernel reads its work from the control block and
-    // returns at once when it has none
-    k_peel_wave<<<2048, kSmallThreads, 0, s>>>(g, fs, pb.wprox, ap, ctl);
-    TIP_HIP_TRY(hipGetLastError());
-    if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[0], s));
-    k_peel_bitmap<<<std::min(big_grid, spill.slots), kBigThreads, 0, s>>>(g, pb.tb, pb.tk, pb.ntt, fs, ap, spill,
-                                                                           ctl);
-    TIP_HIP_TRY(hipGetLastError());
+    // returns at once when it has none.  With the frontier sizes known on the
+    // host (n_cur), kernels without work are not launched at all.
+    const auto has = [&](int b) { return !n_cur || n_cur[b] > 0; };
+    if (has(kBinWave)) {
+        k_peel_wave<<<2048, kSmallThreads, 0, s>>>(g, fs, pb.wprox, ap, ctl);
+        TIP_HIP_TRY(hipGetLastError());
+    }
+    if (has(kBinBitmap)) {
+        if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[0], s));
+        k_peel_bitmap<<<std::min(big_grid, spill.slots), kBigThreads, 0, s>>>(g, pb.tb, pb.tk, pb.ntt, fs, ap,
+                                                                               spill, ctl);
+        TIP_HIP_TRY(hipGetLastError());
+        if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[1], s));
+    }
     // heavier counter widths first: their vertices have the most wedges
-    launch_dense<16>(g, pb, fs, ap, ctl, s);
-    launch_dense<8>(g, pb, fs, ap, ctl, s);
-    launch_dense<4>(g, pb, fs, ap, ctl, s);
-    launch_dense<2>(g, pb, fs, ap, ctl, s);
-    if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[1], s));
+    if (has(dense_bin(16, false)) || has(dense_bin(16, true))) launch_dense<16>(g, pb, fs, ap, ctl, s);
+    if (has(dense_bin(8, false)) || has(dense_bin(8, true))) launch_dense<8>(g, pb, fs, ap, ctl, s);
+    if (has(dense_bin(4, false)) || has(dense_bin(4, true))) launch_dense<4>(g, pb, fs, ap, ctl, s);
+    if (has(dense_bin(2, false)) || has(dense_bin(2, true))) launch_dense<2>(g, pb, fs, ap, ctl, s);
     k_frontier_scan<<<grid1(g.n_a, 4096), kT, 0, s>>>(fs, pb.live[0], pb.live[1], pb.supp, pb.state, pb.wprox,
                                                        pb.bin, 1, ctl);
     TIP_HIP_TRY(hipGetLastError());

@@ -145,7 +145,7 @@ struct RoundGraph {
     void build(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena& spill, int big_grid) {
         TIP_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         TIP_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < kRoundsPerGraph; ++k) launch_round(g, pb, ctl, spill, big_grid, cs, nullptr);
+        for (int k = 0; k < kRoundsPerGraph; ++k) launch_round(g, pb, ctl, spill, big_grid, cs, nullptr, nullptr);
         TIP_HIP_TRY(hipStreamEndCapture(cs, &graph));
         TIP_HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     }
@@ -267,7 +267,7 @@ __global__ void k_scatter_i32(const int32_t* by_rank, const int32_t* orig, int32
 // or all of FD) to the second (outputs and statistics).
 struct RunState {
     Events ev;
-    Events kev;  // [0], [1]: around the workgroup update kernels of one round
+    Events kev;  // [0], [1]: around the bitmap-path update kernel of one round
     double peel_ms = 0.0;
     int64_t peel_launches = 0;
     int32_t S = 0;
@@ -366,9 +366,8 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
                     TIP_HIP_TRY(hipGraphLaunch(rg->exec, s));
                     continue;
                 }
-                int32_t nb = 0;
-                for (int b = kBinBitmap; b < kBins; ++b) nb += n_cur[b];
-                launch_round(g, pb, w.ctl, w.spill, big_grid, s, time_kernels && nb > 0 ? kev.e : nullptr);
+                const int32_t nb = n_cur[kBinBitmap];
+                launch_round(g, pb, w.ctl, w.spill, big_grid, s, time_kernels && nb > 0 ? kev.e : nullptr, n_cur);
                 if (nb > 0) {
                     ++peel_launches;
                     if (time_kernels) {

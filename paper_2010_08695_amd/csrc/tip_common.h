@@ -28,6 +28,7 @@ constexpr int64_t kSmallMaxWedges = 448;   // wave path handles <= this many wed
 // Coarse-grained update kernels (see peel.hip).
 constexpr int kBmTile = 1 << 19;           // keys per bitmap-path tile (64 KiB of bits)
 constexpr int kBmRep = 8192;               // bitmap-path repeat slots (64 KiB)
+constexpr int kBmRuns = 1024;              // neighbour runs staged per pass by the bitmap path
 constexpr int kUnit = 128;                 // consecutive list entries per traversal unit
 constexpr int kDenseThreads = 256;         // threads of the dense (vertex, key range) kernel
 constexpr int kDenseLdsBytes = 32768;      // counter bytes per dense workgroup (four per CU)

@@ -104,10 +104,13 @@ void launch_range_begin(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t h
 // One coarse-grained round, driven entirely by the control block: update
 // kernels over the current activeSet, then the next activeSet and the buffer
 // swap.  Fixed grids, no host synchronisation, so it can be graph-captured.
-// ev_big: optional pair of events recorded around the workgroup update
-// kernels (not while capturing).
+// ev_big: optional pair of events recorded around the bitmap-path update
+// kernel, the one timed by TIP_FLAG_TIME_KERNELS (not while capturing).
+// n_cur: the frontier sizes per bin when the host knows them (kernels
+// without work are then skipped), or nullptr (graph capture: every kernel
+// is launched and checks its own work).
 void launch_round(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena& spill, int big_grid,
-                  hipStream_t s, hipEvent_t* ev_big);
+                  hipStream_t s, hipEvent_t* ev_big, const int32_t* n_cur);
 void launch_assign_live(PeelBuffers& pb, int cur_live, int32_t n_live, int32_t label, hipStream_t s);
 // One graph's part of a fine-grained launch.
 struct FdJob {
