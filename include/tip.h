@@ -71,6 +71,11 @@ typedef struct {
  * form; same results, for comparison. */
 #define TIP_FLAG_BATCH_PLAIN 4
 
+/* TIP_FLAG_NO_COMPACT: never remove peeled vertices from the adjacency
+ * lists the coarse-grained update traverses (Dynamic Graph Maintenance
+ * section; on by default).  Same results, more wedges traversed. */
+#define TIP_FLAG_NO_COMPACT 8
+
 /* Options.  Zero-initialised means defaults. */
 typedef struct {
     int32_t P;       /* number of tip-number ranges of the coarse-grained step
@@ -83,8 +88,12 @@ typedef struct {
                         kernel when w > tune[1] and w > n_side * bits(d) /
                         tune[0] (bits(d) = 2, 4, 8, 16 for d <= 3, 15, 255,
                         65535), else by a per-vertex kernel;
-                        tune[0]: 0 = 64; tune[1]: 0 = 32768; both >= 0;
-                        tune[2..7] reserved, must be 0 */
+                        tune[0]: 0 = 64; tune[1]: 0 = 32768;
+                        tune[2]: compaction of the traversed lists at a
+                        range start once the entries of vertices peeled
+                        since the last compaction reach tune[2] per mille of
+                        the entries left (0 = 125);
+                        tune[0..2] >= 0; tune[3..7] reserved, must be 0 */
 } tip_opts;
 
 /* Work and time accounting of one decomposition (NULL = not wanted). */

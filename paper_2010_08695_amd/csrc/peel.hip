@@ -154,7 +154,9 @@ struct ItemKeys {
 };
 
 __global__ void k_peel_bins(const int64_t* __restrict__ a_off, const int64_t* __restrict__ wprox, int32_t n_a,
-                            int64_t dense_div, int64_t bm_max, ItemKeys ik, uint8_t* bin) {
+                            int64_t dense_div, int64_t bm_max, ItemKeys ik, const Ctl* ctl, uint8_t* bin) {
+    // keys the update can touch: all of side A, or below the live bound
+    const int64_t nk = ctl ? max<int64_t>(1, ctl->key_hi) : max<int32_t>(1, n_a);
     GRID_STRIDE(u, (int64_t)n_a) {
         const int64_t w = wprox[u];
         const int64_t d = a_off[u + 1] - a_off[u];
@@ -162,8 +164,8 @@ __global__ void k_peel_bins(const int64_t* __restrict__ a_off, const int64_t* __
         uint8_t b = kBinBitmap;
         if (w <= kSmallMaxWedges) {
             b = kBinWave;
-        } else if (bits && w > max<int64_t>(bm_max, (int64_t)n_a * bits / dense_div)) {
-            const bool heavy = (double)w * (double)ik.k[dense_kind(bits)] > (double)kItemWedges * (double)n_a;
+        } else if (bits && w > max<int64_t>(bm_max, nk * bits / dense_div)) {
+            const bool heavy = (double)w * (double)ik.k[dense_kind(bits)] > (double)kItemWedges * (double)nk;
             b = (uint8_t)dense_bin(bits, heavy);
         }
         bin[u] = b;
@@ -319,7 +321,8 @@ __device__ inline void append_binned(bool pred, int32_t u, uint8_t b, const Fron
 // nothing to do when the round's activeSet was empty).
 __global__ void k_frontier_scan(FrontSet fs, const int32_t* live0, const int32_t* live1,
                                 const int64_t* __restrict__ supp, int32_t* state, const int64_t* __restrict__ wprox,
-                                const uint8_t* __restrict__ bin, int next, Ctl* ctl) {
+                                const uint8_t* __restrict__ bin, const int64_t* __restrict__ a_off, int next,
+                                Ctl* ctl) {
     if (next) {
         int32_t any = 0;
 #pragma unroll
@@ -336,7 +339,7 @@ __global__ void k_frontier_scan(FrontSet fs, const int32_t* live0, const int32_t
     for (int b = 0; b < kBins; ++b) fr.list[b] = fs.list[buf][b];
     fr.count = next ? ctl->n_next : ctl->n_front;
     long long ws = 0;
-    unsigned long long skipped = 0;
+    unsigned long long skipped = 0, dead = 0;
     UNIFORM_STRIDE(base, (int64_t)n_live) {
         const int64_t j = base + threadIdx.x;
         bool pred = false;
@@ -348,6 +351,7 @@ __global__ void k_frontier_scan(FrontSet fs, const int32_t* live0, const int32_t
             if (su < hi && state[u] == kLive) {
                 state[u] = label;
                 ws += wprox[u];
+                dead += (unsigned long long)(a_off[u + 1] - a_off[u]);
                 if (su == 0) ++skipped;
                 else {
                     pred = true;
@@ -359,9 +363,11 @@ __global__ void k_frontier_scan(FrontSet fs, const int32_t* live0, const int32_t
     }
     ws = wave_sum_i64(ws);
     skipped = (unsigned long long)wave_sum_i64((int64_t)skipped);
+    dead = (unsigned long long)wave_sum_i64((int64_t)dead);
     if ((threadIdx.x & (kWave - 1)) == 0) {
         if (ws) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->w_range), (unsigned long long)ws);
         if (skipped) atomicAdd(&ctl->skipped, skipped);
+        if (dead) atomicAdd(&ctl->dead_edges, dead);
     }
 }
 
@@ -547,6 +553,7 @@ k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t nt
     __syncthreads();
     const Spill sp{spa.dense + (int64_t)blockIdx.x * spa.stride, spa.list + (int64_t)blockIdx.x * spa.stride};
     const int32_t sub = kBmTile / tk;  // table tiles per bitmap tile
+    const int32_t key_hi = ctl->key_hi;
     PeelCounters pc;
     for (;;) {
         const int64_t it = next_item(L.st, &ctl->head[kBinBitmap]);
@@ -558,8 +565,8 @@ k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t nt
         }
         const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
         if (tid == 0) pc.edges += (unsigned long long)d;
-        for (int32_t klo = 0; klo < g.n_a; klo += kBmTile) {
-            const int32_t khi = (int32_t)min<int64_t>(g.n_a, (int64_t)klo + kBmTile);
+        for (int32_t klo = 0; klo < key_hi; klo += kBmTile) {
+            const int32_t khi = (int32_t)min<int64_t>(key_hi, (int64_t)klo + kBmTile);
             const int32_t t0 = klo / tk, t1 = min(t0 + sub, ntt);
             for (int64_t g0 = 0; g0 < d; g0 += kBmRuns) {
                 const int gs = (int)min<int64_t>(kBmRuns, d - g0);
@@ -650,6 +657,10 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
     constexpr int BL = 2 + 2 * (BITS == 2 ? 0 : BITS == 4 ? 1 : BITS == 8 ? 2 : 3), BH = BL + 1;
     const int32_t n_l = ctl->n_front[BL], n_h = ctl->n_front[BH];
     if (n_l + n_h == 0) return;
+    // only tiles below the live key bound can hold a key to update; ntt
+    // itself stays the row stride of the tile-bound table
+    const int32_t ntk = min(ntt, (int32_t)((max(ctl->key_hi, 1) + (int64_t)tk - 1) / tk));
+    g_max = min(g_max, ntk);
     const int32_t* __restrict__ front_l = fs.list[ctl->front_buf][BL];
     const int32_t* __restrict__ front_h = fs.list[ctl->front_buf][BH];
     // light items span gl tiles, heavy ones gh = gl / kHeavySplit; gl is
@@ -657,7 +668,7 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
     // per resident workgroup
     const auto n_items_of = [&](int32_t l) {
         const int32_t h = max(1, l / kHeavySplit);
-        return (int64_t)n_l * ((ntt + l - 1) / l) + (int64_t)n_h * ((ntt + h - 1) / h);
+        return (int64_t)n_l * ((ntk + l - 1) / l) + (int64_t)n_h * ((ntk + h - 1) / h);
     };
     int32_t gl = g_max;
     while (gl > 1 && n_items_of(gl) < 4 * slots) gl = (gl + 1) / 2;
@@ -674,7 +685,7 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
         for (int w = tid; w < n4; w += NT) cnt4[w] = make_uint4(0, 0, 0, 0);
     }
     __syncthreads();
-    const int32_t ngh = (ntt + gh - 1) / gh, ngl = (ntt + gl - 1) / gl;
+    const int32_t ngh = (ntk + gh - 1) / gh, ngl = (ntk + gl - 1) / gl;
     const int64_t n_heavy_items = (int64_t)n_h * ngh;
     const int64_t n_items = n_heavy_items + (int64_t)n_l * ngl;
     PeelCounters pc;
@@ -685,12 +696,12 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
         if (it < n_heavy_items) {
             u = front_h[it / ngh];
             t_begin = (int32_t)(it % ngh) * gh;
-            t_end = min(ntt, t_begin + gh);
+            t_end = min(ntk, t_begin + gh);
         } else {
             const int64_t r = it - n_heavy_items;
             u = front_l[r / ngl];
             t_begin = (int32_t)(r % ngl) * gl;
-            t_end = min(ntt, t_begin + gl);
+            t_end = min(ntk, t_begin + gl);
         }
         if (ap.supp[u] == 0) {
             pc.skipped += (tid == 0 && t_begin == 0);
@@ -793,6 +804,124 @@ __global__ void k_assign_live(const int32_t* __restrict__ live, int32_t n_live, 
     GRID_STRIDE(j, (int64_t)n_live) state[live[j]] = label;
 }
 
+// ---------------------------------------------------------------------------
+// List compaction (DGM): vertices that are no longer live are removed from
+// the lists the coarse-grained update traverses.  c(u, w) for live w is
+// unchanged, so results are too; only dead entries stop being read.
+// ---------------------------------------------------------------------------
+
+__global__ void k_dgm_flags(const int32_t* __restrict__ adj, int64_t n, const int32_t* __restrict__ state,
+                            int64_t* flag) {
+    GRID_STRIDE(q, n) flag[q] = state[adj[q]] == kLive ? 1 : 0;
+}
+
+__global__ void k_dgm_scatter(const int32_t* __restrict__ adj, const int32_t* __restrict__ row, int64_t n,
+                              const int64_t* __restrict__ flag, const int64_t* __restrict__ pos, int32_t* nadj,
+                              int32_t* nrow) {
+    GRID_STRIDE(q, n) {
+        if (flag[q]) {
+            nadj[pos[q]] = adj[q];
+            nrow[pos[q]] = row[q];
+        }
+    }
+}
+
+// New offsets; the new entry count goes to ctl->cd_m and the dead-entry
+// counter restarts.
+__global__ void k_dgm_offsets(const int64_t* __restrict__ off, int32_t n_b, int64_t n, const int64_t* __restrict__ flag,
+                              const int64_t* __restrict__ pos, int64_t* noff, Ctl* ctl) {
+    const int64_t total = n > 0 ? pos[n - 1] + flag[n - 1] : 0;
+    GRID_STRIDE(v, (int64_t)n_b + 1) {
+        const int64_t o = off[v];
+        noff[v] = o < n ? pos[o] : total;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->cd_m = total;
+        ctl->dead_edges = 0;
+    }
+}
+
+// Tile bounds of the compacted lists without searching: entry q of N_v is
+// the first entry >= t * tk for every tile t after the previous entry's
+// tile, up to its own.
+__global__ void k_dgm_tiles(const int64_t* __restrict__ off, const int32_t* __restrict__ adj,
+                            const int32_t* __restrict__ row, const long long* n_p, int32_t tk, int32_t ntt,
+                            int32_t* tb) {
+    const int64_t n = *n_p;
+    GRID_STRIDE(q, n) {
+        const int32_t v = row[q];
+        const int64_t o = off[v];
+        const int32_t t = adj[q] / tk;
+        const int32_t tp = q == o ? -1 : adj[q - 1] / tk;
+        int32_t* r = tb + (int64_t)v * (ntt + 1);
+        for (int32_t x = tp + 1; x <= t; ++x) r[x] = (int32_t)(q - o);
+    }
+}
+
+// Tiles after a list's last entry (every tile of an empty list) point to its end.
+__global__ void k_dgm_tiles_tail(const int64_t* __restrict__ off, const int32_t* __restrict__ adj, int32_t n_b,
+                                 int32_t tk, int32_t ntt, int32_t* tb) {
+    const int64_t tot = (int64_t)n_b * (ntt + 1);
+    GRID_STRIDE(i, tot) {
+        const int64_t v = i / (ntt + 1);
+        const int32_t t = (int32_t)(i % (ntt + 1));
+        const int64_t lo = off[v], hi = off[v + 1];
+        const int32_t tl = hi > lo ? adj[hi - 1] / tk : -1;
+        if (t > tl) tb[i] = (int32_t)(hi - lo);
+    }
+}
+
+// Wedges of each u over the current CD lists (u's own entry excluded): a
+// wave-level segmented sum over the CSR positions (rows are contiguous), one
+// atomic per row segment of a wave.  wlive must be zero.
+__global__ void k_wlive(const int32_t* __restrict__ a_row, const int32_t* __restrict__ a_adj, int64_t m,
+                        const int64_t* __restrict__ cd_off, int64_t* wlive) {
+    const int lane = threadIdx.x & (kWave - 1);
+    UNIFORM_STRIDE(base, m) {
+        const int64_t p = base + threadIdx.x;
+        int32_t u = -1;
+        int64_t x = 0;
+        if (p < m) {
+            u = a_row[p];
+            const int32_t v = a_adj[p];
+            const int64_t l = cd_off[v + 1] - cd_off[v];
+            x = l > 1 ? l - 1 : 0;
+        }
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int64_t y = __shfl_up(x, d, kWave);
+            const int32_t uy = __shfl_up(u, d, kWave);
+            if (lane >= d && uy == u) x += y;
+        }
+        const int32_t un = __shfl_down(u, 1, kWave);
+        if (u >= 0 && (lane == kWave - 1 || un != u) && x) atomic_add_i64(&wlive[u], x);
+    }
+}
+
+__global__ void k_set_key_hi(Ctl* ctl, int32_t v) { ctl->key_hi = v; }
+
+// Largest live rank + 1: every key the update can still touch is below it.
+__global__ void k_key_hi(const int32_t* __restrict__ state, int32_t n_a, Ctl* ctl) {
+    int32_t hi = 0;
+    GRID_STRIDE(u, (int64_t)n_a)
+        if (state[u] == kLive) hi = (int32_t)u + 1;
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) hi = max(hi, __shfl_xor(hi, d, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0 && hi) atomicMax(&ctl->key_hi, hi);
+}
+
+__global__ void k_set_cd_m(Ctl* ctl, long long m, int32_t n_a) {
+    ctl->cd_m = m;
+    ctl->dead_edges = 0;
+    ctl->key_hi = n_a;
+}
+
+ItemKeys item_keys(const PeelBuffers& pb) {
+    ItemKeys ik;
+    for (int k = 0; k < kDenseKinds; ++k) ik.k[k] = (int64_t)dense_item_tiles(2 << k, pb.tk, pb.ntt) * pb.tk;
+    return ik;
+}
+
 FrontSet front_set(PeelBuffers& pb) {
     FrontSet f;
     for (int i = 0; i < 2; ++i)
@@ -808,7 +937,7 @@ int peel_occupancy() {
     return std::max(1, a);
 }
 
-void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers& pb, const Tune& tune,
+void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers& pb, const Tune& tune, Ctl* ctl,
                        hipStream_t s) {
     fill_i64(pb.wprox, 0, g.n_a, s);
     // the select histogram is cleared after every use, so it starts cleared
@@ -818,16 +947,59 @@ void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers
         TIP_HIP_TRY(hipGetLastError());
     }
     if (g.n_a > 0) {
-        ItemKeys ik;
-        for (int k = 0; k < kDenseKinds; ++k)
-            ik.k[k] = (int64_t)dense_item_tiles(2 << k, pb.tk, pb.ntt) * pb.tk;
-        k_peel_bins<<<grid1(g.n_a), kT, 0, s>>>(g.a_off, pb.wprox, g.n_a, tune.dense_div, tune.bitmap_max, ik,
-                                                pb.bin);
+        k_peel_bins<<<grid1(g.n_a), kT, 0, s>>>(g.a_off, pb.wprox, g.n_a, tune.dense_div, tune.bitmap_max,
+                                                item_keys(pb), nullptr, pb.bin);
         TIP_HIP_TRY(hipGetLastError());
+        TIP_HIP_TRY(hipMemcpyAsync(pb.wlive, pb.wprox, sizeof(int64_t) * g.n_a, hipMemcpyDeviceToDevice, s));
     }
+    // the CD lists start as a copy of the CSC
+    TIP_HIP_TRY(hipMemcpyAsync(pb.cd_off, g.b_off, sizeof(int64_t) * ((size_t)g.n_b + 1), hipMemcpyDeviceToDevice, s));
+    if (g.m > 0) {
+        TIP_HIP_TRY(hipMemcpyAsync(pb.cd_adj, g.b_adj, sizeof(int32_t) * g.m, hipMemcpyDeviceToDevice, s));
+        TIP_HIP_TRY(hipMemcpyAsync(pb.cd_row, g.b_row, sizeof(int32_t) * g.m, hipMemcpyDeviceToDevice, s));
+    }
+    k_set_cd_m<<<1, 1, 0, s>>>(ctl, (long long)g.m, g.n_a);
+    TIP_HIP_TRY(hipGetLastError());
     const int64_t n_tb = (int64_t)g.n_b * (pb.ntt + 1);
     if (n_tb > 0) {
         k_tile_bounds<<<grid1(n_tb), kT, 0, s>>>(g.b_off, g.b_adj, g.n_b, pb.tk, pb.ntt, pb.tb);
+        TIP_HIP_TRY(hipGetLastError());
+    }
+}
+
+void launch_compact(const DevGraph& g, PeelBuffers& pb, const CompactScratch& cs, int64_t cd_m, const Tune& tune,
+                    Ctl* ctl, hipStream_t s) {
+    if (cd_m <= 0) return;
+    k_dgm_flags<<<grid1(cd_m), kT, 0, s>>>(pb.cd_adj, cd_m, pb.state, cs.flag);
+    TIP_HIP_TRY(hipGetLastError());
+    scan_exclusive_i64(cs.flag, cs.pos, cd_m, cs.scan_tmp, s);
+    k_dgm_scatter<<<grid1(cd_m), kT, 0, s>>>(pb.cd_adj, pb.cd_row, cd_m, cs.flag, cs.pos, cs.adj, cs.row);
+    TIP_HIP_TRY(hipGetLastError());
+    k_dgm_offsets<<<grid1((int64_t)g.n_b + 1), kT, 0, s>>>(pb.cd_off, g.n_b, cd_m, cs.flag, cs.pos, pb.cd_tmp_off,
+                                                           ctl);
+    TIP_HIP_TRY(hipGetLastError());
+    // back to the fixed addresses the (possibly graph-captured) rounds read
+    TIP_HIP_TRY(hipMemcpyAsync(pb.cd_adj, cs.adj, sizeof(int32_t) * cd_m, hipMemcpyDeviceToDevice, s));
+    TIP_HIP_TRY(hipMemcpyAsync(pb.cd_row, cs.row, sizeof(int32_t) * cd_m, hipMemcpyDeviceToDevice, s));
+    TIP_HIP_TRY(hipMemcpyAsync(pb.cd_off, pb.cd_tmp_off, sizeof(int64_t) * ((size_t)g.n_b + 1),
+                               hipMemcpyDeviceToDevice, s));
+    k_dgm_tiles<<<grid1(cd_m), kT, 0, s>>>(pb.cd_off, pb.cd_adj, pb.cd_row, &ctl->cd_m, pb.tk, pb.ntt, pb.tb);
+    TIP_HIP_TRY(hipGetLastError());
+    const int64_t n_tb = (int64_t)g.n_b * (pb.ntt + 1);
+    if (n_tb > 0) {
+        k_dgm_tiles_tail<<<grid1(n_tb), kT, 0, s>>>(pb.cd_off, pb.cd_adj, g.n_b, pb.tk, pb.ntt, pb.tb);
+        TIP_HIP_TRY(hipGetLastError());
+    }
+    if (g.n_a > 0) {
+        fill_i64(pb.wlive, 0, g.n_a, s);
+        k_wlive<<<grid1(g.m, 8192), kT, 0, s>>>(g.a_row, g.a_adj, g.m, pb.cd_off, pb.wlive);
+        TIP_HIP_TRY(hipGetLastError());
+        k_set_key_hi<<<1, 1, 0, s>>>(ctl, 0);
+        TIP_HIP_TRY(hipGetLastError());
+        k_key_hi<<<grid1(g.n_a, 2048), kT, 0, s>>>(pb.state, g.n_a, ctl);
+        TIP_HIP_TRY(hipGetLastError());
+        k_peel_bins<<<grid1(g.n_a), kT, 0, s>>>(g.a_off, pb.wlive, g.n_a, tune.dense_div, tune.bitmap_max,
+                                                item_keys(pb), ctl, pb.bin);
         TIP_HIP_TRY(hipGetLastError());
     }
 }
@@ -857,13 +1029,13 @@ void launch_select(PeelBuffers& pb, int cur_live, int32_t n_live, uint64_t max_s
     }
 }
 
-void launch_range_begin(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi, int32_t label, Ctl* ctl,
-                        hipStream_t s) {
+void launch_range_begin(const DevGraph& g, PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi,
+                        int32_t label, Ctl* ctl, hipStream_t s) {
     k_set_range<<<1, 1, 0, s>>>(ctl, (long long)hi, label, cur_live, n_live);
     TIP_HIP_TRY(hipGetLastError());
     if (n_live <= 0) return;
     k_frontier_scan<<<grid1(n_live, 4096), kT, 0, s>>>(front_set(pb), pb.live[0], pb.live[1], pb.supp, pb.state,
-                                                        pb.wprox, pb.bin, 0, ctl);
+                                                        pb.wprox, pb.bin, g.a_off, 0, ctl);
     TIP_HIP_TRY(hipGetLastError());
 }
 
@@ -872,28 +1044,32 @@ void launch_round(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena
     const CdApply ap{pb.supp, pb.state};
     const FrontSet fs = front_set(pb);
     if (g.n_a <= 0) return;
+    // the update traverses the CD copy of the lists N_v
+    DevGraph gc = g;
+    gc.b_off = pb.cd_off;
+    gc.b_adj = pb.cd_adj;
     // grids are fixed; every kernel reads its work from the control block and
     // returns at once when it has none.  With the frontier sizes known on the
     // host (n_cur), kernels without work are not launched at all.
     const auto has = [&](int b) { return !n_cur || n_cur[b] > 0; };
     if (has(kBinWave)) {
-        k_peel_wave<<<2048, kSmallThreads, 0, s>>>(g, fs, pb.wprox, ap, ctl);
+        k_peel_wave<<<2048, kSmallThreads, 0, s>>>(gc, fs, pb.wlive, ap, ctl);
         TIP_HIP_TRY(hipGetLastError());
     }
     if (has(kBinBitmap)) {
         if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[0], s));
-        k_peel_bitmap<<<std::min(big_grid, spill.slots), kBigThreads, 0, s>>>(g, pb.tb, pb.tk, pb.ntt, fs, ap,
+        k_peel_bitmap<<<std::min(big_grid, spill.slots), kBigThreads, 0, s>>>(gc, pb.tb, pb.tk, pb.ntt, fs, ap,
                                                                                spill, ctl);
         TIP_HIP_TRY(hipGetLastError());
         if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[1], s));
     }
     // heavier counter widths first: their vertices have the most wedges
-    if (has(dense_bin(16, false)) || has(dense_bin(16, true))) launch_dense<16>(g, pb, fs, ap, ctl, s);
-    if (has(dense_bin(8, false)) || has(dense_bin(8, true))) launch_dense<8>(g, pb, fs, ap, ctl, s);
-    if (has(dense_bin(4, false)) || has(dense_bin(4, true))) launch_dense<4>(g, pb, fs, ap, ctl, s);
-    if (has(dense_bin(2, false)) || has(dense_bin(2, true))) launch_dense<2>(g, pb, fs, ap, ctl, s);
+    if (has(dense_bin(16, false)) || has(dense_bin(16, true))) launch_dense<16>(gc, pb, fs, ap, ctl, s);
+    if (has(dense_bin(8, false)) || has(dense_bin(8, true))) launch_dense<8>(gc, pb, fs, ap, ctl, s);
+    if (has(dense_bin(4, false)) || has(dense_bin(4, true))) launch_dense<4>(gc, pb, fs, ap, ctl, s);
+    if (has(dense_bin(2, false)) || has(dense_bin(2, true))) launch_dense<2>(gc, pb, fs, ap, ctl, s);
     k_frontier_scan<<<grid1(g.n_a, 4096), kT, 0, s>>>(fs, pb.live[0], pb.live[1], pb.supp, pb.state, pb.wprox,
-                                                       pb.bin, 1, ctl);
+                                                       pb.bin, g.a_off, 1, ctl);
     TIP_HIP_TRY(hipGetLastError());
     k_ctl_swap_front<<<1, 1, 0, s>>>(ctl);
     TIP_HIP_TRY(hipGetLastError());

@@ -81,6 +81,11 @@ void plan(Arena& ar, int32_t n_a, int32_t n_b, int64_t m, int32_t P, int slots, 
     w.pb.tk = dense_tile_keys(na);
     w.pb.ntt = (int32_t)((na + w.pb.tk - 1) / w.pb.tk);
     w.pb.tb = ar.take<int32_t>(nb * (w.pb.ntt + 1));
+    w.pb.cd_off = ar.take<int64_t>(nb + 1);
+    w.pb.cd_adj = ar.take<int32_t>(mm);
+    w.pb.cd_row = ar.take<int32_t>(mm);
+    w.pb.cd_tmp_off = ar.take<int64_t>(nb + 1);
+    w.pb.wlive = ar.take<int64_t>(na);
     w.fb.fd_vert = ar.take<int32_t>(na);
     w.fb.fd_pos = ar.take<int32_t>(na);
     w.fb.sub_off = ar.take<int64_t>(S + 1);
@@ -320,7 +325,8 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
     } else {
         // Coarse-grained decomposition (Alg. 3).
         PeelBuffers& pb = w.pb;
-        launch_peel_setup(g, w.aux.deg_b, pb, tune, s);
+        launch_peel_setup(g, w.aux.deg_b, pb, tune, w.ctl, s);
+        const CompactScratch cscr{w.ib.flags, reinterpret_cast<int64_t*>(w.ib.keys), w.ib.scan_tmp, w.ib.ea, w.ib.eb};
         fill_i32(pb.state, kLive, n_a, s);
         iota_i32(pb.live[0], n_a, s);
         int cur_live = 0;
@@ -336,6 +342,11 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
             n_live = c0.n_live_next;
             cur_live ^= 1;
             if (n_live == 0) break;
+            // DGM: drop the vertices of finished ranges from the CD lists once
+            // they hold enough of the remaining entries
+            if (tune.compact_permille > 0 && c0.dead_edges > 0 &&
+                (double)c0.dead_edges * 1000.0 >= (double)c0.cd_m * (double)tune.compact_permille)
+                launch_compact(g, pb, cscr, c0.cd_m, tune, w.ctl, s);
             const uint64_t max_supp = c0.max_supp;
             const long long w_rem = c0.w_rem;
             // adaptive target: remaining wedges over remaining subsets,
@@ -351,7 +362,7 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
                 hi = c1.sel_found ? (int64_t)c1.sel_prefix + 1 : (int64_t)max_supp + 1;
             }
             bounds.push_back(hi);
-            launch_range_begin(pb, cur_live, n_live, hi, label, w.ctl, s);
+            launch_range_begin(g, pb, cur_live, n_live, hi, label, w.ctl, s);
             for (;;) {
                 const Ctl& c2 = read_ctl(w, s);
                 int32_t n_cur[kBins];
@@ -508,12 +519,12 @@ void check_edges(const tip_edges* g) {
 int32_t check_opts(const tip_opts* opt) {
     if (!opt) return kDefaultP;
     if (opt->P < 0 || opt->P > kMaxP) throw InvalidArg("P must be in [0, 65535]");
-    if (opt->flags & ~(TIP_FLAG_TIME_KERNELS | TIP_FLAG_NO_GRAPH | TIP_FLAG_BATCH_PLAIN))
+    if (opt->flags & ~(TIP_FLAG_TIME_KERNELS | TIP_FLAG_NO_GRAPH | TIP_FLAG_BATCH_PLAIN | TIP_FLAG_NO_COMPACT))
         throw InvalidArg("unknown flag bits");
-    if (opt->tune[0] < 0) throw InvalidArg("tune[0] must be >= 0");
-    if (opt->tune[1] < 0) throw InvalidArg("tune[1] must be >= 0");
-    for (int i = 2; i < 8; ++i)
-        if (opt->tune[i] != 0) throw InvalidArg("tune[2..7] must be 0");
+    for (int i = 0; i < 3; ++i)
+        if (opt->tune[i] < 0) throw InvalidArg("tune[0..2] must be >= 0");
+    for (int i = 3; i < 8; ++i)
+        if (opt->tune[i] != 0) throw InvalidArg("tune[3..7] must be 0");
     return opt->P == 0 ? kDefaultP : opt->P;
 }
 
@@ -521,6 +532,8 @@ Tune tune_of(const tip_opts* opt) {
     Tune t;
     if (opt && opt->tune[0] > 0) t.dense_div = opt->tune[0];
     if (opt && opt->tune[1] > 0) t.bitmap_max = opt->tune[1];
+    if (opt && opt->tune[2] > 0) t.compact_permille = opt->tune[2];
+    if (opt && (opt->flags & TIP_FLAG_NO_COMPACT)) t.compact_permille = 0;
     return t;
 }
 

@@ -44,6 +44,10 @@ constexpr int kApplyBatch = 4;             // (key, c) pairs a lane gathers befo
 constexpr int kDenseBatch = 8;             // the same in the dense kernel
 constexpr int64_t kItemWedges = 16384;     // a dense item of a light vertex has at most about this many wedges
 constexpr int kHeavySplit = 8;
+// CD lists are compacted at a range start once the entries of vertices
+// assigned since the last compaction reach this share (per mille) of the
+// entries left (tip_opts.tune[2]).
+constexpr int64_t kDefaultCompactPermille = 125;
 
 // Counter width (bits) of the dense kernel for a vertex of degree d: c(u, w)
 // <= d_u must fit; 0 = too wide for the dense kernel.

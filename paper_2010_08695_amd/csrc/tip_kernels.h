@@ -33,6 +33,10 @@ struct Ctl {
     unsigned long long big_edges;
     unsigned long long big_pairs;
     unsigned long long head[kBins];  // next work item of each update kernel in the current round
+    unsigned long long dead_edges;   // list entries of vertices assigned since the last compaction
+    long long cd_m;                  // entries left in the CD lists
+    int32_t key_hi;                  // every live vertex of side A has a rank below this
+    int32_t pad2;
     // Range state read by the round kernels, so that a sequence of rounds
     // can be launched (or replayed from a graph) without host arguments.
     long long range_hi;      // upper bound of the current range
@@ -60,9 +64,27 @@ struct PeelBuffers {
     int32_t* front[2][kBins];  // [buffer][bin] frontier lists
     int64_t* sel_hist;   // [256]
     uint8_t* bin;        // [n_a] update kernel of each vertex
-    int32_t* tb;         // [n_b * (ntt + 1)] tile bounds of every list of the other side
+    int32_t* tb;         // [n_b * (ntt + 1)] tile bounds of every CD list
     int32_t tk;          // keys per tile (dense_tile_keys(n_a))
     int32_t ntt;         // number of tiles of side A
+    // The lists N_v the coarse-grained update traverses: a copy of the CSC
+    // from which peeled vertices are periodically removed (DGM); the CSC
+    // itself stays whole for the fine-grained step.
+    int64_t* cd_off;     // [n_b + 1]
+    int32_t* cd_adj;     // [m]
+    int32_t* cd_row;     // [m]
+    int64_t* cd_tmp_off; // [n_b + 1] compaction scratch
+    int64_t* wlive;      // [n_a] wedges of u over the CD lists (selects u's update kernel)
+};
+
+// Scratch borrowed from the ingest buffers (idle during the coarse-grained
+// step) by the list compaction.
+struct CompactScratch {
+    int64_t* flag;       // [m]
+    int64_t* pos;        // [m]
+    int64_t* scan_tmp;
+    int32_t* adj;        // [m]
+    int32_t* row;        // [m]
 };
 
 struct FdBuffers {
@@ -87,20 +109,28 @@ struct FdBuffers {
 struct Tune {
     int64_t dense_div = kDefaultDenseDiv;
     int64_t bitmap_max = kDefaultBitmapMax;
+    int64_t compact_permille = kDefaultCompactPermille;  // 0: never compact
 };
 
 // counting
 void launch_count(const DevGraph& g, CountBuffers& cb, Ctl* ctl, const SpillArena& spill, int big_grid,
                   hipStream_t s);
 // CD
-void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers& pb, const Tune& tune,
+void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers& pb, const Tune& tune, Ctl* ctl,
                        hipStream_t s);
 void launch_range_start(PeelBuffers& pb, int cur_live, int32_t n_live, Ctl* ctl, hipStream_t s);
+// Removes every vertex that is no longer live from the CD lists (DGM),
+// rebuilds their tile bounds and re-selects the update kernel of every live
+// vertex from its wedges over the compacted lists.  cd_m: entries before;
+// the count after is left in ctl->cd_m.  Range bounds keep using the
+// original wedge proxy, so the partition does not depend on compaction.
+void launch_compact(const DevGraph& g, PeelBuffers& pb, const CompactScratch& cs, int64_t cd_m, const Tune& tune,
+                    Ctl* ctl, hipStream_t s);
 void launch_select(PeelBuffers& pb, int cur_live, int32_t n_live, uint64_t max_supp, int64_t tgt, Ctl* ctl,
                    hipStream_t s);
 // Sets the range state and builds the range's first activeSet.
-void launch_range_begin(PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi, int32_t label, Ctl* ctl,
-                        hipStream_t s);
+void launch_range_begin(const DevGraph& g, PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi,
+                        int32_t label, Ctl* ctl, hipStream_t s);
 // One coarse-grained round, driven entirely by the control block: update
 // kernels over the current activeSet, then the next activeSet and the buffer
 // swap.  Fixed grids, no host synchronisation, so it can be graph-captured.

@@ -22,6 +22,7 @@ TIP_OK, TIP_EINVAL, TIP_ENOMEM, TIP_EDEVICE, TIP_EOVERFLOW, TIP_EBUSY = 0, -1, -
 TIP_FLAG_TIME_KERNELS = 1
 TIP_FLAG_NO_GRAPH = 2
 TIP_FLAG_BATCH_PLAIN = 4
+TIP_FLAG_NO_COMPACT = 8
 SIDE_U, SIDE_V = 0, 1
 STATUS_NAMES = {0: "TIP_OK", -1: "TIP_EINVAL", -2: "TIP_ENOMEM", -3: "TIP_EDEVICE",
                 -4: "TIP_EOVERFLOW", -5: "TIP_EBUSY"}
@@ -167,7 +168,7 @@ def decompose(g, side: int = SIDE_U, P: int = 0, with_stats: bool = False, flags
     return (theta, st.to_dict()) if with_stats else theta
 
 
-def decompose_ex(g, side: int = SIDE_U, P: int = 0, flags: int = 0) -> dict:
+def decompose_ex(g, side: int = SIDE_U, P: int = 0, flags: int = 0, tune=None) -> dict:
     """Tip numbers plus the coarse-grained state (subsets, initial supports, bounds)."""
     lib = load()
     e, keep = _edges(g)
@@ -179,7 +180,7 @@ def decompose_ex(g, side: int = SIDE_U, P: int = 0, flags: int = 0) -> dict:
     bounds = np.zeros(Pe + 2, np.int64)
     ns = np.zeros(1, np.int32)
     st = Stats()
-    o = _opts(P, flags)
+    o = _opts(P, flags, 0, tune)
     _check(lib, lib.tip_decompose_ex(ctypes.byref(e), int(side), _ptr(theta), ctypes.byref(o),
                                      ctypes.byref(st), _ptr(subset), _ptr(init), _ptr(bounds), _ptr(ns)))
     k = int(ns[0])

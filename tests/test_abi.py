@@ -91,10 +91,13 @@ def test_decompose_rejects_bad_arguments(lib):
     o.P = 70000
     _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
     o = tip.Opts()
-    o.flags = 8                                   # no such flag
+    o.flags = 16                                  # no such flag
     _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
     o = tip.Opts()
     o.tune[1] = -1
+    _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
+    o = tip.Opts()
+    o.tune[2] = -5
     _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
     o = tip.Opts()
     o.tune[3] = 2

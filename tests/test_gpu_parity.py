@@ -177,6 +177,31 @@ def test_graph_rounds_match_eager(gpu_lib, P):
     np.testing.assert_array_equal(ex_graph["bounds"], ex_eager["bounds"])
 
 
+@pytest.mark.parametrize("permille", [0, 1, 500])
+def test_list_compaction_changes_nothing_but_work(gpu_lib, permille):
+    """Removing peeled vertices from the traversed lists (DGM) leaves the tip
+    numbers, the range partition and the per-range supports unchanged and
+    only lowers the coarse-grained wedge count; permille 1 compacts at
+    almost every range start."""
+    g = gg.chung_lu(8000, 1500, 90000, 2.2, 2.0, seed=29)
+    th = oracle.bup(g, 0)[0]
+    tune = [0, 0, permille]
+    ref = tip.decompose_ex(g, 0, flags=tip.TIP_FLAG_NO_COMPACT)
+    got = tip.decompose_ex(g, 0, tune=tune)
+    np.testing.assert_array_equal(ref["theta"], th)
+    np.testing.assert_array_equal(got["theta"], th)
+    np.testing.assert_array_equal(got["subset"], ref["subset"])
+    np.testing.assert_array_equal(got["init"], ref["init"])
+    np.testing.assert_array_equal(got["bounds"], ref["bounds"])
+    _, s0 = tip.decompose(g, 0, with_stats=True, flags=tip.TIP_FLAG_NO_COMPACT)
+    _, s1 = tip.decompose(g, 0, with_stats=True, tune=tune)
+    assert s1["wedges_cd"] < s0["wedges_cd"]
+    assert s1["pair_updates"] == s0["pair_updates"] and s1["rounds"] == s0["rounds"]
+    for side in (0, 1):
+        np.testing.assert_array_equal(tip.decompose(g, side, tune=tune, flags=tip.TIP_FLAG_NO_GRAPH),
+                                      oracle.bup(g, side)[0])
+
+
 def test_batch_matches_single(gpu_lib):
     gs = [gg.chung_lu(800 + 100 * k, 300, 5000 + 500 * k, 2.2, 2.3, seed=200 + k) for k in range(5)]
     sides = [0, 1, 0, 1, 0]
