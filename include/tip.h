@@ -88,7 +88,7 @@ typedef struct {
                         kernel when w > tune[1] and w > n_side * bits(d) /
                         tune[0] (bits(d) = 2, 4, 8, 16 for d <= 3, 15, 255,
                         65535), else by a per-vertex kernel;
-                        tune[0]: 0 = 64; tune[1]: 0 = 32768;
+                        tune[0]: 0 = 256; tune[1]: 0 = 32768;
                         tune[2]: compaction of the traversed lists at a
                         range start once the entries of vertices peeled
                         since the last compaction reach tune[2] per mille of

@@ -43,22 +43,51 @@ __device__ inline int64_t lower_bound_u64(const uint64_t* __restrict__ a, int64_
 }
 
 // For every CSR edge (u, v): the run of N_v inside u's own subset, i.e. the
-// edges of the induced subgraph G_i seen from v (Alg. 4 induced subgraph).
+// edges of the induced subgraph G_i seen from v (Alg. 4 induced subgraph),
+// and the induced wedges per subset (task_w) and per vertex (fd_w).  Subset
+// sums gather in LDS when there are few subsets (lds_tw); per-vertex sums are
+// segmented wave sums over the CSR rows.  Wave-uniform grid-stride loop.
 __global__ void k_fd_slices(DevGraph g, const int32_t* __restrict__ state, const uint64_t* __restrict__ pkeys,
                             int32_t S, const int32_t* __restrict__ fd_pos, int64_t* fd_beg, int32_t* fd_len,
-                            int64_t* task_w, int64_t* fd_w) {
-    GRID_STRIDE(p, g.m) {
-        const int32_t u = g.a_row[p], v = g.a_adj[p];
-        const int32_t s = state[u];
-        const uint64_t k0 = (uint64_t)v * (uint64_t)S + (uint64_t)s;
-        const int64_t lo = lower_bound_u64(pkeys, g.b_off[v], g.b_off[v + 1], k0);
-        const int64_t hi = lower_bound_u64(pkeys, lo, g.b_off[v + 1], k0 + 1);
-        fd_beg[p] = lo;
-        fd_len[p] = (int32_t)(hi - lo);
-        if (hi - lo > 1) {
-            atomic_add_i64(&task_w[s], hi - lo - 1);
-            atomic_add_i64(&fd_w[fd_pos[u]], hi - lo - 1);
+                            int64_t* task_w, int64_t* fd_w, int lds_tw) {
+    extern __shared__ unsigned long long tw[];  // [S] when lds_tw
+    const int lane = threadIdx.x & (kWave - 1);
+    if (lds_tw) {
+        for (int32_t i = threadIdx.x; i < S; i += blockDim.x) tw[i] = 0;
+        __syncthreads();
+    }
+    UNIFORM_STRIDE(base, g.m) {
+        const int64_t p = base + threadIdx.x;
+        int32_t u = -1;
+        int64_t x = 0;
+        if (p < g.m) {
+            u = g.a_row[p];
+            const int32_t v = g.a_adj[p];
+            const int32_t s = state[u];
+            const uint64_t k0 = (uint64_t)v * (uint64_t)S + (uint64_t)s;
+            const int64_t lo = lower_bound_u64(pkeys, g.b_off[v], g.b_off[v + 1], k0);
+            const int64_t hi = lower_bound_u64(pkeys, lo, g.b_off[v + 1], k0 + 1);
+            fd_beg[p] = lo;
+            fd_len[p] = (int32_t)(hi - lo);
+            x = hi - lo > 1 ? hi - lo - 1 : 0;
+            if (x) {
+                if (lds_tw) atomicAdd(&tw[s], (unsigned long long)x);
+                else atomic_add_i64(&task_w[s], x);
+            }
         }
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int64_t y = __shfl_up(x, d, kWave);
+            const int32_t uy = __shfl_up(u, d, kWave);
+            if (lane >= d && uy == u) x += y;
+        }
+        const int32_t un = __shfl_down(u, 1, kWave);
+        if (u >= 0 && (lane == kWave - 1 || un != u) && x) atomic_add_i64(&fd_w[fd_pos[u]], x);
+    }
+    if (lds_tw) {
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < S; i += blockDim.x)
+            if (tw[i]) atomic_add_i64(&task_w[i], (int64_t)tw[i]);
     }
 }
 
@@ -453,8 +482,9 @@ void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t 
         TIP_HIP_TRY(hipGetLastError());
         radix_sort_pairs(fb.pkeys, fb.pcsc, tmp_keys, tmp_vals, g.m,
                          bits_for((uint64_t)g.n_b * (uint64_t)S), hist, scan_tmp, s);
-        k_fd_slices<<<grid1(g.m), kT, 0, s>>>(g, pb.state, fb.pkeys, S, fb.fd_pos, fb.fd_beg, fb.fd_len, fb.task_w,
-                                              fb.fd_w);
+        const int lds_tw = S <= 4096 ? 1 : 0;
+        k_fd_slices<<<grid1(g.m, 2048), kT, lds_tw ? sizeof(unsigned long long) * (size_t)S : 0, s>>>(
+            g, pb.state, fb.pkeys, S, fb.fd_pos, fb.fd_beg, fb.fd_len, fb.task_w, fb.fd_w, lds_tw);
         TIP_HIP_TRY(hipGetLastError());
     }
     k_fd_order<<<1, 1024, 0, s>>>(fb.task_w, S, fb.order);

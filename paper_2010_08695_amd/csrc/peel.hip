@@ -49,7 +49,9 @@ struct Stage {
 
 // Work items of a round are taken from a per-kernel counter, so workgroups
 // that drew cheap items go on to the next instead of idling behind one that
-// drew an expensive one.  All threads of the workgroup must call.
+// drew an expensive one.  (Taking the next index early does not pay: vector
+// memory results return in order, so every later load would wait for it.)
+// All threads of the workgroup must call.
 template <int NT, int NR>
 __device__ inline int64_t next_item(Stage<NT, NR>& S, unsigned long long* head) {
     __syncthreads();
@@ -509,7 +511,7 @@ k_peel_wave(DevGraph g, FrontSet fs, const int64_t* __restrict__ wprox, CdApply 
 struct BmLds {
     uint32_t bm[kBmTile / 32];
     unsigned long long rep[kBmRep];
-    Stage<kBigThreads, kBmRuns> st;
+    Stage<kBmThreads, kBmRuns> st;
     int32_t spill_n;
 };
 
@@ -536,14 +538,14 @@ __device__ inline void bm_rep_insert(BmLds& L, const Spill& sp, uint32_t k) {
     }
 }
 
-__global__ void __launch_bounds__(kBigThreads)
+__global__ void __launch_bounds__(kBmThreads)
 k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, FrontSet fs, CdApply ap,
               SpillArena spa, Ctl* ctl) {
     const int64_t n_front = ctl->n_front[kBinBitmap];
     if (n_front == 0) return;
     const int32_t* __restrict__ front = fs.list[ctl->front_buf][kBinBitmap];
     __shared__ BmLds L;
-    constexpr int NT = kBigThreads;
+    constexpr int NT = kBmThreads;
     constexpr int kPer = kBmRep / NT;  // repeat slots scanned by each thread
     static_assert(kBmRep % NT == 0 && kPer >= 1 && kPer <= 32, "repeat slots per thread");
     const int tid = threadIdx.x;
@@ -551,7 +553,10 @@ k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t nt
     for (int s = tid; s < kBmRep; s += NT) L.rep[s] = 0;
     if (tid == 0) L.spill_n = 0;
     __syncthreads();
-    const Spill sp{spa.dense + (int64_t)blockIdx.x * spa.stride, spa.list + (int64_t)blockIdx.x * spa.stride};
+    // a tile never holds more than min(kBmTile, stride) keys, so workgroups
+    // are packed that far apart in the spill arena
+    const int64_t sp_gap = min<int64_t>(kBmTile, spa.stride);
+    const Spill sp{spa.dense + (int64_t)blockIdx.x * sp_gap, spa.list + (int64_t)blockIdx.x * sp_gap};
     const int32_t sub = kBmTile / tk;  // table tiles per bitmap tile
     const int32_t key_hi = ctl->key_hi;
     PeelCounters pc;
@@ -559,11 +564,12 @@ k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t nt
         const int64_t it = next_item(L.st, &ctl->head[kBinBitmap]);
         if (it >= n_front) break;
         const int32_t u = front[it];
-        if (ap.supp[u] == 0) {
+        const int64_t su = ap.supp[u];
+        const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
+        if (su == 0) {
             pc.skipped += tid == 0;
             continue;
         }
-        const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
         if (tid == 0) pc.edges += (unsigned long long)d;
         for (int32_t klo = 0; klo < key_hi; klo += kBmTile) {
             const int32_t khi = (int32_t)min<int64_t>(key_hi, (int64_t)klo + kBmTile);
@@ -703,12 +709,13 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
             t_begin = (int32_t)(r % ngl) * gl;
             t_end = min(ntk, t_begin + gl);
         }
-        if (ap.supp[u] == 0) {
+        const int64_t su = ap.supp[u];
+        const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
+        if (su == 0) {
             pc.skipped += (tid == 0 && t_begin == 0);
             continue;
         }
         const int32_t klo = t_begin * tk;
-        const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
         if (tid == 0 && t_begin == 0) pc.edges += (unsigned long long)d;
         for (int64_t g0 = 0; g0 < d; g0 += NT) {
             const int gs = (int)min<int64_t>(NT, d - g0);
@@ -933,7 +940,7 @@ FrontSet front_set(PeelBuffers& pb) {
 
 int peel_occupancy() {
     int a = 0;
-    TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_peel_bitmap, kBigThreads, 0));
+    TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_peel_bitmap, kBmThreads, 0));
     return std::max(1, a);
 }
 
@@ -1039,6 +1046,14 @@ void launch_range_begin(const DevGraph& g, PeelBuffers& pb, int cur_live, int32_
     TIP_HIP_TRY(hipGetLastError());
 }
 
+// Resident workgroups of the bitmap-path kernel on the current device.
+int bitmap_grid() {
+    int dev = 0, cus = 0;
+    TIP_HIP_TRY(hipGetDevice(&dev));
+    TIP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    return std::max(1, cus) * peel_occupancy();
+}
+
 void launch_round(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena& spill, int big_grid,
                   hipStream_t s, hipEvent_t* ev_big, const int32_t* n_cur) {
     const CdApply ap{pb.supp, pb.state};
@@ -1058,8 +1073,11 @@ void launch_round(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena
     }
     if (has(kBinBitmap)) {
         if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[0], s));
-        k_peel_bitmap<<<std::min(big_grid, spill.slots), kBigThreads, 0, s>>>(gc, pb.tb, pb.tk, pb.ntt, fs, ap,
-                                                                               spill, ctl);
+        // workgroups the spill arena can hold at the bitmap path's spacing
+        const int64_t gap = std::min<int64_t>(kBmTile, spill.stride);
+        const int64_t fit = (int64_t)spill.slots * (spill.stride / std::max<int64_t>(gap, 1));
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(bitmap_grid(), fit));
+        k_peel_bitmap<<<grid, kBmThreads, 0, s>>>(gc, pb.tb, pb.tk, pb.ntt, fs, ap, spill, ctl);
         TIP_HIP_TRY(hipGetLastError());
         if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[1], s));
     }

@@ -79,6 +79,8 @@ void plan(Arena& ar, int32_t n_a, int32_t n_b, int64_t m, int32_t P, int slots, 
     w.pb.sel_hist = ar.take<int64_t>(256);
     w.pb.bin = ar.take<uint8_t>(na);
     w.pb.tk = dense_tile_keys(na);
+    // the bitmap path walks whole table tiles of at most kBmTile keys
+    if (w.pb.tk > kBmTile) throw InvalidArg("a side with more than 2^28 vertices is not supported");
     w.pb.ntt = (int32_t)((na + w.pb.tk - 1) / w.pb.tk);
     w.pb.tb = ar.take<int32_t>(nb * (w.pb.ntt + 1));
     w.pb.cd_off = ar.take<int64_t>(nb + 1);

@@ -26,6 +26,7 @@ constexpr int kSmallSlots = 1024;          // per-wave hash slots (8 KiB)
 constexpr int64_t kSmallMaxWedges = 448;   // wave path handles <= this many wedges
 
 // Coarse-grained update kernels (see peel.hip).
+constexpr int kBmThreads = 1024;           // threads of the bitmap-path workgroup (one per CU)
 constexpr int kBmTile = 1 << 19;           // keys per bitmap-path tile (64 KiB of bits)
 constexpr int kBmRep = 8192;               // bitmap-path repeat slots (64 KiB)
 constexpr int kBmRuns = 1024;              // neighbour runs staged per pass by the bitmap path
@@ -38,7 +39,7 @@ constexpr int kDenseLdsBytes = 32768;      // counter bytes per dense workgroup 
 constexpr int kDenseKinds = 4;
 constexpr int kBins = 2 + 2 * kDenseKinds;
 constexpr int kBinWave = 0, kBinBitmap = 1;
-constexpr int kDefaultDenseDiv = 64;       // dense needs w[u] > n * bits / div (tip_opts.tune[0])
+constexpr int kDefaultDenseDiv = 256;      // dense needs w[u] > n * bits / div (tip_opts.tune[0])
 constexpr int64_t kDefaultBitmapMax = 32768;  // bitmap path up to this many wedges (tip_opts.tune[1])
 constexpr int kApplyBatch = 4;             // (key, c) pairs a lane gathers before applying them
 constexpr int kDenseBatch = 8;             // the same in the dense kernel
