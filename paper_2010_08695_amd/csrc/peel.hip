@@ -649,147 +649,184 @@ __device__ inline uint32_t ge2_mask(uint32_t x) {
 
 // Dense path: a work item is (frontier vertex, table tiles [t_begin, t_end)):
 // one workgroup counts the 2-hop keys of one vertex inside that key range
-// with one BITS-bit LDS counter per key; the bins guarantee c(u, w) <= d_u
-// fits.  Heavy vertices come first, in items of gh tiles, then light ones in
-// items of gl tiles (gh <= gl).  LDS: gl * tk * BITS / 8 counter bytes
-// (dynamic) + staging.
+// with one BITS-bit LDS counter per key (the bins guarantee c(u, w) <= d_u
+// fits), then applies C(c, 2) for every key with c >= 2.  Counters are all
+// zero between items: an item clears every word it read.
 template <int BITS>
-__global__ void __launch_bounds__(kDenseThreads)
-k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, FrontSet fs, int32_t g_max,
-             int64_t slots, CdApply ap, Ctl* ctl) {
+__device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt,
+                                  int32_t u, int32_t t_begin, int32_t t_end, uint32_t* cnt,
+                                  Stage<kDenseThreads>& S, const CdApply& ap, PeelCounters& pc) {
     constexpr int NT = kDenseThreads;
     constexpr int PER_WORD = 32 / BITS;          // counters per 32-bit word
     constexpr uint32_t FMASK = BITS == 16 ? 0xffffu : ((1u << BITS) - 1);
-    constexpr int BL = 2 + 2 * (BITS == 2 ? 0 : BITS == 4 ? 1 : BITS == 8 ? 2 : 3), BH = BL + 1;
-    const int32_t n_l = ctl->n_front[BL], n_h = ctl->n_front[BH];
-    if (n_l + n_h == 0) return;
+    const int tid = threadIdx.x;
+    uint4* cnt4 = reinterpret_cast<uint4*>(cnt);
+    const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
+    const int32_t klo = t_begin * tk;
+    if (tid == 0 && t_begin == 0) pc.edges += (unsigned long long)d;
+    for (int64_t g0 = 0; g0 < d; g0 += NT) {
+        const int gs = (int)min<int64_t>(NT, d - g0);
+        int64_t s0 = 0;
+        int32_t len = 0;
+        if (tid < gs) {
+            const int32_t v = g.a_adj[e0 + g0 + tid];
+            const int32_t* row = tb + (int64_t)v * (ntt + 1);
+            const int32_t a = row[t_begin];
+            s0 = g.b_off[v] + a;
+            len = row[t_end] - a;
+        }
+        const int32_t nu = stage_units(S, gs, s0, len);
+        unsigned long long wl = 0;
+        traverse_units(S, gs, nu, g.b_adj, [&](int32_t w) {
+            if (w != u) {
+                ++wl;
+                const uint32_t k = (uint32_t)(w - klo);
+                atomicAdd(&cnt[k / PER_WORD], 1u << ((k % PER_WORD) * BITS));
+            }
+        });
+        pc.wedges += wl;
+        __syncthreads();
+    }
+    // keys with c >= 2 are gathered per lane in registers and applied in
+    // batches; counters are cleared as they are read
+    const int32_t n4 = (int32_t)((int64_t)(t_end - t_begin) * tk / PER_WORD / 4);
+    PairBuf<kDenseBatch> pbuf;
+    for (int32_t base = 0; base < n4; base += NT) {
+        const int32_t w4 = base + tid;
+        uint4 x = make_uint4(0, 0, 0, 0);
+        if (w4 < n4) {
+            x = cnt4[w4];
+            if (x.x | x.y | x.z | x.w) cnt4[w4] = make_uint4(0, 0, 0, 0);
+        }
+        const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+        uint32_t msk[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) msk[q] = ge2_mask<BITS>(xs[q]);
+        const int32_t kbase = klo + w4 * 4 * PER_WORD;
+        for (;;) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                while (msk[q] && pbuf.n < kDenseBatch) {
+                    const int bit = __ffs(msk[q]) - 1;
+                    msk[q] &= msk[q] - 1;
+                    const int f = bit / BITS;
+                    pbuf.push(kbase + q * PER_WORD + f, (int32_t)((xs[q] >> (f * BITS)) & FMASK));
+                }
+            }
+            if (!__ballot((msk[0] | msk[1] | msk[2] | msk[3]) != 0)) break;
+            ap.flush(pbuf, pc.pairs);
+        }
+    }
+    ap.flush(pbuf, pc.pairs);
+    __syncthreads();
+}
+
+// Item layout of one dense launch: counter widths 16, 8, 4, 2 bits in that
+// order (most wedges per vertex first), each heavy vertices (items of gh
+// tiles) then light ones (items of gl tiles).
+struct DensePlan {
+    int64_t end[kDenseKinds];      // cumulative item counts
+    int64_t n_heavy[kDenseKinds];  // heavy items of each width
+    int32_t gl[kDenseKinds], gh[kDenseKinds], ngl[kDenseKinds], ngh[kDenseKinds];
+};
+
+constexpr int kDenseOrder[kDenseKinds] = {3, 2, 1, 0};  // kinds of 16, 8, 4, 2 bits
+
+// One launch for every dense vertex of the round, whatever its counter
+// width: a single work queue, one tail.  g_max[kind]: widest light item
+// (tiles) the LDS allows for that width.  LDS: kDenseLdsBytes of counters +
+// staging.
+__global__ void __launch_bounds__(kDenseThreads)
+k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, FrontSet fs, ItemKeys g_max,
+             int64_t slots, CdApply ap, Ctl* ctl) {
+    constexpr int NT = kDenseThreads;
     // only tiles below the live key bound can hold a key to update; ntt
     // itself stays the row stride of the tile-bound table
     const int32_t ntk = min(ntt, (int32_t)((max(ctl->key_hi, 1) + (int64_t)tk - 1) / tk));
-    g_max = min(g_max, ntk);
-    const int32_t* __restrict__ front_l = fs.list[ctl->front_buf][BL];
-    const int32_t* __restrict__ front_h = fs.list[ctl->front_buf][BH];
-    // light items span gl tiles, heavy ones gh = gl / kHeavySplit; gl is
-    // narrowed from g_max while there would be fewer than about four items
-    // per resident workgroup
-    const auto n_items_of = [&](int32_t l) {
-        const int32_t h = max(1, l / kHeavySplit);
-        return (int64_t)n_l * ((ntk + l - 1) / l) + (int64_t)n_h * ((ntk + h - 1) / h);
-    };
-    int32_t gl = g_max;
-    while (gl > 1 && n_items_of(gl) < 4 * slots) gl = (gl + 1) / 2;
-    const int32_t gh = max(1, gl / kHeavySplit);
-    unsigned long long* head = &ctl->head[BL];
+    __shared__ DensePlan pl;   // identical in every thread; kept in LDS so it is indexed without scratch
+    int64_t total = 0;
+    for (int o = 0; o < kDenseKinds; ++o) {
+        const int k = kDenseOrder[o];
+        const int32_t n_l = ctl->n_front[dense_bin_of_kind(k, false)], n_h = ctl->n_front[dense_bin_of_kind(k, true)];
+        // light items span gl tiles, heavy ones gh = gl / kHeavySplit; gl is
+        // narrowed while this width would have fewer than about four items
+        // per resident workgroup
+        const auto n_items_of = [&](int32_t l) {
+            const int32_t h = max(1, l / kHeavySplit);
+            return (int64_t)n_l * ((ntk + l - 1) / l) + (int64_t)n_h * ((ntk + h - 1) / h);
+        };
+        int32_t gl = (int32_t)min<int64_t>(g_max.k[k], ntk);
+        while (gl > 1 && n_items_of(gl) < 4 * slots) gl = (gl + 1) / 2;
+        const int32_t gh = max(1, gl / kHeavySplit);
+        const int32_t ngl = (ntk + gl - 1) / gl, ngh = (ntk + gh - 1) / gh;
+        const int64_t nh_items = (int64_t)n_h * ngh;
+        total += nh_items + (int64_t)n_l * ngl;
+        if (threadIdx.x == 0) {
+            pl.gl[o] = gl;
+            pl.gh[o] = gh;
+            pl.ngl[o] = ngl;
+            pl.ngh[o] = ngh;
+            pl.n_heavy[o] = nh_items;
+            pl.end[o] = total;
+        }
+    }
+    if (total == 0) return;
     extern __shared__ __align__(16) uint32_t dyn[];
     uint32_t* cnt = dyn;
-    const int64_t max_keys = (int64_t)gl * tk;
-    Stage<NT>& S = *reinterpret_cast<Stage<NT>*>(dyn + max_keys / PER_WORD);
-    uint4* cnt4 = reinterpret_cast<uint4*>(cnt);
+    Stage<NT>& S = *reinterpret_cast<Stage<NT>*>(dyn + kDenseLdsBytes / 4);
     const int tid = threadIdx.x;
     {
-        const int32_t n4 = (int32_t)(max_keys / PER_WORD / 4);
-        for (int w = tid; w < n4; w += NT) cnt4[w] = make_uint4(0, 0, 0, 0);
+        uint4* cnt4 = reinterpret_cast<uint4*>(cnt);
+        for (int w = tid; w < kDenseLdsBytes / 16; w += NT) cnt4[w] = make_uint4(0, 0, 0, 0);
     }
     __syncthreads();
-    const int32_t ngh = (ntk + gh - 1) / gh, ngl = (ntk + gl - 1) / gl;
-    const int64_t n_heavy_items = (int64_t)n_h * ngh;
-    const int64_t n_items = n_heavy_items + (int64_t)n_l * ngl;
+    const int32_t buf = ctl->front_buf;
     PeelCounters pc;
     for (;;) {
-        const int64_t it = next_item(S, head);
-        if (it >= n_items) break;
+        const int64_t it = next_item(S, &ctl->head[dense_bin_of_kind(0, false)]);
+        if (it >= total) break;
+        int o = 0;
+        while (it >= pl.end[o]) ++o;
+        const int k = kDenseOrder[o];
+        const int64_t r = it - (o ? pl.end[o - 1] : 0);
         int32_t u, t_begin, t_end;
-        if (it < n_heavy_items) {
-            u = front_h[it / ngh];
-            t_begin = (int32_t)(it % ngh) * gh;
-            t_end = min(ntk, t_begin + gh);
+        if (r < pl.n_heavy[o]) {
+            u = fs.list[buf][dense_bin_of_kind(k, true)][r / pl.ngh[o]];
+            t_begin = (int32_t)(r % pl.ngh[o]) * pl.gh[o];
+            t_end = min(ntk, t_begin + pl.gh[o]);
         } else {
-            const int64_t r = it - n_heavy_items;
-            u = front_l[r / ngl];
-            t_begin = (int32_t)(r % ngl) * gl;
-            t_end = min(ntk, t_begin + gl);
+            const int64_t q = r - pl.n_heavy[o];
+            u = fs.list[buf][dense_bin_of_kind(k, false)][q / pl.ngl[o]];
+            t_begin = (int32_t)(q % pl.ngl[o]) * pl.gl[o];
+            t_end = min(ntk, t_begin + pl.gl[o]);
         }
-        const int64_t su = ap.supp[u];
-        const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
-        if (su == 0) {
+        if (ap.supp[u] == 0) {
             pc.skipped += (tid == 0 && t_begin == 0);
             continue;
         }
-        const int32_t klo = t_begin * tk;
-        if (tid == 0 && t_begin == 0) pc.edges += (unsigned long long)d;
-        for (int64_t g0 = 0; g0 < d; g0 += NT) {
-            const int gs = (int)min<int64_t>(NT, d - g0);
-            int64_t s0 = 0;
-            int32_t len = 0;
-            if (tid < gs) {
-                const int32_t v = g.a_adj[e0 + g0 + tid];
-                const int32_t* row = tb + (int64_t)v * (ntt + 1);
-                const int32_t a = row[t_begin];
-                s0 = g.b_off[v] + a;
-                len = row[t_end] - a;
-            }
-            const int32_t nu = stage_units(S, gs, s0, len);
-            unsigned long long wl = 0;
-            traverse_units(S, gs, nu, g.b_adj, [&](int32_t w) {
-                if (w != u) {
-                    ++wl;
-                    const uint32_t k = (uint32_t)(w - klo);
-                    atomicAdd(&cnt[k / PER_WORD], 1u << ((k % PER_WORD) * BITS));
-                }
-            });
-            pc.wedges += wl;
-            __syncthreads();
+        switch (k) {
+            case 3: dense_item<16>(g, tb, tk, ntt, u, t_begin, t_end, cnt, S, ap, pc); break;
+            case 2: dense_item<8>(g, tb, tk, ntt, u, t_begin, t_end, cnt, S, ap, pc); break;
+            case 1: dense_item<4>(g, tb, tk, ntt, u, t_begin, t_end, cnt, S, ap, pc); break;
+            default: dense_item<2>(g, tb, tk, ntt, u, t_begin, t_end, cnt, S, ap, pc); break;
         }
-        // keys with c >= 2 are gathered per lane in registers and applied in
-        // batches; counters are cleared as they are read
-        const int32_t n4 = (int32_t)((int64_t)(t_end - t_begin) * tk / PER_WORD / 4);
-        PairBuf<kDenseBatch> pbuf;
-        for (int32_t base = 0; base < n4; base += NT) {
-            const int32_t w4 = base + tid;
-            uint4 x = make_uint4(0, 0, 0, 0);
-            if (w4 < n4) {
-                x = cnt4[w4];
-                if (x.x | x.y | x.z | x.w) cnt4[w4] = make_uint4(0, 0, 0, 0);
-            }
-            const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
-            uint32_t msk[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) msk[q] = ge2_mask<BITS>(xs[q]);
-            const int32_t kbase = klo + w4 * 4 * PER_WORD;
-            for (;;) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    while (msk[q] && pbuf.n < kDenseBatch) {
-                        const int bit = __ffs(msk[q]) - 1;
-                        msk[q] &= msk[q] - 1;
-                        const int f = bit / BITS;
-                        pbuf.push(kbase + q * PER_WORD + f, (int32_t)((xs[q] >> (f * BITS)) & FMASK));
-                    }
-                }
-                if (!__ballot((msk[0] | msk[1] | msk[2] | msk[3]) != 0)) break;
-                ap.flush(pbuf, pc.pairs);
-            }
-        }
-        ap.flush(pbuf, pc.pairs);
-        __syncthreads();
     }
     pc.flush(ctl, false);
 }
 
-size_t dense_lds_bytes(int64_t keys, int bits) { return (size_t)(keys * bits / 8) + sizeof(Stage<kDenseThreads>); }
+size_t dense_lds_bytes() { return (size_t)kDenseLdsBytes + sizeof(Stage<kDenseThreads>); }
 
-template <int BITS>
 void launch_dense(const DevGraph& g, PeelBuffers& pb, const FrontSet& fs, CdApply ap, Ctl* ctl, hipStream_t s) {
     int dev = 0, cus = 0;
     TIP_HIP_TRY(hipGetDevice(&dev));
     TIP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int32_t g_max = dense_item_tiles(BITS, pb.tk, pb.ntt);
-    const size_t lds = dense_lds_bytes((int64_t)g_max * pb.tk, BITS);
+    ItemKeys g_max;
+    for (int k = 0; k < kDenseKinds; ++k) g_max.k[k] = dense_item_tiles(2 << k, pb.tk, pb.ntt);
+    const size_t lds = dense_lds_bytes();
     int occ = 0;
-    TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel_dense<BITS>, kDenseThreads, lds));
+    TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel_dense, kDenseThreads, lds));
     const int64_t slots = (int64_t)cus * std::max(1, occ);
-    k_peel_dense<BITS><<<(unsigned)slots, kDenseThreads, lds, s>>>(g, pb.tb, pb.tk, pb.ntt, fs, g_max, slots, ap,
-                                                                  ctl);
+    k_peel_dense<<<(unsigned)slots, kDenseThreads, lds, s>>>(g, pb.tb, pb.tk, pb.ntt, fs, g_max, slots, ap, ctl);
     TIP_HIP_TRY(hipGetLastError());
 }
 
@@ -1081,11 +1118,9 @@ void launch_round(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena
         TIP_HIP_TRY(hipGetLastError());
         if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[1], s));
     }
-    // heavier counter widths first: their vertices have the most wedges
-    if (has(dense_bin(16, false)) || has(dense_bin(16, true))) launch_dense<16>(gc, pb, fs, ap, ctl, s);
-    if (has(dense_bin(8, false)) || has(dense_bin(8, true))) launch_dense<8>(gc, pb, fs, ap, ctl, s);
-    if (has(dense_bin(4, false)) || has(dense_bin(4, true))) launch_dense<4>(gc, pb, fs, ap, ctl, s);
-    if (has(dense_bin(2, false)) || has(dense_bin(2, true))) launch_dense<2>(gc, pb, fs, ap, ctl, s);
+    bool any_dense = false;
+    for (int b = dense_bin(2, false); b < kBins; ++b) any_dense = any_dense || has(b);
+    if (any_dense) launch_dense(gc, pb, fs, ap, ctl, s);
     k_frontier_scan<<<grid1(g.n_a, 4096), kT, 0, s>>>(fs, pb.live[0], pb.live[1], pb.supp, pb.state, pb.wprox,
                                                        pb.bin, g.a_off, 1, ctl);
     TIP_HIP_TRY(hipGetLastError());

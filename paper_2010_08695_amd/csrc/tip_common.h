@@ -56,7 +56,8 @@ __host__ __device__ inline int dense_bits(int64_t d) {
     return d <= 3 ? 2 : d <= 15 ? 4 : d <= 255 ? 8 : d <= 65535 ? 16 : 0;
 }
 __host__ __device__ inline int dense_kind(int bits) { return bits == 2 ? 0 : bits == 4 ? 1 : bits == 8 ? 2 : 3; }
-__host__ __device__ inline int dense_bin(int bits, bool heavy) { return 2 + 2 * dense_kind(bits) + (heavy ? 1 : 0); }
+__host__ __device__ inline int dense_bin_of_kind(int kind, bool heavy) { return 2 + 2 * kind + (heavy ? 1 : 0); }
+__host__ __device__ inline int dense_bin(int bits, bool heavy) { return dense_bin_of_kind(dense_kind(bits), heavy); }
 
 // Granularity (keys) of the per-list tile-bound table for a side of n keys:
 // 16K keys, or coarser so that there are at most 512 tiles.
