@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_WEDGE = 4
 BYTES_PER_EDGE = 4
 BYTES_PER_PAIR = 16
-DOMINANT_KERNEL = "k_peel_bitmap"
+DOMINANT_KERNEL = "k_peel_dense"
 KERNEL_SOURCES = ["paper_2010_08695_amd/csrc/peel.hip", "paper_2010_08695_amd/csrc/agg.h",
                   "paper_2010_08695_amd/csrc/tip_common.h"]
 

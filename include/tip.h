@@ -54,11 +54,11 @@ typedef struct {
     const int32_t* ev; /* [m] V ids */
 } tip_edges;
 
-/* TIP_FLAG_TIME_KERNELS: time every launch of the coarse-grained
- * bitmap-path update kernel (k_peel_bitmap: one workgroup per peeled vertex
- * of up to tune[1] wedges; the single kernel with the most device time on
- * power-law graphs) with HIP events on the call's stream and report it in
- * tip_stats.peel_*. */
+/* TIP_FLAG_TIME_KERNELS: time every launch of the coarse-grained dense
+ * update kernel (k_peel_dense: (vertex, key range) work items with LDS
+ * counters; the single kernel with the most device time on power-law
+ * graphs) with HIP events on the call's stream and report it in
+ * tip_stats.peel_*.  Rounds are then launched from the host. */
 #define TIP_FLAG_TIME_KERNELS 1
 
 /* TIP_FLAG_NO_GRAPH: launch every coarse-grained round from the host
@@ -108,7 +108,7 @@ typedef struct {
     int64_t spills;       /* repeat keys that did not fit in LDS (kept in HBM) */
     int64_t skipped;      /* peeled vertices with no butterfly left (no update needed) */
     int64_t m_unique;     /* edges after duplicate merging */
-    /* the coarse-grained bitmap-path update kernel alone (k_peel_bitmap) */
+    /* the coarse-grained dense update kernel alone (k_peel_dense) */
     int64_t peel_launches; /* launches */
     int64_t peel_wedges;   /* wedges it traversed */
     int64_t peel_edges;    /* first-hop edges (u, v) it read */

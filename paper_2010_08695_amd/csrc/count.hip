@@ -94,19 +94,28 @@ k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, con
             }
             wave_sync();
         }
-        // pass 2: middle vertices gain c - 1 per wedge
+        // pass 2: middle vertices gain c - 1 per wedge; with one chunk of
+        // neighbours the runs staged by pass 1 are still in LDS
+        const bool one_chunk = d <= kWave;
         for (int64_t g0 = 0; g0 < d; g0 += kWave) {
             const int gs = (int)min<int64_t>(kWave, d - g0);
             int64_t len = 0;
             int32_t y = 0;
-            if (lane < gs) {
-                const int64_t e = e0 + g0 + lane;
-                y = sv.own_adj[e];
-                W.sbeg[lane] = sv.oth_off[y];
-                len = min(sv.oth_cut[y], sv.own_rev[e]);
+            int64_t tot;
+            if (one_chunk) {
+                if (lane < gs) y = sv.own_adj[e0 + lane];
+                tot = W.pre[gs];
+            } else {
+                if (lane < gs) {
+                    const int64_t e = e0 + g0 + lane;
+                    y = sv.own_adj[e];
+                    W.sbeg[lane] = sv.oth_off[y];
+                    len = min(sv.oth_cut[y], sv.own_rev[e]);
+                }
+                tot = wave_scan_lengths(W, len);
             }
             W.acc[lane] = 0;
-            const int64_t tot = wave_scan_lengths(W, len);
+            wave_sync();
             int j = 0;
             for (int64_t i = lane; i < tot; i += kWave) {
                 while (j + 1 < gs && W.pre[j + 1] <= i) ++j;
@@ -191,17 +200,26 @@ k_count_big(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64
                 __syncthreads();
             }
             const bool spilled = L.spill_n > 0;
-            // pass 2
+            // pass 2; with one group of neighbours the runs staged by pass 1
+            // are still in LDS
+            const bool one_group = d <= kGroup;
             for (int64_t g0 = 0; g0 < d; g0 += kGroup) {
                 const int gs = (int)min<int64_t>(kGroup, d - g0);
                 int64_t len = 0;
-                if (tid < gs) {
-                    int64_t s0;
-                    CountSlice::get(sv, e0 + g0 + tid, multi, klo, khi, s0, len);
-                    L.sbeg[tid] = s0;
-                    L.acc[tid] = 0;
+                int64_t tot;
+                if (one_group) {
+                    if (tid < gs) L.acc[tid] = 0;
+                    tot = L.pre[gs];
+                    __syncthreads();
+                } else {
+                    if (tid < gs) {
+                        int64_t s0;
+                        CountSlice::get(sv, e0 + g0 + tid, multi, klo, khi, s0, len);
+                        L.sbeg[tid] = s0;
+                        L.acc[tid] = 0;
+                    }
+                    tot = block_scan_lengths<NT>(L, gs, len);
                 }
-                const int64_t tot = block_scan_lengths<NT>(L, gs, len);
                 for (int64_t i = tid; i < tot; i += NT) {
                     const int j = find_slice(L, gs, i);
                     const uint32_t k = (uint32_t)(sv.oth_adj[L.sbeg[j] + (i - L.pre[j])] - klo);

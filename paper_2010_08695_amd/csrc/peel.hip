@@ -627,7 +627,7 @@ k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t nt
             __syncthreads();
         }
     }
-    pc.flush(ctl, true);
+    pc.flush(ctl, false);
 }
 
 // Counters of value >= 2 in a word of BITS-bit counters: the top bit of
@@ -811,7 +811,7 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
             default: dense_item<2>(g, tb, tk, ntt, u, t_begin, t_end, cnt, S, ap, pc); break;
         }
     }
-    pc.flush(ctl, false);
+    pc.flush(ctl, true);
 }
 
 size_t dense_lds_bytes() { return (size_t)kDenseLdsBytes + sizeof(Stage<kDenseThreads>); }
@@ -1109,18 +1109,20 @@ void launch_round(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena
         TIP_HIP_TRY(hipGetLastError());
     }
     if (has(kBinBitmap)) {
-        if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[0], s));
         // workgroups the spill arena can hold at the bitmap path's spacing
         const int64_t gap = std::min<int64_t>(kBmTile, spill.stride);
         const int64_t fit = (int64_t)spill.slots * (spill.stride / std::max<int64_t>(gap, 1));
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(bitmap_grid(), fit));
         k_peel_bitmap<<<grid, kBmThreads, 0, s>>>(gc, pb.tb, pb.tk, pb.ntt, fs, ap, spill, ctl);
         TIP_HIP_TRY(hipGetLastError());
-        if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[1], s));
     }
     bool any_dense = false;
     for (int b = dense_bin(2, false); b < kBins; ++b) any_dense = any_dense || has(b);
-    if (any_dense) launch_dense(gc, pb, fs, ap, ctl, s);
+    if (any_dense) {
+        if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[0], s));
+        launch_dense(gc, pb, fs, ap, ctl, s);
+        if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[1], s));
+    }
     k_frontier_scan<<<grid1(g.n_a, 4096), kT, 0, s>>>(fs, pb.live[0], pb.live[1], pb.supp, pb.state, pb.wprox,
                                                        pb.bin, g.a_off, 1, ctl);
     TIP_HIP_TRY(hipGetLastError());

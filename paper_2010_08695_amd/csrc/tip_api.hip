@@ -274,7 +274,7 @@ __global__ void k_scatter_i32(const int32_t* by_rank, const int32_t* orig, int32
 // or all of FD) to the second (outputs and statistics).
 struct RunState {
     Events ev;
-    Events kev;  // [0], [1]: around the bitmap-path update kernel of one round
+    Events kev;  // [0], [1]: around the dense update kernel of one round
     double peel_ms = 0.0;
     int64_t peel_launches = 0;
     int32_t S = 0;
@@ -379,7 +379,8 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
                     TIP_HIP_TRY(hipGraphLaunch(rg->exec, s));
                     continue;
                 }
-                const int32_t nb = n_cur[kBinBitmap];
+                int32_t nb = 0;  // vertices for the timed (dense) update kernel
+                for (int b = dense_bin_of_kind(0, false); b < kBins; ++b) nb += n_cur[b];
                 launch_round(g, pb, w.ctl, w.spill, big_grid, s, time_kernels && nb > 0 ? kev.e : nullptr, n_cur);
                 if (nb > 0) {
                     ++peel_launches;

@@ -134,8 +134,8 @@ void launch_range_begin(const DevGraph& g, PeelBuffers& pb, int cur_live, int32_
 // One coarse-grained round, driven entirely by the control block: update
 // kernels over the current activeSet, then the next activeSet and the buffer
 // swap.  Fixed grids, no host synchronisation, so it can be graph-captured.
-// ev_big: optional pair of events recorded around the bitmap-path update
-// kernel, the one timed by TIP_FLAG_TIME_KERNELS (not while capturing).
+// ev_big: optional pair of events recorded around the dense update kernel,
+// the one timed by TIP_FLAG_TIME_KERNELS (not while capturing).
 // n_cur: the frontier sizes per bin when the host knows them (kernels
 // without work are then skipped), or nullptr (graph capture: every kernel
 // is launched and checks its own work).
