@@ -193,6 +193,7 @@ __global__ void k_ctl_begin_range(Ctl* ctl) {
     ctl->max_supp = 0;
     ctl->w_rem = 0;
     ctl->w_range = 0;
+    for (int i = 0; i < kSpread; ++i) ctl->spread[i][kScWRange] = 0;
     for (int b = 0; b < kBins; ++b) ctl->n_front[b] = ctl->n_next[b] = ctl->head[b] = 0;
 }
 
@@ -367,9 +368,9 @@ __global__ void k_frontier_scan(FrontSet fs, const int32_t* live0, const int32_t
     skipped = (unsigned long long)wave_sum_i64((int64_t)skipped);
     dead = (unsigned long long)wave_sum_i64((int64_t)dead);
     if ((threadIdx.x & (kWave - 1)) == 0) {
-        if (ws) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->w_range), (unsigned long long)ws);
-        if (skipped) atomicAdd(&ctl->skipped, skipped);
-        if (dead) atomicAdd(&ctl->dead_edges, dead);
+        if (ws) spread_add(ctl, kScWRange, (unsigned long long)ws);
+        if (skipped) spread_add(ctl, kScSkipped, skipped);
+        if (dead) spread_add(ctl, kScDeadEdges, dead);
     }
 }
 
@@ -438,14 +439,14 @@ struct PeelCounters {
         spills = (unsigned long long)wave_sum_i64((int64_t)spills);
         edges = (unsigned long long)wave_sum_i64((int64_t)edges);
         if ((threadIdx.x & (kWave - 1)) == 0) {
-            if (wedges) atomicAdd(&ctl->wedges_cd, wedges);
-            if (pairs) atomicAdd(&ctl->pair_updates, pairs);
-            if (skipped) atomicAdd(&ctl->skipped, skipped);
-            if (spills) atomicAdd(&ctl->spills, spills);
+            if (wedges) spread_add(ctl, kScWedgesCd, wedges);
+            if (pairs) spread_add(ctl, kScPairs, pairs);
+            if (skipped) spread_add(ctl, kScSkipped, skipped);
+            if (spills) spread_add(ctl, kScSpills, spills);
             if (big) {
-                if (wedges) atomicAdd(&ctl->big_wedges, wedges);
-                if (pairs) atomicAdd(&ctl->big_pairs, pairs);
-                if (edges) atomicAdd(&ctl->big_edges, edges);
+                if (wedges) spread_add(ctl, kScBigWedges, wedges);
+                if (pairs) spread_add(ctl, kScBigPairs, pairs);
+                if (edges) spread_add(ctl, kScBigEdges, edges);
             }
         }
     }
@@ -654,7 +655,7 @@ __device__ inline uint32_t ge2_mask(uint32_t x) {
 // zero between items: an item clears every word it read.
 template <int BITS>
 __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt,
-                                  int32_t u, int32_t t_begin, int32_t t_end, uint32_t* cnt,
+                                  int32_t u, int32_t t_begin, int32_t t_end, int32_t gpass, uint32_t* cnt,
                                   Stage<kDenseThreads>& S, const CdApply& ap, PeelCounters& pc) {
     constexpr int NT = kDenseThreads;
     constexpr int PER_WORD = 32 / BITS;          // counters per 32-bit word
@@ -662,63 +663,77 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
     const int tid = threadIdx.x;
     uint4* cnt4 = reinterpret_cast<uint4*>(cnt);
     const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
-    const int32_t klo = t_begin * tk;
     if (tid == 0 && t_begin == 0) pc.edges += (unsigned long long)d;
-    for (int64_t g0 = 0; g0 < d; g0 += NT) {
-        const int gs = (int)min<int64_t>(NT, d - g0);
-        int64_t s0 = 0;
-        int32_t len = 0;
-        if (tid < gs) {
-            const int32_t v = g.a_adj[e0 + g0 + tid];
-            const int32_t* row = tb + (int64_t)v * (ntt + 1);
-            const int32_t a = row[t_begin];
-            s0 = g.b_off[v] + a;
-            len = row[t_end] - a;
-        }
-        const int32_t nu = stage_units(S, gs, s0, len);
-        unsigned long long wl = 0;
-        traverse_units(S, gs, nu, g.b_adj, [&](int32_t w) {
-            if (w != u) {
-                ++wl;
-                const uint32_t k = (uint32_t)(w - klo);
-                atomicAdd(&cnt[k / PER_WORD], 1u << ((k % PER_WORD) * BITS));
+    // with at most NT neighbours, their ids and list offsets stay in
+    // registers for all passes; only the tile bounds are read per pass
+    const bool one = d <= NT;
+    int32_t v1 = 0;
+    int64_t bo1 = 0;
+    if (one && tid < d) {
+        v1 = g.a_adj[e0 + tid];
+        bo1 = g.b_off[v1];
+    }
+    // one pass per gpass tiles: count in LDS, then apply and clear
+    for (int32_t p0 = t_begin; p0 < t_end; p0 += gpass) {
+        const int32_t p1 = min(t_end, p0 + gpass);
+        const int32_t klo = p0 * tk;
+        for (int64_t g0 = 0; g0 < d; g0 += NT) {
+            const int gs = (int)min<int64_t>(NT, d - g0);
+            int64_t s0 = 0;
+            int32_t len = 0;
+            if (tid < gs) {
+                const int32_t v = one ? v1 : g.a_adj[e0 + g0 + tid];
+                const int64_t bo = one ? bo1 : g.b_off[v];
+                const int32_t* row = tb + (int64_t)v * (ntt + 1);
+                const int32_t a = row[p0];
+                s0 = bo + a;
+                len = row[p1] - a;
             }
-        });
-        pc.wedges += wl;
+            const int32_t nu = stage_units(S, gs, s0, len);
+            unsigned long long wl = 0;
+            traverse_units(S, gs, nu, g.b_adj, [&](int32_t w) {
+                if (w != u) {
+                    ++wl;
+                    const uint32_t k = (uint32_t)(w - klo);
+                    atomicAdd(&cnt[k / PER_WORD], 1u << ((k % PER_WORD) * BITS));
+                }
+            });
+            pc.wedges += wl;
+            __syncthreads();
+        }
+        // keys with c >= 2 are gathered per lane in registers and applied in
+        // batches; counters are cleared as they are read
+        const int32_t n4 = (int32_t)((int64_t)(p1 - p0) * tk / PER_WORD / 4);
+        PairBuf<kDenseBatch> pbuf;
+        for (int32_t base = 0; base < n4; base += NT) {
+            const int32_t w4 = base + tid;
+            uint4 x = make_uint4(0, 0, 0, 0);
+            if (w4 < n4) {
+                x = cnt4[w4];
+                if (x.x | x.y | x.z | x.w) cnt4[w4] = make_uint4(0, 0, 0, 0);
+            }
+            const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+            uint32_t msk[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) msk[q] = ge2_mask<BITS>(xs[q]);
+            const int32_t kbase = klo + w4 * 4 * PER_WORD;
+            for (;;) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    while (msk[q] && pbuf.n < kDenseBatch) {
+                        const int bit = __ffs(msk[q]) - 1;
+                        msk[q] &= msk[q] - 1;
+                        const int f = bit / BITS;
+                        pbuf.push(kbase + q * PER_WORD + f, (int32_t)((xs[q] >> (f * BITS)) & FMASK));
+                    }
+                }
+                if (!__ballot((msk[0] | msk[1] | msk[2] | msk[3]) != 0)) break;
+                ap.flush(pbuf, pc.pairs);
+            }
+        }
+        ap.flush(pbuf, pc.pairs);
         __syncthreads();
     }
-    // keys with c >= 2 are gathered per lane in registers and applied in
-    // batches; counters are cleared as they are read
-    const int32_t n4 = (int32_t)((int64_t)(t_end - t_begin) * tk / PER_WORD / 4);
-    PairBuf<kDenseBatch> pbuf;
-    for (int32_t base = 0; base < n4; base += NT) {
-        const int32_t w4 = base + tid;
-        uint4 x = make_uint4(0, 0, 0, 0);
-        if (w4 < n4) {
-            x = cnt4[w4];
-            if (x.x | x.y | x.z | x.w) cnt4[w4] = make_uint4(0, 0, 0, 0);
-        }
-        const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
-        uint32_t msk[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) msk[q] = ge2_mask<BITS>(xs[q]);
-        const int32_t kbase = klo + w4 * 4 * PER_WORD;
-        for (;;) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                while (msk[q] && pbuf.n < kDenseBatch) {
-                    const int bit = __ffs(msk[q]) - 1;
-                    msk[q] &= msk[q] - 1;
-                    const int f = bit / BITS;
-                    pbuf.push(kbase + q * PER_WORD + f, (int32_t)((xs[q] >> (f * BITS)) & FMASK));
-                }
-            }
-            if (!__ballot((msk[0] | msk[1] | msk[2] | msk[3]) != 0)) break;
-            ap.flush(pbuf, pc.pairs);
-        }
-    }
-    ap.flush(pbuf, pc.pairs);
-    __syncthreads();
 }
 
 // Item layout of one dense launch: counter widths 16, 8, 4, 2 bits in that
@@ -727,7 +742,7 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
 struct DensePlan {
     int64_t end[kDenseKinds];      // cumulative item counts
     int64_t n_heavy[kDenseKinds];  // heavy items of each width
-    int32_t gl[kDenseKinds], gh[kDenseKinds], ngl[kDenseKinds], ngh[kDenseKinds];
+    int32_t gl[kDenseKinds], gh[kDenseKinds], ngl[kDenseKinds], ngh[kDenseKinds], np[kDenseKinds];
 };
 
 constexpr int kDenseOrder[kDenseKinds] = {3, 2, 1, 0};  // kinds of 16, 8, 4, 2 bits
@@ -751,17 +766,25 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
         // light items span gl tiles, heavy ones gh = gl / kHeavySplit; gl is
         // narrowed while this width would have fewer than about four items
         // per resident workgroup
-        const auto n_items_of = [&](int32_t l) {
+        // a light item makes np passes of gl tiles; np shrinks first, then
+        // gl, while the round would have too few items to keep every
+        // resident workgroup busy
+        const auto n_items_of = [&](int32_t l, int32_t np) {
             const int32_t h = max(1, l / kHeavySplit);
-            return (int64_t)n_l * ((ntk + l - 1) / l) + (int64_t)n_h * ((ntk + h - 1) / h);
+            const int64_t span = (int64_t)l * np;
+            return (int64_t)n_l * ((ntk + span - 1) / span) + (int64_t)n_h * ((ntk + h - 1) / h);
         };
         int32_t gl = (int32_t)min<int64_t>(g_max.k[k], ntk);
-        while (gl > 1 && n_items_of(gl) < 4 * slots) gl = (gl + 1) / 2;
+        int32_t np = kDensePasses;
+        while (np > 1 && n_items_of(gl, np) < 8 * slots) np >>= 1;
+        while (np == 1 && gl > 1 && n_items_of(gl, 1) < 4 * slots) gl = (gl + 1) / 2;
         const int32_t gh = max(1, gl / kHeavySplit);
-        const int32_t ngl = (ntk + gl - 1) / gl, ngh = (ntk + gh - 1) / gh;
+        const int32_t ngl = (int32_t)((ntk + (int64_t)gl * np - 1) / ((int64_t)gl * np));
+        const int32_t ngh = (ntk + gh - 1) / gh;
         const int64_t nh_items = (int64_t)n_h * ngh;
         total += nh_items + (int64_t)n_l * ngl;
         if (threadIdx.x == 0) {
+            pl.np[o] = np;
             pl.gl[o] = gl;
             pl.gh[o] = gh;
             pl.ngl[o] = ngl;
@@ -789,26 +812,28 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
         while (it >= pl.end[o]) ++o;
         const int k = kDenseOrder[o];
         const int64_t r = it - (o ? pl.end[o - 1] : 0);
-        int32_t u, t_begin, t_end;
+        int32_t u, t_begin, t_end, gpass;
         if (r < pl.n_heavy[o]) {
             u = fs.list[buf][dense_bin_of_kind(k, true)][r / pl.ngh[o]];
-            t_begin = (int32_t)(r % pl.ngh[o]) * pl.gh[o];
-            t_end = min(ntk, t_begin + pl.gh[o]);
+            gpass = pl.gh[o];
+            t_begin = (int32_t)(r % pl.ngh[o]) * gpass;
+            t_end = min(ntk, t_begin + gpass);
         } else {
             const int64_t q = r - pl.n_heavy[o];
             u = fs.list[buf][dense_bin_of_kind(k, false)][q / pl.ngl[o]];
-            t_begin = (int32_t)(q % pl.ngl[o]) * pl.gl[o];
-            t_end = min(ntk, t_begin + pl.gl[o]);
+            gpass = pl.gl[o];
+            t_begin = (int32_t)(q % pl.ngl[o]) * gpass * pl.np[o];
+            t_end = min(ntk, t_begin + gpass * pl.np[o]);
         }
         if (ap.supp[u] == 0) {
             pc.skipped += (tid == 0 && t_begin == 0);
             continue;
         }
         switch (k) {
-            case 3: dense_item<16>(g, tb, tk, ntt, u, t_begin, t_end, cnt, S, ap, pc); break;
-            case 2: dense_item<8>(g, tb, tk, ntt, u, t_begin, t_end, cnt, S, ap, pc); break;
-            case 1: dense_item<4>(g, tb, tk, ntt, u, t_begin, t_end, cnt, S, ap, pc); break;
-            default: dense_item<2>(g, tb, tk, ntt, u, t_begin, t_end, cnt, S, ap, pc); break;
+            case 3: dense_item<16>(g, tb, tk, ntt, u, t_begin, t_end, gpass, cnt, S, ap, pc); break;
+            case 2: dense_item<8>(g, tb, tk, ntt, u, t_begin, t_end, gpass, cnt, S, ap, pc); break;
+            case 1: dense_item<4>(g, tb, tk, ntt, u, t_begin, t_end, gpass, cnt, S, ap, pc); break;
+            default: dense_item<2>(g, tb, tk, ntt, u, t_begin, t_end, gpass, cnt, S, ap, pc); break;
         }
     }
     pc.flush(ctl, true);
@@ -881,7 +906,7 @@ __global__ void k_dgm_offsets(const int64_t* __restrict__ off, int32_t n_b, int6
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->cd_m = total;
-        ctl->dead_edges = 0;
+        for (int i = 0; i < kSpread; ++i) ctl->spread[i][kScDeadEdges] = 0;
     }
 }
 
@@ -956,7 +981,7 @@ __global__ void k_key_hi(const int32_t* __restrict__ state, int32_t n_a, Ctl* ct
 
 __global__ void k_set_cd_m(Ctl* ctl, long long m, int32_t n_a) {
     ctl->cd_m = m;
-    ctl->dead_edges = 0;
+    for (int i = 0; i < kSpread; ++i) ctl->spread[i][kScDeadEdges] = 0;
     ctl->key_hi = n_a;
 }
 

@@ -346,8 +346,9 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
             if (n_live == 0) break;
             // DGM: drop the vertices of finished ranges from the CD lists once
             // they hold enough of the remaining entries
-            if (tune.compact_permille > 0 && c0.dead_edges > 0 &&
-                (double)c0.dead_edges * 1000.0 >= (double)c0.cd_m * (double)tune.compact_permille)
+            const unsigned long long dead = spread_sum(c0, kScDeadEdges);
+            if (tune.compact_permille > 0 && dead > 0 &&
+                (double)dead * 1000.0 >= (double)c0.cd_m * (double)tune.compact_permille)
                 launch_compact(g, pb, cscr, c0.cd_m, tune, w.ctl, s);
             const uint64_t max_supp = c0.max_supp;
             const long long w_rem = c0.w_rem;
@@ -397,7 +398,8 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
                 }
             }
             const Ctl& c3 = read_ctl(w, s);
-            if (c3.w_range > 0) scale = std::min(1.0, (double)tgt / (double)c3.w_range);
+            const long long w_range = (long long)spread_sum(c3, kScWRange);
+            if (w_range > 0) scale = std::min(1.0, (double)tgt / (double)w_range);
             lo = hi;
         }
         (void)lo;
@@ -453,19 +455,19 @@ void run_back(Work& w, int32_t n_a, int32_t n_b, bool decompose, RunOut& out, Ru
     if (st) {
         std::memset(st, 0, sizeof(*st));
         st->wedges_count = (int64_t)cf.wedges_count;
-        st->wedges_cd = (int64_t)cf.wedges_cd;
+        st->wedges_cd = (int64_t)spread_sum(cf, kScWedgesCd);
         st->wedges_fd = (int64_t)cf.wedges_fd;
-        st->pair_updates = (int64_t)cf.pair_updates;
+        st->pair_updates = (int64_t)(cf.pair_updates + spread_sum(cf, kScPairs));
         st->rounds = (int64_t)cf.rounds_done;
         st->subsets = S;
         st->fd_levels = (int64_t)cf.fd_levels;
-        st->spills = (int64_t)cf.spills;
-        st->skipped = (int64_t)cf.skipped;
+        st->spills = (int64_t)(cf.spills + spread_sum(cf, kScSpills));
+        st->skipped = (int64_t)spread_sum(cf, kScSkipped);
         st->m_unique = g.m;
         st->peel_launches = rs.peel_launches;
-        st->peel_wedges = (int64_t)cf.big_wedges;
-        st->peel_edges = (int64_t)cf.big_edges;
-        st->peel_pairs = (int64_t)cf.big_pairs;
+        st->peel_wedges = (int64_t)spread_sum(cf, kScBigWedges);
+        st->peel_edges = (int64_t)spread_sum(cf, kScBigEdges);
+        st->peel_pairs = (int64_t)spread_sum(cf, kScBigPairs);
         st->peel_ms = rs.peel_ms;
         st->t_ingest_ms = ev.ms(0, 1);
         st->t_count_ms = ev.ms(1, 2);

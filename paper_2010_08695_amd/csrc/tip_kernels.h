@@ -5,6 +5,15 @@
 
 namespace tip {
 
+// Counters that many waves add to in every launch are spread over
+// kSpread sub-slots (chosen by block index) so their atomics do not
+// serialise on one address; the host sums the slots.
+constexpr int kSpread = 64;
+enum SpreadCounter {
+    kScWedgesCd = 0, kScPairs, kScSkipped, kScSpills, kScBigWedges, kScBigPairs, kScBigEdges, kScWRange,
+    kScDeadEdges, kScCount
+};
+
 // Device-resident control block of one decomposition.
 struct Ctl {
     int32_t n_live;         // live-list length (after the last compaction)
@@ -37,6 +46,7 @@ struct Ctl {
     long long cd_m;                  // entries left in the CD lists
     int32_t key_hi;                  // every live vertex of side A has a rank below this
     int32_t pad2;
+    unsigned long long spread[kSpread][kScCount];
     // Range state read by the round kernels, so that a sequence of rounds
     // can be launched (or replayed from a graph) without host arguments.
     long long range_hi;      // upper bound of the current range
@@ -46,6 +56,16 @@ struct Ctl {
     int32_t front_buf;       // which frontier buffer is current
     unsigned long long rounds_done;  // rounds with a non-empty activeSet
 };
+
+__device__ inline void spread_add(Ctl* ctl, int c, unsigned long long v) {
+    atomicAdd(&ctl->spread[blockIdx.x & (kSpread - 1)][c], v);
+}
+
+inline unsigned long long spread_sum(const Ctl& c, int k) {
+    unsigned long long s = 0;
+    for (int i = 0; i < kSpread; ++i) s += c.spread[i][k];
+    return s;
+}
 
 struct CountBuffers {
     int64_t* bfly_a;     // [n_a]
