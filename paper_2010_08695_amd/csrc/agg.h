@@ -67,6 +67,16 @@ __device__ inline int64_t wave_incl_scan_i64(int64_t x) {
     return x;
 }
 
+__device__ inline int32_t wave_incl_scan_i32(int32_t x) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int32_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
 // Lower bound of `key` in the sorted range adj[lo, hi).
 __device__ inline int64_t lower_bound_i32(const int32_t* __restrict__ adj, int64_t lo, int64_t hi, int32_t key) {
     while (lo < hi) {

@@ -148,9 +148,10 @@ __global__ void k_wproxy(DevGraph g, const int32_t* __restrict__ deg_b, int64_t*
 // (a few percent of the wedges) fit its LDS table, i.e. up to bm_max wedges;
 // above that the dense kernel, unless its counter bytes (n_a * bits / 8,
 // bits from the degree so that c(u, w) <= d_u fits) are large against the
-// wedges (w <= n_a * bits / dense_div).  A dense vertex is heavy when a
-// light-sized item (item_keys[kind] keys) would hold more than kItemWedges
-// of its wedges.
+// wedges (w <= n_a * bits / dense_div), or one table tile of its counters
+// does not fit the workgroup's LDS (sides of more than 8M keys).  A dense
+// vertex is heavy when a light-sized item (item_keys[kind] keys) would hold
+// more than kItemWedges of its wedges.
 struct ItemKeys {
     int64_t k[kDenseKinds];
 };
@@ -166,7 +167,8 @@ __global__ void k_peel_bins(const int64_t* __restrict__ a_off, const int64_t* __
         uint8_t b = kBinBitmap;
         if (w <= kSmallMaxWedges) {
             b = kBinWave;
-        } else if (bits && w > max<int64_t>(bm_max, nk * bits / dense_div)) {
+        } else if (bits && ik.k[dense_kind(bits)] * bits <= (int64_t)kDenseLdsBytes * 8 &&
+                   w > max<int64_t>(bm_max, nk * bits / dense_div)) {
             const bool heavy = (double)w * (double)ik.k[dense_kind(bits)] > (double)kItemWedges * (double)nk;
             b = (uint8_t)dense_bin(bits, heavy);
         }
@@ -660,7 +662,9 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
     constexpr int NT = kDenseThreads;
     constexpr int PER_WORD = 32 / BITS;          // counters per 32-bit word
     constexpr uint32_t FMASK = BITS == 16 ? 0xffffu : ((1u << BITS) - 1);
+    constexpr int32_t kStageWords = 4 * kWave;  // one quad per lane of the wave
     const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
     uint4* cnt4 = reinterpret_cast<uint4*>(cnt);
     const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
     if (tid == 0 && t_begin == 0) pc.edges += (unsigned long long)d;
@@ -701,37 +705,64 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
             pc.wedges += wl;
             __syncthreads();
         }
-        // keys with c >= 2 are gathered per lane in registers and applied in
-        // batches; counters are cleared as they are read
+        // keys with c >= 2: each wave stages its pairs in key order in the 64
+        // counter quads it has just read (256 packed (key offset, c) words per
+        // round) and applies them from consecutive lanes, so that an atomic
+        // instruction touches few 128-byte lines of supports; then it clears
+        // the quads.  n4 is a multiple of NT (tk is a multiple of 16K keys).
         const int32_t n4 = (int32_t)((int64_t)(p1 - p0) * tk / PER_WORD / 4);
-        PairBuf<kDenseBatch> pbuf;
         for (int32_t base = 0; base < n4; base += NT) {
             const int32_t w4 = base + tid;
-            uint4 x = make_uint4(0, 0, 0, 0);
-            if (w4 < n4) {
-                x = cnt4[w4];
-                if (x.x | x.y | x.z | x.w) cnt4[w4] = make_uint4(0, 0, 0, 0);
-            }
+            const uint4 x = cnt4[w4];
             const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
             uint32_t msk[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) msk[q] = ge2_mask<BITS>(xs[q]);
-            const int32_t kbase = klo + w4 * 4 * PER_WORD;
-            for (;;) {
+            if (__ballot((msk[0] | msk[1] | msk[2] | msk[3]) != 0)) {
+                uint32_t* win = reinterpret_cast<uint32_t*>(cnt4 + (w4 - lane));
+                const int32_t kwin = klo + (w4 - lane) * 4 * PER_WORD;
+                const uint32_t koff = (uint32_t)lane * 4 * PER_WORD;
+                for (;;) {
+                    const int32_t mine = __popc(msk[0]) + __popc(msk[1]) + __popc(msk[2]) + __popc(msk[3]);
+                    const int32_t incl = wave_incl_scan_i32(mine);
+                    const int32_t total = __shfl(incl, kWave - 1, kWave);
+                    if (total == 0) break;
+                    int32_t pos = incl - mine;
+                    wave_sync();  // every lane has read its quad before the window is written
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    while (msk[q] && pbuf.n < kDenseBatch) {
-                        const int bit = __ffs(msk[q]) - 1;
-                        msk[q] &= msk[q] - 1;
-                        const int f = bit / BITS;
-                        pbuf.push(kbase + q * PER_WORD + f, (int32_t)((xs[q] >> (f * BITS)) & FMASK));
+                    for (int q = 0; q < 4; ++q) {
+                        while (msk[q] && pos < kStageWords) {
+                            const int bit = __ffs(msk[q]) - 1;
+                            msk[q] &= msk[q] - 1;
+                            const int f = bit / BITS;
+                            win[pos++] = ((koff + (uint32_t)(q * PER_WORD + f)) << 16) | ((xs[q] >> (f * BITS)) & FMASK);
+                        }
                     }
+                    wave_sync();
+                    const int32_t n_st = min(total, kStageWords);
+                    int32_t key[kStageWords / kWave], c2[kStageWords / kWave], st[kStageWords / kWave];
+#pragma unroll
+                    for (int i = 0; i < kStageWords / kWave; ++i) {
+                        const int32_t j = lane + i * kWave;
+                        st[i] = 0;
+                        if (j < n_st) {
+                            const uint32_t e = win[j];
+                            key[i] = kwin + (int32_t)(e >> 16);
+                            c2[i] = (int32_t)(e & 0xffffu);
+                            st[i] = ap.state[key[i]];
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < kStageWords / kWave; ++i)
+                        if (st[i] == kLive) {
+                            atomic_add_i64(&ap.supp[key[i]], -choose2(c2[i]));
+                            ++pc.pairs;
+                        }
+                    wave_sync();  // the window is read before the next round rewrites it
                 }
-                if (!__ballot((msk[0] | msk[1] | msk[2] | msk[3]) != 0)) break;
-                ap.flush(pbuf, pc.pairs);
             }
+            cnt4[w4] = make_uint4(0, 0, 0, 0);
         }
-        ap.flush(pbuf, pc.pairs);
         __syncthreads();
     }
 }

@@ -42,7 +42,6 @@ constexpr int kBinWave = 0, kBinBitmap = 1;
 constexpr int kDefaultDenseDiv = 256;      // dense needs w[u] > n * bits / div (tip_opts.tune[0])
 constexpr int64_t kDefaultBitmapMax = 32768;  // bitmap path up to this many wedges (tip_opts.tune[1])
 constexpr int kApplyBatch = 4;             // (key, c) pairs a lane gathers before applying them
-constexpr int kDenseBatch = 8;             // the same in the dense kernel
 constexpr int64_t kItemWedges = 16384;     // a dense item of a light vertex has at most about this many wedges
 constexpr int kHeavySplit = 8;
 constexpr int kDensePasses = 4;            // key-range passes of one light dense work item
