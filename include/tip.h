@@ -85,10 +85,12 @@ typedef struct {
     int32_t tune[8]; /* update-kernel selection of the coarse-grained step;
                         a vertex of degree d with w wedges in its 2-hop
                         neighbourhood is updated by the dense key-range
-                        kernel when w > tune[1] and w > n_side * bits(d) /
+                        kernel when w > tune[1] and w > k * bits(d) /
                         tune[0] (bits(d) = 2, 4, 8, 16 for d <= 3, 15, 255,
-                        65535), else by a per-vertex kernel;
-                        tune[0]: 0 = 256; tune[1]: 0 = 32768;
+                        65535; k = ids below the largest live one), and one
+                        list tile of such counters fits the LDS, else by a
+                        per-vertex kernel;
+                        tune[0]: 0 = 1024; tune[1]: 0 = 2048;
                         tune[2]: compaction of the traversed lists at a
                         range start once the entries of vertices peeled
                         since the last compaction reach tune[2] per mille of

@@ -25,7 +25,7 @@ import numpy as np
 
 from . import graphgen, tip
 
-DEFAULT_GRID = {"dense_div": [32, 64, 128, 256], "bitmap_max": [8192, 16384, 32768, 65536]}
+DEFAULT_GRID = {"dense_div": [256, 512, 1024, 2048], "bitmap_max": [1024, 2048, 4096, 8192]}
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "libtip_autotune.json")
 
 

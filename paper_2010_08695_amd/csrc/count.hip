@@ -24,6 +24,32 @@ struct SideView {
     int64_t* oth_bfly;
 };
 
+// The highest-degree vertices of each side (the smallest ids, since ids are
+// ranks by descending degree) end most butterflies' priority wedges, so their
+// counts take a large share of all increments.  Each workgroup accumulates
+// the increments of ids below kCountHot in LDS and adds them to HBM once at
+// its end; one address in HBM takes only ~1e8 atomics per second.
+constexpr int kCountHot = 112;
+
+struct HotCounts {
+    unsigned long long v[2][kCountHot];
+
+    __device__ inline void clear() {
+        for (int i = threadIdx.x; i < 2 * kCountHot; i += blockDim.x) v[i / kCountHot][i % kCountHot] = 0;
+    }
+    __device__ inline void add(int64_t* bfly, int side, int64_t id, int64_t x) {
+        if (id < kCountHot) atomicAdd(&v[side][id], (unsigned long long)x);
+        else atomic_add_i64(&bfly[id], x);
+    }
+    // after a barrier that every thread of the workgroup reaches
+    __device__ inline void flush(int64_t* bfly_a, int64_t* bfly_b) const {
+        for (int i = threadIdx.x; i < 2 * kCountHot; i += blockDim.x) {
+            const unsigned long long x = v[i / kCountHot][i % kCountHot];
+            if (x) atomic_add_i64(i < kCountHot ? &bfly_a[i] : &bfly_b[i - kCountHot], (int64_t)x);
+        }
+    }
+};
+
 __device__ inline SideView side_view(const DevGraph& g, bool side_b, int64_t* bfly_a, int64_t* bfly_b) {
     SideView v;
     if (!side_b) {
@@ -34,14 +60,35 @@ __device__ inline SideView side_view(const DevGraph& g, bool side_b, int64_t* bf
     return v;
 }
 
+// Sum over the lanes of a wave that hold the same row (rows are sorted, so
+// equal rows are adjacent): the last lane of each run adds it to out[row].
+__device__ inline void wave_row_add(int32_t row, int64_t x, int64_t* out) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int64_t y = __shfl_up(x, d, kWave);
+        const int32_t ry = __shfl_up(row, d, kWave);
+        if (lane >= d && ry == row) x += y;
+    }
+    const int32_t rn = __shfl_down(row, 1, kWave);
+    if (row >= 0 && (lane == kWave - 1 || rn != row) && x) atomic_add_i64(&out[row], x);
+}
+
+// Counting wedges of every start vertex; CSR rows are contiguous, so the
+// per-edge terms are summed per row inside each wave before the atomic.
 __global__ void k_count_work(DevGraph g, int64_t* work) {
-    GRID_STRIDE(p, g.m) {
-        const int32_t x = g.a_row[p], y = g.a_adj[p];
-        const int64_t l1 = min(g.b_cut[y], g.a_rev[p]);
-        if (l1) atomic_add_i64(&work[x], l1);
-        const int32_t yb = g.b_row[p], xb = g.b_adj[p];
-        const int64_t l2 = min(g.a_cut[xb], g.b_rev[p]);
-        if (l2) atomic_add_i64(&work[(int64_t)g.n_a + yb], l2);
+    UNIFORM_STRIDE(base, g.m) {
+        const int64_t p = base + threadIdx.x;
+        int32_t x = -1, yb = -1;
+        int64_t l1 = 0, l2 = 0;
+        if (p < g.m) {
+            x = g.a_row[p];
+            l1 = min(g.b_cut[g.a_adj[p]], g.a_rev[p]);
+            yb = g.b_row[p];
+            l2 = min(g.a_cut[g.b_adj[p]], g.b_rev[p]);
+        }
+        wave_row_add(x, l1, work);
+        wave_row_add(yb, l2, work + g.n_a);
     }
 }
 
@@ -62,15 +109,18 @@ __global__ void __launch_bounds__(kSmallThreads)
 k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, const int64_t* __restrict__ work,
               int64_t* bfly_a, int64_t* bfly_b) {
     __shared__ WaveLds WL[kSmallThreads / kWave];
+    __shared__ HotCounts hot;
     const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     WaveLds& W = WL[wid];
     for (int s = lane; s < kSmallSlots; s += kWave) W.tab[s] = 0;
-    wave_sync();
+    hot.clear();
+    __syncthreads();
     const int64_t n_items = ctl->n_items[0];
     const int nw = kSmallThreads / kWave;
     for (int64_t it = (int64_t)blockIdx.x * nw + wid; it < n_items; it += (int64_t)gridDim.x * nw) {
         const int32_t item = items[it];
         const bool side_b = item >= g.n_a;
+        const int own = side_b ? 1 : 0;
         const int32_t x = side_b ? item - g.n_a : item;
         const SideView sv = side_view(g, side_b, bfly_a, bfly_b);
         const int64_t e0 = sv.own_off[x], d = sv.own_off[x + 1] - e0;
@@ -123,7 +173,7 @@ k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, con
                 if (c > 1) atomicAdd(reinterpret_cast<unsigned long long*>(&W.acc[j]), (unsigned long long)(c - 1));
             }
             wave_sync();
-            if (lane < gs && W.acc[lane]) atomic_add_i64(&sv.oth_bfly[y], W.acc[lane]);
+            if (lane < gs && W.acc[lane]) hot.add(sv.oth_bfly, 1 - own, y, W.acc[lane]);
             wave_sync();
         }
         // pass 3: start and end vertices gain C(c, 2)
@@ -134,16 +184,18 @@ k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, con
                 const int64_t c = (int64_t)(v & 0xffffffffull);
                 if (c >= 2) {
                     const int64_t b = choose2(c);
-                    atomic_add_i64(&sv.own_bfly[(int64_t)(v >> 32) - 1], b);
+                    hot.add(sv.own_bfly, own, (int64_t)(v >> 32) - 1, b);
                     local += b;
                 }
                 W.tab[s] = 0;
             }
         }
         local = wave_sum_i64(local);
-        if (lane == 0 && local) atomic_add_i64(&sv.own_bfly[x], local);
+        if (lane == 0 && local) hot.add(sv.own_bfly, own, x, local);
         wave_sync();
     }
+    __syncthreads();
+    hot.flush(bfly_a, bfly_b);
 }
 
 // Slice of the counting wedges of edge e restricted to keys [klo, khi).
@@ -166,8 +218,10 @@ __global__ void __launch_bounds__(kBigThreads)
 k_count_big(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64_t* bfly_a, int64_t* bfly_b,
             SpillArena spa, Ctl* ctl_rw) {
     __shared__ BigLds L;
+    __shared__ HotCounts hot;
     constexpr int NT = kBigThreads;
     const int tid = threadIdx.x;
+    hot.clear();
     bm_clear<NT>(L, kBmBits);
     if (tid == 0) L.spill_n = 0;
     __syncthreads();
@@ -177,6 +231,7 @@ k_count_big(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64
     for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int32_t item = items[it];
         const bool side_b = item >= g.n_a;
+        const int own = side_b ? 1 : 0;
         const int32_t x = side_b ? item - g.n_a : item;
         const SideView sv = side_view(g, side_b, bfly_a, bfly_b);
         const int64_t e0 = sv.own_off[x], d = sv.own_off[x + 1] - e0;
@@ -227,7 +282,7 @@ k_count_big(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64
                     if (c > 1) atomicAdd(reinterpret_cast<unsigned long long*>(&L.acc[j]), (unsigned long long)(c - 1));
                 }
                 __syncthreads();
-                if (tid < gs && L.acc[tid]) atomic_add_i64(&sv.oth_bfly[sv.own_adj[e0 + g0 + tid]], L.acc[tid]);
+                if (tid < gs && L.acc[tid]) hot.add(sv.oth_bfly, 1 - own, sv.own_adj[e0 + g0 + tid], L.acc[tid]);
                 __syncthreads();
             }
             // pass 3
@@ -237,7 +292,7 @@ k_count_big(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64
                 if (v) {
                     const int64_t c = 1 + (int64_t)(v & 0xffffffffull);
                     const int64_t b = choose2(c);
-                    atomic_add_i64(&sv.own_bfly[klo + (int64_t)(v >> 32) - 1], b);
+                    hot.add(sv.own_bfly, own, klo + (int64_t)(v >> 32) - 1, b);
                     local += b;
                 }
             }
@@ -246,18 +301,20 @@ k_count_big(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64
             for (int32_t i = tid; i < nsp; i += NT) {
                 const int32_t k = sp.list[i];
                 const int64_t b = choose2(1 + (int64_t)sp.dense[k]);
-                atomic_add_i64(&sv.own_bfly[klo + (int64_t)k], b);
+                hot.add(sv.own_bfly, own, klo + (int64_t)k, b);
                 local += b;
                 sp.dense[k] = 0;
             }
             const int64_t total = block_sum_i64<NT>(L, local);
-            if (tid == 0 && total) atomic_add_i64(&sv.own_bfly[x], total);
+            if (tid == 0 && total) hot.add(sv.own_bfly, own, x, total);
             bm_clear<NT>(L, khi - klo);
             if (tid == 0) L.spill_n = 0;
             __syncthreads();
         }
     }
     if (tid == 0 && spills) atomicAdd(&ctl_rw->spills, spills);
+    __syncthreads();
+    hot.flush(bfly_a, bfly_b);
 }
 
 }  // namespace

@@ -39,8 +39,8 @@ constexpr int kDenseLdsBytes = 32768;      // counter bytes per dense workgroup 
 constexpr int kDenseKinds = 4;
 constexpr int kBins = 2 + 2 * kDenseKinds;
 constexpr int kBinWave = 0, kBinBitmap = 1;
-constexpr int kDefaultDenseDiv = 256;      // dense needs w[u] > n * bits / div (tip_opts.tune[0])
-constexpr int64_t kDefaultBitmapMax = 32768;  // bitmap path up to this many wedges (tip_opts.tune[1])
+constexpr int kDefaultDenseDiv = 1024;     // dense needs w[u] > n * bits / div (tip_opts.tune[0])
+constexpr int64_t kDefaultBitmapMax = 2048;   // bitmap path up to this many wedges (tip_opts.tune[1])
 constexpr int kApplyBatch = 4;             // (key, c) pairs a lane gathers before applying them
 constexpr int64_t kItemWedges = 16384;     // a dense item of a light vertex has at most about this many wedges
 constexpr int kHeavySplit = 8;

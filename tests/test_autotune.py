@@ -20,13 +20,13 @@ def test_choose_fastest_and_tie_break():
 def test_tune_graph_with_fake_timer():
     g = gg.complete_bipartite(3, 3)
     theta = np.arange(3)
-    cost = {(64, 16384): 1.0}
+    cost = {(512, 4096): 1.0}
 
     def timer(g, side, tune):
         return theta, cost.get(tuple(tune), 10.0 + tune[0] / 1000)
 
     r = autotune.tune_graph(g, 0, timer=timer)
-    assert r["tune"] == [64, 16384] and r["ms"] == 1.0
+    assert r["tune"] == [512, 4096] and r["ms"] == 1.0
     assert len(r["trials"]) == len(autotune.DEFAULT_GRID["dense_div"]) * len(autotune.DEFAULT_GRID["bitmap_max"])
 
 
