@@ -105,7 +105,10 @@ __global__ void k_fd_order(const int64_t* __restrict__ task_w, int32_t S, int32_
     }
 }
 
-__global__ void k_fd_reset_head(Ctl* ctl) { ctl->fd_head = 0; }
+__global__ void k_fd_reset_board(FdBoard* b) {
+    int32_t* w = reinterpret_cast<int32_t*>(b);
+    for (int i = threadIdx.x; i < (int)(sizeof(FdBoard) / 4); i += blockDim.x) w[i] = 0;
+}
 
 // LDS of the fine-grained kernel.  The per-wave hash tables (light peeled
 // vertices) and the bitmap + repeat table (heavy ones) are used in separate
@@ -125,10 +128,20 @@ struct FdLds {
     int64_t red[kFdThreads / kWave];
     int32_t spill_n;
     int32_t flag;
+    int32_t wave_head;   // next per-wave update of the level
 };
 
+// Next entry of the level's per-wave update list for the calling wavefront.
+__device__ inline int32_t fd_next_wave_item(FdLds& L) {
+    int32_t q = 0;
+    if ((threadIdx.x & (kWave - 1)) == 0) q = atomicAdd(&L.wave_head, 1);
+    return __shfl(q, 0, kWave);
+}
+
+// Block exclusive scan of 64-bit values (all threads take part); returns the
+// thread's offset and the total.
 template <int NT>
-__device__ inline int32_t fd_scan_i32(FdLds& L, int32_t x, int32_t& total) {
+__device__ inline int64_t fd_scan_i64(FdLds& L, int64_t x, int64_t& total) {
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int64_t inc = wave_incl_scan_i64<NT>(x);
     __syncthreads();
@@ -141,9 +154,9 @@ __device__ inline int32_t fd_scan_i32(FdLds& L, int32_t x, int32_t& total) {
         off += w < wid ? v : 0;
         tot += v;
     }
-    total = (int32_t)tot;
+    total = tot;
     __syncthreads();
-    return (int32_t)(off + inc - x);
+    return off + inc - x;
 }
 
 template <int NT>
@@ -203,6 +216,509 @@ __device__ inline void fd_rep_insert(FdLds& L, const Spill& sp, uint32_t k) {
     }
 }
 
+// Where the state of the subset being peeled lives.  Subsets of at most
+// kFdLdsVerts vertices keep supports, liveness, heavy flags and the vertex
+// lists in LDS for the whole task (the supports take LDS atomics, and the
+// next level's minimum is tracked on the fly); larger ones keep them in HBM.
+struct FdSmall {
+    int64_t sup[kFdLdsVerts];
+    int32_t vert[kFdLdsVerts];
+    uint16_t lc[kFdLdsVerts], ln[kFdLdsVerts], pl[kFdLdsVerts], ph[kFdLdsVerts];
+    uint8_t flag[kFdLdsVerts];     // bit 0: alive, bit 1: heavy
+    long long upd_min;             // least support left by this level's decrements
+    int64_t red_min[kFdThreads / kWave];
+};
+constexpr uint8_t kFdAlive = 1, kFdHeavy = 2;
+constexpr int kFdPack = 21;  // packed per-level counts: per-wave | heavy << 21 | kept << 42
+static_assert(sizeof(FdLds::Shared) >= (size_t)kFdWaveKeys * (kFdThreads / kWave), "per-wave counters fit the union");
+
+// Decrements of the subset's dead vertices are applied too: their support is
+// never read again (each level reads the live list only), and skipping the
+// liveness load shortens every update's chain of memory round trips.
+struct FdHbmState {
+    int64_t* sup;
+    int32_t* alive;
+    const int32_t* vert;
+    __device__ inline bool live(int32_t) const { return true; }
+    __device__ inline int32_t vtx(int32_t x) const { return vert[x]; }
+    __device__ inline void dec(int32_t w, int64_t d) const { atomic_add_i64(&sup[w], -d); }
+};
+
+struct FdLdsState {
+    FdSmall* S;
+    __device__ inline bool live(int32_t w) const { return (S->flag[w] & kFdAlive) != 0; }
+    __device__ inline int32_t vtx(int32_t x) const { return S->vert[x]; }
+    __device__ inline void dec(int32_t w, int64_t d) const {
+        const int64_t old = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&S->sup[w]),
+                                               (unsigned long long)(-d));
+        atomicMin(&S->upd_min, (long long)(old - d));
+    }
+};
+
+// Update of one light peeled vertex x (few wedges inside the subset) by one
+// wavefront with its private hash table of `slots` entries.
+template <class St>
+__device__ inline void fd_update_light(const DevGraph& g, const FdBuffers& fb, FdLds& L, unsigned long long* tab,
+                                       int32_t x, uint32_t slots, const St& st, unsigned long long& wedges,
+                                       unsigned long long& pairs) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const uint32_t mask = slots - 1;
+    const int32_t ux = st.vtx(x);
+    const int64_t e0 = g.a_off[ux], d = g.a_off[ux + 1] - e0;
+    for (int64_t g0 = 0; g0 < d; g0 += kWave) {
+        const int gs = (int)min<int64_t>(kWave, d - g0);
+        int64_t len = 0;
+        if (lane < gs) {
+            const int64_t e = e0 + g0 + lane;
+            L.wsbeg[wid][lane] = fb.fd_beg[e];
+            len = fb.fd_len[e];
+        }
+        const int64_t inc = wave_incl_scan_i64<kWave>(len);
+        L.wpre[wid][lane] = inc - len;
+        const int64_t tot = __shfl(inc, kWave - 1, kWave);
+        if (lane == 0) L.wpre[wid][kWave] = tot;
+        wave_sync();
+        int lo = 0;
+        for (int64_t i0 = lane; i0 < tot; i0 += 4 * kWave) {
+            int32_t ws[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int64_t i = i0 + k * kWave;
+                ws[k] = x;
+                if (i < tot) {
+                    while (lo + 1 < gs && L.wpre[wid][lo + 1] <= i) ++lo;
+                    ws[k] = fb.pcsc[L.wsbeg[wid][lo] + (i - L.wpre[wid][lo])];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (ws[k] != x) fd_wave_insert(tab, (uint32_t)ws[k], mask);
+        }
+        if (lane == 0) wedges += (unsigned long long)(tot - gs);
+        wave_sync();
+    }
+    for (uint32_t sl = lane; sl < slots; sl += kWave) {
+        const unsigned long long v = tab[sl];
+        if (v) {
+            tab[sl] = 0;
+            const int64_t c = (int64_t)(v & 0xffffffffull);
+            const int32_t w = (int32_t)((v >> 32) - 1);
+            if (c >= 2 && st.live(w)) {
+                st.dec(w, choose2(c));
+                ++pairs;
+            }
+        }
+    }
+    wave_sync();
+}
+
+// Counters of value >= 2 in a word of four 8-bit counters: the top bit of
+// every such byte is set in the result.
+__device__ inline uint32_t ge2_bytes(uint32_t v) {
+    const uint32_t t = v & 0xfefefefeu;
+    return (((t & 0x7f7f7f7fu) + 0x7f7f7f7fu) | t) & 0x80808080u;
+}
+
+// Update of one peeled vertex x of degree at most 255 in a subset of at most
+// kFdWaveKeys vertices by one wavefront: one 8-bit LDS counter per vertex of
+// the subset (c(x, w) <= d_x fits), scanned and cleared afterwards.
+template <class St>
+__device__ inline void fd_update_wave_dense(const DevGraph& g, const FdBuffers& fb, FdLds& L, uint32_t* cnt,
+                                            int32_t x, int32_t n_i, const St& st, unsigned long long& wedges,
+                                            unsigned long long& pairs) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int32_t ux = st.vtx(x);
+    const int64_t e0 = g.a_off[ux], d = g.a_off[ux + 1] - e0;
+    for (int64_t g0 = 0; g0 < d; g0 += kWave) {
+        const int gs = (int)min<int64_t>(kWave, d - g0);
+        int64_t len = 0;
+        if (lane < gs) {
+            const int64_t e = e0 + g0 + lane;
+            L.wsbeg[wid][lane] = fb.fd_beg[e];
+            len = fb.fd_len[e];
+        }
+        const int64_t inc = wave_incl_scan_i64<kWave>(len);
+        L.wpre[wid][lane] = inc - len;
+        const int64_t tot = __shfl(inc, kWave - 1, kWave);
+        if (lane == 0) L.wpre[wid][kWave] = tot;
+        wave_sync();
+        int lo = 0;
+        for (int64_t i0 = lane; i0 < tot; i0 += 4 * kWave) {
+            int32_t ws[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int64_t i = i0 + k * kWave;
+                ws[k] = x;
+                if (i < tot) {
+                    while (lo + 1 < gs && L.wpre[wid][lo + 1] <= i) ++lo;
+                    ws[k] = fb.pcsc[L.wsbeg[wid][lo] + (i - L.wpre[wid][lo])];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (ws[k] != x) atomicAdd(&cnt[ws[k] >> 2], 1u << ((ws[k] & 3) * 8));
+        }
+        if (lane == 0) wedges += (unsigned long long)(tot - gs);
+        wave_sync();
+    }
+    const int32_t nw = (n_i + 3) >> 2;
+    for (int32_t i = lane; i < nw; i += kWave) {
+        const uint32_t v = cnt[i];
+        if (v) {
+            cnt[i] = 0;
+            uint32_t m = ge2_bytes(v);
+            while (m) {
+                const int f = (__ffs(m) - 1) >> 3;
+                m &= m - 1;
+                const int32_t w = i * 4 + f;
+                if (st.live(w)) {
+                    st.dec(w, choose2((int64_t)((v >> (f * 8)) & 0xffu)));
+                    ++pairs;
+                }
+            }
+        }
+    }
+    wave_sync();
+}
+
+// Update of one heavy peeled vertex x by the whole workgroup: one LDS bit
+// per key of a kFdBits-key tile, repeats in the LDS table (spilling to HBM).
+template <class St>
+__device__ inline void fd_update_heavy(const DevGraph& g, const FdBuffers& fb, FdLds& L, const Spill& sp,
+                                       int32_t x, int32_t n_i, const St& st, unsigned long long& wedges,
+                                       unsigned long long& pairs, unsigned long long& spills) {
+    constexpr int NT = kFdThreads;
+    constexpr int NW = NT / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const bool multi = n_i > kFdBits;
+    const int32_t ux = st.vtx(x);
+    const int64_t e0 = g.a_off[ux], d = g.a_off[ux + 1] - e0;
+    for (int32_t klo = 0; klo < n_i; klo += kFdBits) {
+        const int32_t khi = (int32_t)min<int64_t>(n_i, (int64_t)klo + kFdBits);
+        const bool self_in = x >= klo && x < khi;
+        for (int64_t g0 = 0; g0 < d; g0 += kGroup) {
+            const int gs = (int)min<int64_t>(kGroup, d - g0);
+            int64_t len = 0;
+            if (tid < gs) {
+                const int64_t e = e0 + g0 + tid;
+                int64_t a = fb.fd_beg[e], b = a + fb.fd_len[e];
+                if (multi) {
+                    a = lower_bound_i32(fb.pcsc, a, b, klo);
+                    b = lower_bound_i32(fb.pcsc, a, b, khi);
+                }
+                L.sbeg[tid] = a;
+                len = b - a;
+            }
+            // exclusive scan of run lengths into L.pre
+            const int64_t x64 = tid < gs ? len : 0;
+            const int64_t incl = wave_incl_scan_i64<NT>(x64);
+            __syncthreads();
+            if (lane == kWave - 1) L.red[wid] = incl;
+            __syncthreads();
+            int64_t off = 0, tot = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const int64_t v = L.red[w];
+                off += w < wid ? v : 0;
+                tot += v;
+            }
+            if (tid < gs) L.pre[tid] = off + incl - x64;
+            if (tid == 0) L.pre[gs] = tot;
+            __syncthreads();
+            for (int64_t i = tid; i < tot; i += NT) {
+                int lo = 0, hi = gs;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (L.pre[mid] <= i) lo = mid;
+                    else hi = mid;
+                }
+                const int32_t w = fb.pcsc[L.sbeg[lo] + (i - L.pre[lo])];
+                if (w != x) {
+                    const uint32_t k = (uint32_t)(w - klo);
+                    const uint32_t bit = 1u << (k & 31);
+                    if (atomicOr(&L.u.big.bm[k >> 5], bit) & bit) fd_rep_insert(L, sp, k);
+                }
+            }
+            if (tid == 0) wedges += (unsigned long long)(tot - (self_in ? gs : 0));
+            __syncthreads();
+        }
+        for (int sl = tid; sl < kFdRep; sl += NT) {
+            const unsigned long long v = L.u.big.rep[sl];
+            if (v) {
+                const int32_t w = klo + (int32_t)((v >> 32) - 1);
+                if (st.live(w)) {
+                    st.dec(w, choose2(1 + (int64_t)(v & 0xffffffffull)));
+                    ++pairs;
+                }
+            }
+        }
+        const int32_t nsp = L.spill_n;
+        if (tid == 0) spills += (unsigned long long)nsp;
+        for (int32_t i = tid; i < nsp; i += NT) {
+            const int32_t k = sp.list[i];
+            const int32_t w = klo + k;
+            if (st.live(w)) {
+                st.dec(w, choose2(1 + (int64_t)sp.dense[k]));
+                ++pairs;
+            }
+            sp.dense[k] = 0;
+        }
+        __syncthreads();
+        const int32_t words = (khi - klo + 31) >> 5;
+        for (int w = tid; w < words; w += NT) L.u.big.bm[w] = 0;
+        for (int sl = tid; sl < kFdRep; sl += NT) L.u.big.rep[sl] = 0;
+        if (tid == 0) L.spill_n = 0;
+        __syncthreads();
+    }
+}
+
+// Per-wave updates taken from a help-board slot until its published list is
+// exhausted: one atomic on the slot word hands out kFdHelpChunk entries;
+// finished entries are counted in `done` after their decrements are visible
+// device-wide.
+template <class St>
+__device__ inline void fd_help_slot(const DevGraph& g, const FdBuffers& fb, FdLds& L, unsigned long long* tab,
+                                    uint32_t* wcnt, const int32_t* pl, const int64_t* fw, int32_t n_i,
+                                    FdHelpSlot* hs, const St& st, unsigned long long& wedges,
+                                    unsigned long long& pairs) {
+    const int lane = threadIdx.x & (kWave - 1);
+    for (;;) {
+        unsigned long long wv = 0;
+        if (lane == 0) wv = atomicAdd(&hs->word, (unsigned long long)kFdHelpChunk);
+        wv = __shfl(wv, 0, kWave);
+        const uint32_t q0 = (uint32_t)wv, nl = (uint32_t)(wv >> 32);
+        if (q0 >= nl) break;
+        const uint32_t q1 = min(nl, q0 + (uint32_t)kFdHelpChunk);
+        __threadfence();
+        for (uint32_t q = q0; q < q1; ++q) {
+            const int32_t x = pl[q];
+            if (n_i <= kFdWaveKeys) fd_update_wave_dense(g, fb, L, wcnt, x, n_i, st, wedges, pairs);
+            else fd_update_light(g, fb, L, tab, x, min<uint32_t>(kFdWaveSlots, wave_slots(fw[x])), st, wedges, pairs);
+        }
+        __threadfence();
+        if (lane == 0) atomicAdd(&hs->done, (int32_t)(q1 - q0));
+    }
+}
+
+// Which update a peeled vertex j of the subset takes.  In subsets of at most
+// kFdWaveKeys vertices every vertex of degree <= 255 with at most
+// kFdWaveDenseMax wedges inside the subset is updated by one wavefront with
+// dense 8-bit counters; in larger subsets only those with at most kFdWaveMax
+// wedges are (with a hash table).  The others are heavy: the whole workgroup
+// updates them one at a time.
+__device__ inline bool fd_heavy(const DevGraph& g, const FdBuffers& fb, int64_t P0, int32_t n_i, int32_t j) {
+    const int64_t w = fb.fd_w[P0 + j];
+    if (n_i <= kFdWaveKeys) {
+        const int32_t v = fb.fd_vert[P0 + j];
+        return g.a_off[v + 1] - g.a_off[v] > 255 || w > kFdWaveDenseMax;
+    }
+    return w > kFdWaveMax;
+}
+
+// Level loop of a subset whose state lives in HBM.
+__device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const int64_t* __restrict__ init,
+                                   int64_t P0, int32_t n_i, FdLds& L, unsigned long long* tab, const Spill& sp,
+                                   FdHelpSlot* hs, unsigned long long& wedges, unsigned long long& pairs,
+                                   unsigned long long& levels, unsigned long long& spills) {
+    constexpr int NT = kFdThreads;
+    constexpr int NW = NT / kWave;
+    const int tid = threadIdx.x, wid = tid / kWave;
+    int32_t* lc = fb.lst[0] + P0;
+    int32_t* ln = fb.lst[1] + P0;
+    int32_t* pl = fb.lst[2] + P0;
+    int32_t* ph = fb.lst[3] + P0;
+    int64_t* sup = fb.supp_fd + P0;
+    const int64_t* fw = fb.fd_w + P0;
+    int32_t* alive = fb.alive + P0;
+    const int32_t* vert = fb.fd_vert + P0;
+    const FdHbmState st{sup, alive, vert};
+    const bool wave_dense = n_i <= kFdWaveKeys;
+    uint32_t* wcnt = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(&L.u) + (size_t)wid * kFdWaveKeys);
+    for (int32_t j = tid; j < n_i; j += NT) {
+        lc[j] = j;
+        sup[j] = init[vert[j]];
+        alive[j] = kFdAlive | (fd_heavy(g, fb, P0, n_i, j) ? kFdHeavy : 0);
+    }
+    __syncthreads();
+    int32_t n_live = n_i;
+    int64_t level = 0;
+    while (n_live > 0) {
+        int64_t mn = INT64_MAX;
+        for (int32_t j = tid; j < n_live; j += NT) {
+            const int64_t sv = sup[lc[j]];
+            mn = sv < mn ? sv : mn;
+        }
+        mn = fd_min<NT>(L, mn);
+        level = mn > level ? mn : level;
+        // peel every live vertex at or below the level; per-wave and heavy
+        // ones go to separate lists, vertices without support left need no
+        // update at all.  Each thread takes a contiguous run of the live
+        // list; one block scan of packed counts gives every offset.
+        const int32_t per = (n_live + NT - 1) / NT;
+        const int32_t j0 = min(n_live, tid * per), j1 = min(n_live, j0 + per);
+        int64_t cnt = 0;
+        for (int32_t j = j0; j < j1; ++j) {
+            const int32_t x = lc[j];
+            const int64_t sx = sup[x];
+            if (sx > level) cnt += 1ll << (2 * kFdPack);
+            else if (sx > 0) cnt += (alive[x] & kFdHeavy) ? (1ll << kFdPack) : 1ll;
+        }
+        int64_t tot;
+        int64_t off = fd_scan_i64<NT>(L, cnt, tot);
+        const int64_t pm = (1ll << kFdPack) - 1;
+        int32_t ol = (int32_t)(off & pm), oh = (int32_t)((off >> kFdPack) & pm), ok = (int32_t)(off >> (2 * kFdPack));
+        if (tid == 0) L.wave_head = 0;
+        const int32_t n_light = (int32_t)(tot & pm), n_heavy = (int32_t)((tot >> kFdPack) & pm);
+        const int32_t n_keep = (int32_t)(tot >> (2 * kFdPack));
+        for (int32_t j = j0; j < j1; ++j) {
+            const int32_t x = lc[j];
+            const int64_t sx = sup[x];
+            if (sx > level) {
+                ln[ok++] = x;
+            } else {
+                const int32_t f = alive[x];
+                alive[x] = f & ~kFdAlive;
+                fb.theta[vert[x]] = level;
+                if (sx > 0) {
+                    if (f & kFdHeavy) ph[oh++] = x;
+                    else pl[ol++] = x;
+                }
+            }
+        }
+        levels += tid == 0;
+        if (hs && n_light >= kFdHelpLevelMin) {
+            // publish the level's per-wave updates on the help board, take
+            // entries like the helpers do, then wait for every taken entry
+            // (levels with fewer updates are not worth the fences)
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) {
+                atomicExch(&hs->done, 0);
+                __threadfence();
+                atomicExch(&hs->word, (unsigned long long)n_light << 32);
+            }
+            __syncthreads();
+            fd_help_slot(g, fb, L, tab, wcnt, pl, fw, n_i, hs, st, wedges, pairs);
+            __syncthreads();
+            if (tid == 0)
+                while (__hip_atomic_load(&hs->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n_light)
+                    __builtin_amdgcn_s_sleep(2);
+            __syncthreads();
+            __threadfence();
+        } else {
+            __syncthreads();
+            for (int32_t q = fd_next_wave_item(L); q < n_light; q = fd_next_wave_item(L)) {
+                const int32_t x = pl[q];
+                if (wave_dense) fd_update_wave_dense(g, fb, L, wcnt, x, n_i, st, wedges, pairs);
+                else fd_update_light(g, fb, L, tab, x, min<uint32_t>(kFdWaveSlots, wave_slots(fw[x])), st, wedges, pairs);
+            }
+        }
+        __syncthreads();
+        for (int32_t q = 0; q < n_heavy; ++q) fd_update_heavy(g, fb, L, sp, ph[q], n_i, st, wedges, pairs, spills);
+        int32_t* tmp = lc;
+        lc = ln;
+        ln = tmp;
+        n_live = n_keep;
+    }
+}
+
+// Level loop of a subset whose state lives in LDS.  Each level makes one
+// pass over the live list (each thread a contiguous run): one block scan
+// gives the offsets of the light, heavy and kept vertices and the least
+// kept support.  The next level's minimum is the least of that and of the
+// supports the decrements leave behind: a kept vertex that no decrement
+// touched still has the support read in the pass.
+__device__ inline void fd_peel_lds(const DevGraph& g, const FdBuffers& fb, const int64_t* __restrict__ init,
+                                   int64_t P0, int32_t n_i, FdLds& L, FdSmall& S, unsigned long long* tab,
+                                   const Spill& sp, unsigned long long& wedges, unsigned long long& pairs,
+                                   unsigned long long& levels, unsigned long long& spills) {
+    constexpr int NT = kFdThreads;
+    constexpr int NW = NT / kWave;
+    constexpr int kSh = kFdPack;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    uint32_t* wcnt = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(&L.u) + (size_t)wid * kFdWaveKeys);
+    const FdLdsState st{&S};
+    int64_t mn = INT64_MAX;
+    for (int32_t j = tid; j < n_i; j += NT) {
+        const int32_t v = fb.fd_vert[P0 + j];
+        const int64_t s0 = init[v];
+        S.vert[j] = v;
+        S.sup[j] = s0;
+        S.flag[j] = kFdAlive | (fd_heavy(g, fb, P0, n_i, j) ? kFdHeavy : 0);
+        S.lc[j] = (uint16_t)j;
+        mn = s0 < mn ? s0 : mn;
+    }
+    mn = fd_min<NT>(L, mn);
+    uint16_t* lc = S.lc;
+    uint16_t* ln = S.ln;
+    int32_t n_live = n_i;
+    int64_t level = 0;
+    while (n_live > 0) {
+        level = mn > level ? mn : level;
+        const int32_t per = (n_live + NT - 1) / NT;
+        const int32_t j0 = min(n_live, tid * per), j1 = min(n_live, j0 + per);
+        int64_t cnt = 0, kmin = INT64_MAX;
+        for (int32_t j = j0; j < j1; ++j) {
+            const int32_t x = lc[j];
+            const int64_t sx = S.sup[x];
+            if (sx > level) {
+                cnt += 1ll << (2 * kSh);
+                kmin = sx < kmin ? sx : kmin;
+            } else if (sx > 0) {
+                cnt += (S.flag[x] & kFdHeavy) ? (1ll << kSh) : 1ll;
+            }
+        }
+        // block exclusive scan of the packed counts and block minimum
+        const int64_t inc = wave_incl_scan_i64<NT>(cnt);
+        const int64_t wmin = wave_min_i64(kmin);
+        __syncthreads();
+        if (lane == kWave - 1) L.red[wid] = inc;
+        if (lane == 0) S.red_min[wid] = wmin;
+        if (tid == 0) S.upd_min = LLONG_MAX;
+        __syncthreads();
+        int64_t off = 0, tot = 0, bmin = INT64_MAX;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int64_t v = L.red[w];
+            off += w < wid ? v : 0;
+            tot += v;
+            bmin = S.red_min[w] < bmin ? S.red_min[w] : bmin;
+        }
+        const int64_t mask = (1ll << kSh) - 1;
+        off += inc - cnt;
+        int32_t ol = (int32_t)(off & mask), oh = (int32_t)((off >> kSh) & mask), ok = (int32_t)(off >> (2 * kSh));
+        if (tid == 0) L.wave_head = 0;
+        const int32_t n_light = (int32_t)(tot & mask), n_heavy = (int32_t)((tot >> kSh) & mask);
+        const int32_t n_keep = (int32_t)(tot >> (2 * kSh));
+        for (int32_t j = j0; j < j1; ++j) {
+            const int32_t x = lc[j];
+            const int64_t sx = S.sup[x];
+            if (sx > level) {
+                ln[ok++] = (uint16_t)x;
+            } else {
+                S.flag[x] &= (uint8_t)~kFdAlive;
+                fb.theta[S.vert[x]] = level;
+                if (sx > 0) {
+                    if (S.flag[x] & kFdHeavy) S.ph[oh++] = (uint16_t)x;
+                    else S.pl[ol++] = (uint16_t)x;
+                }
+            }
+        }
+        __syncthreads();
+        levels += tid == 0;
+        for (int32_t q = fd_next_wave_item(L); q < n_light; q = fd_next_wave_item(L))
+            fd_update_wave_dense(g, fb, L, wcnt, (int32_t)S.pl[q], n_i, st, wedges, pairs);
+        __syncthreads();
+        for (int32_t q = 0; q < n_heavy; ++q) fd_update_heavy(g, fb, L, sp, (int32_t)S.ph[q], n_i, st, wedges, pairs, spills);
+        __syncthreads();
+        mn = min<int64_t>(bmin, (int64_t)S.upd_min);
+        uint16_t* tmp = lc;
+        lc = ln;
+        ln = tmp;
+        n_live = n_keep;
+    }
+}
+
 // One workgroup peels one subset at a time, taking subsets from the
 // workload-sorted queue (dynamic allocation).  Inside a subset it runs
 // bottom-up peeling level by level: the level is max(level, minimum live
@@ -212,10 +728,10 @@ __device__ inline void fd_rep_insert(FdLds& L, const Spill& sp, uint32_t k) {
 // ones one per wavefront with a private hash table, heavy ones one at a time
 // with the whole workgroup and a key bitmap.
 __global__ void __launch_bounds__(kFdThreads)
-k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, int32_t* head, SpillArena spa) {
+k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoard* board, SpillArena spa) {
     __shared__ FdLds L;
+    __shared__ FdSmall S;
     constexpr int NT = kFdThreads;
-    constexpr int NW = NT / kWave;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     {
         unsigned long long* all = &L.u.wtab[0][0];
@@ -226,7 +742,7 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, int32
     const Spill sp{spa.dense + (int64_t)blockIdx.x * spa.stride, spa.list + (int64_t)blockIdx.x * spa.stride};
     unsigned long long* tab = L.u.wtab[wid];
     for (;;) {
-        if (tid == 0) L.flag = atomicAdd(head, 1);
+        if (tid == 0) L.flag = atomicAdd(&board->head, 1);
         __syncthreads();
         const int32_t t = L.flag;
         __syncthreads();
@@ -234,207 +750,38 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, int32
         // one task = one subset of one graph: tasks[t] = job << 32 | subset,
         // or, for a single graph, its own workload-ordered subset list
         const FdJob& J = tasks ? jobs.list[tasks[t] >> 32] : jobs.one;
-        const DevGraph& g = J.g;
         const FdBuffers& fb = J.fb;
-        const int64_t* __restrict__ init = J.init;
         const int32_t sub = tasks ? (int32_t)(tasks[t] & 0xffffffffll) : fb.order[t];
         const int64_t P0 = fb.sub_off[sub];
         const int32_t n_i = (int32_t)(fb.sub_off[sub + 1] - P0);
         if (n_i == 0) continue;
         unsigned long long wedges = 0, pairs = 0, levels = 0, spills = 0;
-        int32_t* lc = fb.lst[0] + P0;
-        int32_t* ln = fb.lst[1] + P0;
-        int32_t* pl = fb.lst[2] + P0;
-        int32_t* ph = fb.lst[3] + P0;
-        int64_t* sup = fb.supp_fd + P0;
-        const int64_t* fw = fb.fd_w + P0;
-        int32_t* alive = fb.alive + P0;
-        const int32_t* vert = fb.fd_vert + P0;
-        for (int32_t j = tid; j < n_i; j += NT) {
-            lc[j] = j;
-            sup[j] = init[vert[j]];
-            alive[j] = 1;
-        }
-        __syncthreads();
-        const bool multi = n_i > kFdBits;
-        int32_t n_live = n_i;
-        int64_t level = 0;
-        while (n_live > 0) {
-            int64_t mn = INT64_MAX;
-            for (int32_t j = tid; j < n_live; j += NT) {
-                const int64_t s = sup[lc[j]];
-                mn = s < mn ? s : mn;
+        if (n_i <= kFdLdsVerts) {
+            fd_peel_lds(J.g, fb, J.init, P0, n_i, L, S, tab, sp, wedges, pairs, levels, spills);
+        } else {
+            // a large subset opens a help-board slot for its per-wave updates
+            FdHelpSlot* hs = nullptr;
+            if (n_i >= kFdHelpMin) {
+                if (tid == 0) {
+                    const int32_t k = atomicAdd(&board->n_slots, 1);
+                    L.flag = k;
+                    if (k < kFdHelpSlots) {
+                        FdHelpSlot& h = board->slot[k];
+                        h.job = tasks ? (int32_t)(tasks[t] >> 32) : -1;
+                        h.n_i = n_i;
+                        h.P0 = P0;
+                        h.word = 0;
+                        h.done = 0;
+                        __threadfence();
+                        atomicExch(&h.state, 1);
+                    }
+                }
+                __syncthreads();
+                if (L.flag < kFdHelpSlots) hs = &board->slot[L.flag];
+                __syncthreads();
             }
-            mn = fd_min<NT>(L, mn);
-            level = mn > level ? mn : level;
-            // peel every live vertex at or below the level; light ones (few
-            // wedges inside the subset) and heavy ones go to separate lists,
-            // vertices without support left need no update at all
-            int32_t n_light = 0, n_heavy = 0, n_keep = 0;
-            for (int32_t b0 = 0; b0 < n_live; b0 += NT) {
-                const int32_t j = b0 + tid;
-                int32_t x = 0;
-                bool pe = false, ke = false, li = false, he = false;
-                if (j < n_live) {
-                    x = lc[j];
-                    const int64_t sx = sup[x];
-                    pe = sx <= level;
-                    ke = !pe;
-                    if (pe && sx > 0) {
-                        he = fw[x] > kFdWaveMax;
-                        li = !he;
-                    }
-                }
-                int32_t tl, th, tk;
-                const int32_t ol = fd_scan_i32<NT>(L, li ? 1 : 0, tl);
-                const int32_t oh = fd_scan_i32<NT>(L, he ? 1 : 0, th);
-                const int32_t ok = fd_scan_i32<NT>(L, ke ? 1 : 0, tk);
-                if (pe) {
-                    alive[x] = 0;
-                    fb.theta[vert[x]] = level;
-                }
-                if (li) pl[n_light + ol] = x;
-                if (he) ph[n_heavy + oh] = x;
-                if (ke) ln[n_keep + ok] = x;
-                n_light += tl;
-                n_heavy += th;
-                n_keep += tk;
-            }
-            __syncthreads();
-            levels += tid == 0;
-            // light peeled vertices: one per wave
-            for (int32_t q = wid; q < n_light; q += NW) {
-                const int32_t x = pl[q];
-                const uint32_t slots = min<uint32_t>(kFdWaveSlots, wave_slots(fw[x]));
-                const uint32_t mask = slots - 1;
-                const int32_t ux = vert[x];
-                const int64_t e0 = g.a_off[ux], d = g.a_off[ux + 1] - e0;
-                for (int64_t g0 = 0; g0 < d; g0 += kWave) {
-                    const int gs = (int)min<int64_t>(kWave, d - g0);
-                    int64_t len = 0;
-                    if (lane < gs) {
-                        const int64_t e = e0 + g0 + lane;
-                        L.wsbeg[wid][lane] = fb.fd_beg[e];
-                        len = fb.fd_len[e];
-                    }
-                    const int64_t inc = wave_incl_scan_i64<kWave>(len);
-                    L.wpre[wid][lane] = inc - len;
-                    const int64_t tot = __shfl(inc, kWave - 1, kWave);
-                    if (lane == 0) L.wpre[wid][kWave] = tot;
-                    wave_sync();
-                    int lo = 0;
-                    for (int64_t i = lane; i < tot; i += kWave) {
-                        while (lo + 1 < gs && L.wpre[wid][lo + 1] <= i) ++lo;
-                        const int32_t w = fb.pcsc[L.wsbeg[wid][lo] + (i - L.wpre[wid][lo])];
-                        if (w != x) fd_wave_insert(tab, (uint32_t)w, mask);
-                    }
-                    if (lane == 0) wedges += (unsigned long long)(tot - gs);
-                    wave_sync();
-                }
-                for (uint32_t s = lane; s < slots; s += kWave) {
-                    const unsigned long long v = tab[s];
-                    if (v) {
-                        tab[s] = 0;
-                        const int64_t c = (int64_t)(v & 0xffffffffull);
-                        const int32_t w = (int32_t)((v >> 32) - 1);
-                        if (c >= 2 && alive[w]) {
-                            atomic_add_i64(&sup[w], -choose2(c));
-                            ++pairs;
-                        }
-                    }
-                }
-                wave_sync();
-            }
-            __syncthreads();
-            // heavy peeled vertices: one at a time with the whole workgroup
-            for (int32_t q = 0; q < n_heavy; ++q) {
-                const int32_t x = ph[q];
-                const int32_t ux = vert[x];
-                const int64_t e0 = g.a_off[ux], d = g.a_off[ux + 1] - e0;
-                for (int32_t klo = 0; klo < n_i; klo += kFdBits) {
-                    const int32_t khi = (int32_t)min<int64_t>(n_i, (int64_t)klo + kFdBits);
-                    const bool self_in = x >= klo && x < khi;
-                    for (int64_t g0 = 0; g0 < d; g0 += kGroup) {
-                        const int gs = (int)min<int64_t>(kGroup, d - g0);
-                        int64_t len = 0;
-                        if (tid < gs) {
-                            const int64_t e = e0 + g0 + tid;
-                            int64_t a = fb.fd_beg[e], b = a + fb.fd_len[e];
-                            if (multi) {
-                                a = lower_bound_i32(fb.pcsc, a, b, klo);
-                                b = lower_bound_i32(fb.pcsc, a, b, khi);
-                            }
-                            L.sbeg[tid] = a;
-                            len = b - a;
-                        }
-                        int32_t tot32;
-                        // exclusive scan of run lengths into L.pre
-                        const int64_t x64 = tid < gs ? len : 0;
-                        const int64_t incl = wave_incl_scan_i64<NT>(x64);
-                        __syncthreads();
-                        if (lane == kWave - 1) L.red[wid] = incl;
-                        __syncthreads();
-                        int64_t off = 0, tot = 0;
-#pragma unroll
-                        for (int w = 0; w < NW; ++w) {
-                            const int64_t v = L.red[w];
-                            off += w < wid ? v : 0;
-                            tot += v;
-                        }
-                        if (tid < gs) L.pre[tid] = off + incl - x64;
-                        if (tid == 0) L.pre[gs] = tot;
-                        __syncthreads();
-                        (void)tot32;
-                        for (int64_t i = tid; i < tot; i += NT) {
-                            int lo = 0, hi = gs;
-                            while (hi - lo > 1) {
-                                const int mid = (lo + hi) >> 1;
-                                if (L.pre[mid] <= i) lo = mid;
-                                else hi = mid;
-                            }
-                            const int32_t w = fb.pcsc[L.sbeg[lo] + (i - L.pre[lo])];
-                            if (w != x) {
-                                const uint32_t k = (uint32_t)(w - klo);
-                                const uint32_t bit = 1u << (k & 31);
-                                if (atomicOr(&L.u.big.bm[k >> 5], bit) & bit) fd_rep_insert(L, sp, k);
-                            }
-                        }
-                        if (tid == 0) wedges += (unsigned long long)(tot - (self_in ? gs : 0));
-                        __syncthreads();
-                    }
-                    for (int s = tid; s < kFdRep; s += NT) {
-                        const unsigned long long v = L.u.big.rep[s];
-                        if (v) {
-                            const int32_t w = klo + (int32_t)((v >> 32) - 1);
-                            if (alive[w]) {
-                                atomic_add_i64(&sup[w], -choose2(1 + (int64_t)(v & 0xffffffffull)));
-                                ++pairs;
-                            }
-                        }
-                    }
-                    const int32_t nsp = L.spill_n;
-                    if (tid == 0) spills += (unsigned long long)nsp;
-                    for (int32_t i = tid; i < nsp; i += NT) {
-                        const int32_t k = sp.list[i];
-                        const int32_t w = klo + k;
-                        if (alive[w]) {
-                            atomic_add_i64(&sup[w], -choose2(1 + (int64_t)sp.dense[k]));
-                            ++pairs;
-                        }
-                        sp.dense[k] = 0;
-                    }
-                    __syncthreads();
-                    const int32_t words = (khi - klo + 31) >> 5;
-                    for (int w = tid; w < words; w += NT) L.u.big.bm[w] = 0;
-                    for (int s = tid; s < kFdRep; s += NT) L.u.big.rep[s] = 0;
-                    if (tid == 0) L.spill_n = 0;
-                    __syncthreads();
-                }
-            }
-            int32_t* tmp = lc;
-            lc = ln;
-            ln = tmp;
-            n_live = n_keep;
+            fd_peel_hbm(J.g, fb, J.init, P0, n_i, L, tab, sp, hs, wedges, pairs, levels, spills);
+            if (hs && tid == 0) atomicExch(&hs->state, 2);
         }
         wedges = (unsigned long long)wave_sum_i64((int64_t)wedges);
         pairs = (unsigned long long)wave_sum_i64((int64_t)pairs);
@@ -446,6 +793,50 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, int32
             if (levels) atomicAdd(&J.ctl->fd_levels, levels);
             if (spills) atomicAdd(&J.ctl->spills, spills);
         }
+    }
+    // No task left: help the large subsets still open until no slot is
+    // open.  The whole workgroup works on one slot at a time (its waves share
+    // the LDS counters, so they must use the same kind of update).  Owners
+    // never wait for helpers, only for entries already taken, so helping is
+    // optional and every wave ends.
+    for (;;) {
+        if (tid == 0) {
+            const int32_t n_open = min(__hip_atomic_load(&board->n_slots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                                       kFdHelpSlots);
+            int32_t pick = -1;  // -1: nothing open, -2: open but nothing to take now
+            for (int32_t k = 0; k < n_open && pick < 0; ++k) {
+                FdHelpSlot* hs = &board->slot[k];
+                if (__hip_atomic_load(&hs->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 1) continue;
+                pick = -2;
+                const unsigned long long wv = __hip_atomic_load(&hs->word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((uint32_t)wv < (uint32_t)(wv >> 32)) pick = k;
+            }
+            L.flag = pick;
+        }
+        __syncthreads();
+        const int32_t k = L.flag;
+        __syncthreads();
+        if (k == -1) break;
+        if (k >= 0) {
+            __threadfence();
+            FdHelpSlot* hs = &board->slot[k];
+            const FdJob& J = hs->job >= 0 ? jobs.list[hs->job] : jobs.one;
+            const FdBuffers& fb = J.fb;
+            const int64_t P0 = hs->P0;
+            const FdHbmState st{fb.supp_fd + P0, fb.alive + P0, fb.fd_vert + P0};
+            uint32_t* wcnt = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(&L.u) + (size_t)wid * kFdWaveKeys);
+            unsigned long long wedges = 0, pairs = 0;
+            fd_help_slot(J.g, fb, L, tab, wcnt, fb.lst[2] + P0, fb.fd_w + P0, hs->n_i, hs, st, wedges, pairs);
+            wedges = (unsigned long long)wave_sum_i64((int64_t)wedges);
+            pairs = (unsigned long long)wave_sum_i64((int64_t)pairs);
+            if (lane == 0) {
+                if (wedges) atomicAdd(&J.ctl->wedges_fd, wedges);
+                if (pairs) atomicAdd(&J.ctl->pair_updates, pairs);
+            }
+        } else {
+            __builtin_amdgcn_s_sleep(64);
+        }
+        __syncthreads();
     }
 }
 
@@ -496,23 +887,26 @@ void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl
                uint64_t* keys_scratch, int32_t* vals_scratch, hipStream_t s) {
     if (g.n_a <= 0) return;
     launch_fd_setup(g, pb, fb, S, tmp_keys, tmp_vals, hist, scan_tmp, keys_scratch, vals_scratch, s);
-    k_fd_reset_head<<<1, 1, 0, s>>>(ctl);
+    k_fd_reset_board<<<1, 256, 0, s>>>(fb.board);
     TIP_HIP_TRY(hipGetLastError());
     FdJobs jobs{};
     jobs.one = FdJob{g, fb, pb.init, ctl};
-    const int grid = std::max(1, std::min<int>(S, big_grid));
-    k_fd_peel<<<grid, kFdThreads, 0, s>>>(jobs, nullptr, S, &ctl->fd_head, spill);
+    // every resident workgroup: those without a task of their own help
+    // with the large subsets
+    const int grid = std::max(1, big_grid);
+    k_fd_peel<<<grid, kFdThreads, 0, s>>>(jobs, nullptr, S, fb.board, spill);
     TIP_HIP_TRY(hipGetLastError());
 }
 
-void launch_fd_batch(const FdJob* d_jobs, const int64_t* d_tasks, int32_t n_tasks, int32_t* d_head,
+void launch_fd_batch(const FdJob* d_jobs, const int64_t* d_tasks, int32_t n_tasks, FdBoard* d_board,
                      const SpillArena& spill, int big_grid, hipStream_t s) {
     if (n_tasks <= 0) return;
-    fill_i32(d_head, 0, 1, s);
+    k_fd_reset_board<<<1, 256, 0, s>>>(d_board);
+    TIP_HIP_TRY(hipGetLastError());
     FdJobs jobs{};
     jobs.list = d_jobs;
-    const int grid = std::max(1, std::min<int>(n_tasks, big_grid));
-    k_fd_peel<<<grid, kFdThreads, 0, s>>>(jobs, d_tasks, n_tasks, d_head, spill);
+    const int grid = std::max(1, big_grid);
+    k_fd_peel<<<grid, kFdThreads, 0, s>>>(jobs, d_tasks, n_tasks, d_board, spill);
     TIP_HIP_TRY(hipGetLastError());
 }
 

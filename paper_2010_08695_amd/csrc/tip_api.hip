@@ -103,6 +103,7 @@ void plan(Arena& ar, int32_t n_a, int32_t n_b, int64_t m, int32_t P, int slots, 
     w.fb.alive = ar.take<int32_t>(na);
     for (int i = 0; i < 4; ++i) w.fb.lst[i] = ar.take<int32_t>(na);
     w.fb.theta = ar.take<int64_t>(na);
+    w.fb.board = ar.take<FdBoard>(1);
     w.ctl = ar.take<Ctl>(1);
     w.total = ar.take<int64_t>(2);
     w.ovf = ar.take<double>(8);
@@ -749,13 +750,13 @@ tip_status decompose_batched(int32_t n, const tip_edges* gs, const int32_t* side
     DeviceBuffer fdbuf;
     if (!tasks.empty()) {
         // five sub-allocations, each aligned by the arena
-        const size_t bytes = sizeof(FdJob) * jobs.size() + sizeof(int64_t) * tasks.size() + sizeof(int32_t) +
+        const size_t bytes = sizeof(FdJob) * jobs.size() + sizeof(int64_t) * tasks.size() + sizeof(FdBoard) +
                              2 * sizeof(int32_t) * (size_t)stride * slots + 4096;
         fdbuf.alloc(bytes);
         Arena ar{static_cast<char*>(fdbuf.p), bytes, 0};
         FdJob* d_jobs = ar.take<FdJob>(jobs.size());
         int64_t* d_tasks = ar.take<int64_t>(tasks.size());
-        int32_t* d_head = ar.take<int32_t>(1);
+        FdBoard* d_board = ar.take<FdBoard>(1);
         SpillArena spill;
         spill.stride = stride;
         spill.slots = slots;
@@ -766,7 +767,7 @@ tip_status decompose_batched(int32_t n, const tip_edges* gs, const int32_t* side
         TIP_HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(FdJob) * jobs.size(), hipMemcpyHostToDevice, s));
         TIP_HIP_TRY(hipMemcpyAsync(d_tasks, tv.data(), sizeof(int64_t) * tv.size(), hipMemcpyHostToDevice, s));
         TIP_HIP_TRY(hipMemsetAsync(spill.dense, 0, sizeof(int32_t) * stride * slots, s));
-        launch_fd_batch(d_jobs, d_tasks, (int32_t)tasks.size(), d_head, spill, slots, s);
+        launch_fd_batch(d_jobs, d_tasks, (int32_t)tasks.size(), d_board, spill, slots, s);
     }
     for (int32_t k = 0; k < n; ++k) TIP_HIP_TRY(hipEventRecord(items[k]->rs.ev.e[4], s));
     for (int32_t k = 0; k < n; ++k) {

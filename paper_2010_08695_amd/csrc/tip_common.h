@@ -80,6 +80,12 @@ constexpr int kFdBits = 1 << 19;           // keys per bitmap tile for heavy pee
 constexpr int kFdRep = 2048;               // repeat slots of that path
 constexpr int kFdWaveSlots = 512;          // per-wave hash slots for light peeled vertices
 constexpr int64_t kFdWaveMax = 224;        // light: at most this many wedges inside the subset
+constexpr int kFdLdsVerts = 2560;         // subsets up to this size keep their peeling state in LDS
+constexpr int kFdWaveKeys = 10240;        // subsets up to this size: per-wave 8-bit counters per vertex
+constexpr int64_t kFdWaveDenseMax = 1024;  // ... for peeled vertices with at most this many wedges
+constexpr int kFdHelpMin = 4096;          // subsets from this size let idle workgroups take their per-wave updates
+constexpr int kFdHelpChunk = 16;          // per-wave updates taken at once from a help-board slot
+constexpr int kFdHelpLevelMin = 256;      // levels with fewer per-wave updates are not published
 
 constexpr int32_t kLive = -1;              // subset id of a vertex not yet assigned
 

@@ -21,7 +21,7 @@ struct Ctl {
     int32_t n_front[kBins]; // current frontier sizes per update kernel
     int32_t n_next[kBins];  // next frontier sizes
     int32_t n_items[2];     // counting work items [wave bin, workgroup bin]
-    int32_t fd_head;        // fine-grained task queue head
+    int32_t pad0;
     int32_t sel_found;      // 0 once no support value reaches the target
     int32_t pad[4];
     unsigned long long max_supp;
@@ -107,6 +107,25 @@ struct CompactScratch {
     int32_t* row;        // [m]
 };
 
+// Help board of one fine-grained launch.  A workgroup peeling a large subset
+// opens a slot and publishes, level by level, its list of per-wave updates;
+// workgroups whose task queue has run dry take entries from open slots.  All
+// zero before the launch.
+struct FdHelpSlot {
+    unsigned long long word;  // (published entries << 32) | next entry to take
+    int32_t done;             // entries of the published level finished
+    int32_t state;            // 0 unused, 1 open, 2 closed
+    int32_t job;              // index in the job list, -1 for the single job
+    int32_t n_i;              // subset size
+    int64_t P0;               // subset start (position)
+};
+constexpr int kFdHelpSlots = 64;
+struct FdBoard {
+    int32_t head;     // task queue head
+    int32_t n_slots;  // slots handed out
+    FdHelpSlot slot[kFdHelpSlots];
+};
+
 struct FdBuffers {
     int32_t* fd_vert;    // [n_a] vertices grouped by subset, ascending rank inside
     int32_t* fd_pos;     // [n_a]
@@ -123,6 +142,7 @@ struct FdBuffers {
     int32_t* alive;      // [n_a] by subset position
     int32_t* lst[4];     // [n_a] live / next-live / light-peel / heavy-peel lists by subset position
     int64_t* theta;      // [n_a] by rank
+    FdBoard* board;      // task queue and help board of the launch
 };
 
 // Update-kernel selection thresholds (tip_opts.tune[0], tune[1]).
@@ -186,7 +206,7 @@ void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t 
 // Persistent peeling of the subsets of many graphs in one launch: tasks[t] =
 // job << 32 | subset, in the order they are to be taken; *head is the queue
 // head (reset here).
-void launch_fd_batch(const FdJob* d_jobs, const int64_t* d_tasks, int32_t n_tasks, int32_t* d_head,
+void launch_fd_batch(const FdJob* d_jobs, const int64_t* d_tasks, int32_t n_tasks, FdBoard* d_board,
                      const SpillArena& spill, int big_grid, hipStream_t s);
 void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl, const SpillArena& spill,
                int big_grid, uint64_t* tmp_keys, int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp,
