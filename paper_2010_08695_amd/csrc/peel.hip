@@ -673,14 +673,20 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
     uint4* cnt4 = reinterpret_cast<uint4*>(cnt);
     const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
     if (tid == 0 && t_begin == 0) pc.edges += (unsigned long long)d;
-    // with at most NT neighbours, their ids and list offsets stay in
-    // registers for all passes; only the tile bounds are read per pass
+    // with at most NT neighbours, their list offsets and the tile bounds of
+    // every pass of the item (at most kDensePasses + 1) are loaded once and
+    // stay in registers; bnd[0] and bnd[1] bound the current pass
     const bool one = d <= NT;
-    int32_t v1 = 0;
     int64_t bo1 = 0;
+    int32_t bnd[kDensePasses + 1];
+#pragma unroll
+    for (int k = 0; k <= kDensePasses; ++k) bnd[k] = 0;
     if (one && tid < d) {
-        v1 = g.a_adj[e0 + tid];
+        const int32_t v1 = g.a_adj[e0 + tid];
         bo1 = g.b_off[v1];
+        const int32_t* row = tb + (int64_t)v1 * (ntt + 1);
+#pragma unroll
+        for (int k = 0; k <= kDensePasses; ++k) bnd[k] = row[min(t_end, t_begin + k * gpass)];
     }
     // one pass per gpass tiles: count in LDS, then apply and clear
     for (int32_t p0 = t_begin; p0 < t_end; p0 += gpass) {
@@ -691,12 +697,16 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
             int64_t s0 = 0;
             int32_t len = 0;
             if (tid < gs) {
-                const int32_t v = one ? v1 : g.a_adj[e0 + g0 + tid];
-                const int64_t bo = one ? bo1 : g.b_off[v];
-                const int32_t* row = tb + (int64_t)v * (ntt + 1);
-                const int32_t a = row[p0];
-                s0 = bo + a;
-                len = row[p1] - a;
+                if (one) {
+                    s0 = bo1 + bnd[0];
+                    len = bnd[1] - bnd[0];
+                } else {
+                    const int32_t v = g.a_adj[e0 + g0 + tid];
+                    const int32_t* row = tb + (int64_t)v * (ntt + 1);
+                    const int32_t a = row[p0];
+                    s0 = g.b_off[v] + a;
+                    len = row[p1] - a;
+                }
             }
             const int32_t nu = stage_units(S, gs, s0, len);
             unsigned long long wl = 0;
@@ -769,6 +779,8 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
             cnt4[w4] = make_uint4(0, 0, 0, 0);
         }
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kDensePasses; ++k) bnd[k] = bnd[k + 1];
     }
 }
 
