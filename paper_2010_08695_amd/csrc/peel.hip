@@ -197,10 +197,12 @@ __global__ void k_tile_bounds(const int64_t* __restrict__ b_off, const int32_t* 
 
 __global__ void k_ctl_begin_range(Ctl* ctl) {
     ctl->n_live_next = 0;
-    ctl->max_supp = 0;
-    ctl->w_rem = 0;
     ctl->w_range = 0;
-    for (int i = 0; i < kSpread; ++i) ctl->spread[i][kScWRange] = 0;
+    for (int i = 0; i < kSpread; ++i) {
+        ctl->spread[i][kScWRange] = 0;
+        ctl->spread[i][kScWRem] = 0;
+        ctl->spread_max[i] = 0;
+    }
     for (int b = 0; b < kBins; ++b) ctl->n_front[b] = ctl->n_next[b] = ctl->head[b] = 0;
 }
 
@@ -249,8 +251,8 @@ __global__ void k_range_start(const int32_t* __restrict__ live_in, int32_t n_in,
             m2 = smx[w] > m2 ? smx[w] : m2;
             w2 += sws[w];
         }
-        if (m2) atomicMax(&ctl->max_supp, m2);
-        if (w2) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->w_rem), (unsigned long long)w2);
+        if (m2) atomicMax(&ctl->spread_max[blockIdx.x & (kSpread - 1)], m2);
+        if (w2) spread_add(ctl, kScWRem, (unsigned long long)w2);
     }
 }
 
@@ -272,11 +274,33 @@ __global__ void k_select_hist(const int32_t* __restrict__ live, int32_t n_live, 
     __syncthreads();
     const uint64_t prefix = ctl->sel_prefix;
     const int hs = shift + 8;
-    GRID_STRIDE(j, (int64_t)n_live) {
-        const int32_t u = live[j];
-        const uint64_t key = (uint64_t)supp[u];
-        if (hs >= 64 || (key >> hs) == (prefix >> hs))
-            atomicAdd(&h[(key >> shift) & 255], (unsigned long long)wprox[u]);
+    const int lane = threadIdx.x & (kWave - 1);
+    // the supports of a range cluster, so a wave's keys often share the
+    // digit: then one LDS atomic adds the wave's sum
+    UNIFORM_STRIDE(base, (int64_t)n_live) {
+        const int64_t j = base + threadIdx.x;
+        bool ok = false;
+        uint32_t dg = 0;
+        unsigned long long w = 0;
+        if (j < n_live) {
+            const int32_t u = live[j];
+            const uint64_t key = (uint64_t)supp[u];
+            if (hs >= 64 || (key >> hs) == (prefix >> hs)) {
+                ok = true;
+                dg = (uint32_t)((key >> shift) & 255);
+                w = (unsigned long long)wprox[u];
+            }
+        }
+        const uint64_t act = __ballot(ok);
+        if (act == 0) continue;
+        const int first = __ffsll((unsigned long long)act) - 1;
+        const uint32_t d0 = (uint32_t)__shfl((int)dg, first, kWave);
+        if (__ballot(ok && dg != d0) == 0) {
+            const unsigned long long tot = (unsigned long long)wave_sum_i64((int64_t)(ok ? w : 0));
+            if (lane == first) atomicAdd(&h[d0], tot);
+        } else if (ok) {
+            atomicAdd(&h[dg], w);
+        }
     }
     __syncthreads();
     if (h[threadIdx.x]) atomicAdd(reinterpret_cast<unsigned long long*>(&hist[threadIdx.x]), h[threadIdx.x]);

@@ -351,8 +351,9 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
             if (tune.compact_permille > 0 && dead > 0 &&
                 (double)dead * 1000.0 >= (double)c0.cd_m * (double)tune.compact_permille)
                 launch_compact(g, pb, cscr, c0.cd_m, tune, w.ctl, s);
-            const uint64_t max_supp = c0.max_supp;
-            const long long w_rem = c0.w_rem;
+            uint64_t max_supp = 0;
+            for (int i = 0; i < kSpread; ++i) max_supp = std::max<uint64_t>(max_supp, c0.spread_max[i]);
+            const long long w_rem = (long long)spread_sum(c0, kScWRem);
             // adaptive target: remaining wedges over remaining subsets,
             // scaled by how far the previous subset overshot its target
             double tgt_d = std::ceil(scale * (double)w_rem / (double)(P - label));

@@ -11,7 +11,7 @@ namespace tip {
 constexpr int kSpread = 64;
 enum SpreadCounter {
     kScWedgesCd = 0, kScPairs, kScSkipped, kScSpills, kScBigWedges, kScBigPairs, kScBigEdges, kScWRange,
-    kScDeadEdges, kScCount
+    kScDeadEdges, kScWRem, kScCount
 };
 
 // Device-resident control block of one decomposition.
@@ -24,8 +24,6 @@ struct Ctl {
     int32_t pad0;
     int32_t sel_found;      // 0 once no support value reaches the target
     int32_t pad[4];
-    unsigned long long max_supp;
-    long long w_rem;        // wedge proxy summed over live vertices
     long long w_range;      // wedge proxy summed over the current subset
     unsigned long long sel_prefix;
     long long sel_cum;
@@ -47,6 +45,7 @@ struct Ctl {
     int32_t key_hi;                  // every live vertex of side A has a rank below this
     int32_t pad2;
     unsigned long long spread[kSpread][kScCount];
+    unsigned long long spread_max[kSpread];  // largest live support at a range start, per workgroup group
     // Range state read by the round kernels, so that a sequence of rounds
     // can be launched (or replayed from a graph) without host arguments.
     long long range_hi;      // upper bound of the current range
