@@ -744,11 +744,12 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
             pc.wedges += wl;
             __syncthreads();
         }
-        // keys with c >= 2: each wave stages its pairs in key order in the 64
-        // counter quads it has just read (256 packed (key offset, c) words per
-        // round) and applies them from consecutive lanes, so that an atomic
-        // instruction touches few 128-byte lines of supports; then it clears
-        // the quads.  n4 is a multiple of NT (tk is a multiple of 16K keys).
+        // keys with c >= 2 are applied in key order from consecutive lanes, so
+        // that an atomic instruction touches few 128-byte lines of supports:
+        // with at most one pair per lane through one cross-lane permute, else
+        // staged in the 64 counter quads the wave has just read (256 packed
+        // (key offset, c) words per round); then the quads are cleared.  n4
+        // is a multiple of NT (tk is a multiple of 16K keys).
         const int32_t n4 = (int32_t)((int64_t)(p1 - p0) * tk / PER_WORD / 4);
         for (int32_t base = 0; base < n4; base += NT) {
             const int32_t w4 = base + tid;
@@ -757,7 +758,34 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
             uint32_t msk[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) msk[q] = ge2_mask<BITS>(xs[q]);
-            if (__ballot((msk[0] | msk[1] | msk[2] | msk[3]) != 0)) {
+            const int32_t mine0 = __popc(msk[0]) + __popc(msk[1]) + __popc(msk[2]) + __popc(msk[3]);
+            const uint64_t has = __ballot(mine0 > 0);
+            if (has != 0 && __ballot(mine0 > 1) == 0) {
+                // at most one pair per lane (the common case): one permute
+                // moves the pairs, in key order, to the first lanes
+                int32_t key = 0;
+                uint32_t c = 0;
+                if (mine0 == 1) {
+                    const int q = msk[0] ? 0 : msk[1] ? 1 : msk[2] ? 2 : 3;
+                    const uint32_t m = q == 0 ? msk[0] : q == 1 ? msk[1] : q == 2 ? msk[2] : msk[3];
+                    const uint32_t xq = q == 0 ? xs[0] : q == 1 ? xs[1] : q == 2 ? xs[2] : xs[3];
+                    const int f = (__ffs(m) - 1) / BITS;
+                    key = klo + w4 * 4 * PER_WORD + q * PER_WORD + f;
+                    c = (xq >> (f * BITS)) & FMASK;
+                }
+                // lanes with a pair go to their rank among them, the others
+                // to the lanes after those: a permutation of the wave
+                const int32_t n_has = __popcll(has);
+                const uint64_t lt = lanemask_lt();
+                const int dst = mine0 == 1 ? __popcll(has & lt) : n_has + __popcll(~has & lt);
+                const int32_t k2 = __builtin_amdgcn_ds_permute(dst << 2, key);
+                const int32_t c2v = __builtin_amdgcn_ds_permute(dst << 2, (int32_t)c);
+                if (lane < n_has && ap.state[k2] == kLive) {
+                    atomic_add_i64(&ap.supp[k2], -choose2(c2v));
+                    ++pc.pairs;
+                }
+            } else if (has != 0) {
+                // denser: stage the pairs through the quad window
                 uint32_t* win = reinterpret_cast<uint32_t*>(cnt4 + (w4 - lane));
                 const int32_t kwin = klo + (w4 - lane) * 4 * PER_WORD;
                 const uint32_t koff = (uint32_t)lane * 4 * PER_WORD;
