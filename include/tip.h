@@ -103,7 +103,9 @@ typedef struct {
     int64_t wedges_count; /* wedges traversed by per-vertex counting (Alg. 1) */
     int64_t wedges_cd;    /* wedges traversed by coarse-grained peeling (Alg. 3) */
     int64_t wedges_fd;    /* wedges traversed by fine-grained peeling (Alg. 4) */
-    int64_t pair_updates; /* support decrements applied (distinct peeled/live pairs) */
+    int64_t pair_updates; /* support decrements issued: (peeled, other) pairs with c >= 2; a pair
+                             whose other vertex is already peeled may be counted, its support is
+                             never read again */
     int64_t rounds;       /* coarse-grained peeling iterations (synchronisation rounds) */
     int64_t subsets;      /* vertex subsets created (P, plus 1 if vertices were left over) */
     int64_t fd_levels;    /* peeling levels run by the fine-grained step */

@@ -437,22 +437,24 @@ struct PairBuf {
     }
 };
 
-// Applies the decrement C(c, 2) of (peeled u, w) pairs to the live w.
+// Applies the decrement C(c, 2) of (peeled u, w) pairs.  It goes to every w,
+// live or not: the support of a vertex that is no longer live is never read
+// again (rounds and range starts read live vertices only, and the fine-grained
+// step starts from the range's snapshot), so no liveness load has to come
+// before the atomic.  Decrements of vertices peeled in the same round can
+// bring their support to 0, which is why zero-support vertices are left out
+// by the frontier scan only (at that point no decrement of the round has
+// happened) and not again by the update kernels.
 struct CdApply {
     int64_t* supp;
-    const int32_t* state;
 
-    // Applies and empties the lane's buffered pairs (all with c >= 2).  The
-    // state loads of the whole batch are issued together; the decrements do
-    // not return a value, so nothing waits on them.
+    // Applies and empties the lane's buffered pairs (all with c >= 2); the
+    // decrements do not return a value, so nothing waits on them.
     template <int B>
     __device__ inline void flush(PairBuf<B>& pb, unsigned long long& pairs) const {
-        int32_t st[B];
-#pragma unroll
-        for (int i = 0; i < B; ++i) st[i] = i < pb.n ? state[pb.key[i]] : 0;
 #pragma unroll
         for (int i = 0; i < B; ++i)
-            if (i < pb.n && st[i] == kLive) {
+            if (i < pb.n) {
                 atomic_add_i64(&supp[pb.key[i]], -choose2(pb.cnt[i]));
                 ++pairs;
             }
@@ -499,10 +501,6 @@ k_peel_wave(DevGraph g, FrontSet fs, const int64_t* __restrict__ wprox, CdApply 
     PeelCounters pc;
     for (int64_t it = (int64_t)blockIdx.x * nw + wid; it < n_front; it += (int64_t)gridDim.x * nw) {
         const int32_t u = front[it];
-        if (ap.supp[u] == 0) {
-            pc.skipped += lane == 0;
-            continue;
-        }
         const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
         const uint32_t slots = wave_slots(wprox[u]);
         for (int64_t g0 = 0; g0 < d; g0 += kWave) {
@@ -596,12 +594,7 @@ k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t nt
         const int64_t it = next_item(L.st, &ctl->head[kBinBitmap]);
         if (it >= n_front) break;
         const int32_t u = front[it];
-        const int64_t su = ap.supp[u];
         const int64_t e0 = g.a_off[u], d = g.a_off[u + 1] - e0;
-        if (su == 0) {
-            pc.skipped += tid == 0;
-            continue;
-        }
         if (tid == 0) pc.edges += (unsigned long long)d;
         for (int32_t klo = 0; klo < key_hi; klo += kBmTile) {
             const int32_t khi = (int32_t)min<int64_t>(key_hi, (int64_t)klo + kBmTile);
@@ -780,7 +773,7 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
                 const int dst = mine0 == 1 ? __popcll(has & lt) : n_has + __popcll(~has & lt);
                 const int32_t k2 = __builtin_amdgcn_ds_permute(dst << 2, key);
                 const int32_t c2v = __builtin_amdgcn_ds_permute(dst << 2, (int32_t)c);
-                if (lane < n_has && ap.state[k2] == kLive) {
+                if (lane < n_has) {
                     atomic_add_i64(&ap.supp[k2], -choose2(c2v));
                     ++pc.pairs;
                 }
@@ -807,24 +800,15 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
                     }
                     wave_sync();
                     const int32_t n_st = min(total, kStageWords);
-                    int32_t key[kStageWords / kWave], c2[kStageWords / kWave], st[kStageWords / kWave];
 #pragma unroll
                     for (int i = 0; i < kStageWords / kWave; ++i) {
                         const int32_t j = lane + i * kWave;
-                        st[i] = 0;
                         if (j < n_st) {
                             const uint32_t e = win[j];
-                            key[i] = kwin + (int32_t)(e >> 16);
-                            c2[i] = (int32_t)(e & 0xffffu);
-                            st[i] = ap.state[key[i]];
-                        }
-                    }
-#pragma unroll
-                    for (int i = 0; i < kStageWords / kWave; ++i)
-                        if (st[i] == kLive) {
-                            atomic_add_i64(&ap.supp[key[i]], -choose2(c2[i]));
+                            atomic_add_i64(&ap.supp[kwin + (int32_t)(e >> 16)], -choose2((int32_t)(e & 0xffffu)));
                             ++pc.pairs;
                         }
+                    }
                     wave_sync();  // the window is read before the next round rewrites it
                 }
             }
@@ -924,10 +908,6 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
             gpass = pl.gl[o];
             t_begin = (int32_t)(q % pl.ngl[o]) * gpass * pl.np[o];
             t_end = min(ntk, t_begin + gpass * pl.np[o]);
-        }
-        if (ap.supp[u] == 0) {
-            pc.skipped += (tid == 0 && t_begin == 0);
-            continue;
         }
         switch (k) {
             case 3: dense_item<16>(g, tb, tk, ntt, u, t_begin, t_end, gpass, cnt, S, ap, pc); break;
@@ -1218,7 +1198,7 @@ int bitmap_grid() {
 
 void launch_round(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena& spill, int big_grid,
                   hipStream_t s, hipEvent_t* ev_big, const int32_t* n_cur) {
-    const CdApply ap{pb.supp, pb.state};
+    const CdApply ap{pb.supp};
     const FrontSet fs = front_set(pb);
     if (g.n_a <= 0) return;
     // the update traverses the CD copy of the lists N_v

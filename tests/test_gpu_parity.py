@@ -214,7 +214,8 @@ def test_list_compaction_changes_nothing_but_work(gpu_lib, permille):
     _, s0 = tip.decompose(g, 0, with_stats=True, flags=tip.TIP_FLAG_NO_COMPACT)
     _, s1 = tip.decompose(g, 0, with_stats=True, tune=tune)
     assert s1["wedges_cd"] < s0["wedges_cd"]
-    assert s1["pair_updates"] == s0["pair_updates"] and s1["rounds"] == s0["rounds"]
+    # decrements of peeled vertices drop with their list entries
+    assert s1["pair_updates"] <= s0["pair_updates"] and s1["rounds"] == s0["rounds"]
     for side in (0, 1):
         np.testing.assert_array_equal(tip.decompose(g, side, tune=tune, flags=tip.TIP_FLAG_NO_GRAPH),
                                       oracle.bup(g, side)[0])
