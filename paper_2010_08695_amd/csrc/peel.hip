@@ -847,12 +847,12 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
     for (int o = 0; o < kDenseKinds; ++o) {
         const int k = kDenseOrder[o];
         const int32_t n_l = ctl->n_front[dense_bin_of_kind(k, false)], n_h = ctl->n_front[dense_bin_of_kind(k, true)];
-        // light items span gl tiles, heavy ones gh = gl / kHeavySplit; gl is
-        // narrowed while this width would have fewer than about four items
-        // per resident workgroup
-        // a light item makes np passes of gl tiles; np shrinks first, then
-        // gl, while the round would have too few items to keep every
-        // resident workgroup busy
+        // light items span gl tiles, heavy ones gh = gl / kHeavySplit; a
+        // light item makes np passes of gl tiles.  np shrinks first (to
+        // about two items per resident workgroup), then gl (to about one):
+        // every item pays its staging, scans and barriers and one atomic on
+        // the shared item counter, so small rounds gain from fewer, larger
+        // items
         const auto n_items_of = [&](int32_t l, int32_t np) {
             const int32_t h = max(1, l / kHeavySplit);
             const int64_t span = (int64_t)l * np;
@@ -860,8 +860,8 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
         };
         int32_t gl = (int32_t)min<int64_t>(g_max.k[k], ntk);
         int32_t np = kDensePasses;
-        while (np > 1 && n_items_of(gl, np) < 8 * slots) np >>= 1;
-        while (np == 1 && gl > 1 && n_items_of(gl, 1) < 4 * slots) gl = (gl + 1) / 2;
+        while (np > 1 && n_items_of(gl, np) < 2 * slots) np >>= 1;
+        while (np == 1 && gl > 1 && n_items_of(gl, 1) < slots) gl = (gl + 1) / 2;
         const int32_t gh = max(1, gl / kHeavySplit);
         const int32_t ngl = (int32_t)((ntk + (int64_t)gl * np - 1) / ((int64_t)gl * np));
         const int32_t ngh = (ntk + gh - 1) / gh;
