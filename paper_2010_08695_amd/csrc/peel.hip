@@ -206,6 +206,46 @@ __global__ void k_ctl_begin_range(Ctl* ctl) {
     for (int b = 0; b < kBins; ++b) ctl->n_front[b] = ctl->n_next[b] = ctl->head[b] = 0;
 }
 
+// Workgroup size of the scans over a live list.
+constexpr int kScanThreads = 512;
+
+// Appends val, for every thread with pred, to list b (b < NB) with one
+// atomic per list per workgroup: the appends of a scan go to a handful of
+// counters, and one address takes only about 1e8 atomics per second.  All
+// threads of the workgroup must call.
+template <int NB>
+__device__ inline void block_append(bool pred, int32_t val, int b, int32_t* const* lists, int32_t* counts) {
+    constexpr int NW = kScanThreads / kWave;
+    __shared__ int32_t s_off[NB][NW];
+    __shared__ int32_t s_base[NB];
+    if (!__syncthreads_or(pred)) return;  // one barrier when nothing is appended
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    uint64_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const uint64_t m = __ballot(pred && b == k);
+        if (lane == 0) s_off[k][wid] = __popcll(m);
+        if (pred && b == k) mine = m;
+    }
+    __syncthreads();
+    if (tid < NB) {
+        int32_t tot = 0;
+        for (int w = 0; w < NW; ++w) {
+            const int32_t c = s_off[tid][w];
+            s_off[tid][w] = tot;
+            tot += c;
+        }
+        s_base[tid] = tot ? atomicAdd(&counts[tid], tot) : 0;
+    }
+    __syncthreads();
+    if (pred) lists[b][s_base[b] + s_off[b][wid] + __popcll(mine & lanemask_lt())] = val;
+    __syncthreads();
+}
+
+inline unsigned scan_grid(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, (n + kScanThreads - 1) / kScanThreads));
+}
+
 // Compacts the live list, snapshots the supports of the live vertices
 // (Alg. 3 support init) and reduces the maximum support and the wedge proxy
 // of the remaining vertices.
@@ -228,10 +268,10 @@ __global__ void k_range_start(const int32_t* __restrict__ live_in, int32_t n_in,
             mx = max(mx, (unsigned long long)su);
             ws += wprox[u];
         }
-        wave_append(keep, u, live_out, &ctl->n_live_next);
+        block_append<1>(keep, u, 0, &live_out, &ctl->n_live_next);
     }
-    __shared__ unsigned long long smx[kT / kWave];
-    __shared__ long long sws[kT / kWave];
+    __shared__ unsigned long long smx[kScanThreads / kWave];
+    __shared__ long long sws[kScanThreads / kWave];
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) {
         const unsigned long long o = __shfl_xor(mx, d, kWave);
@@ -247,7 +287,7 @@ __global__ void k_range_start(const int32_t* __restrict__ live_in, int32_t n_in,
     if (threadIdx.x == 0) {
         unsigned long long m2 = 0;
         long long w2 = 0;
-        for (int w = 0; w < kT / kWave; ++w) {
+        for (int w = 0; w < kScanThreads / kWave; ++w) {
             m2 = smx[w] > m2 ? smx[w] : m2;
             w2 += sws[w];
         }
@@ -342,6 +382,8 @@ struct FrontSet {
 };
 
 // Appends u to the frontier list of its bin; all lanes of the wave must call.
+// (Appends are sparse after a range's first round; per-workgroup batching
+// measured slower here than in the range start.)
 __device__ inline void append_binned(bool pred, int32_t u, uint8_t b, const Fronts& f) {
 #pragma unroll
     for (int k = 0; k < kBins; ++k) wave_append(pred && b == k, u, f.list[k], &f.count[k]);
@@ -1157,7 +1199,7 @@ void launch_range_start(PeelBuffers& pb, int cur_live, int32_t n_live, Ctl* ctl,
     k_ctl_begin_range<<<1, 1, 0, s>>>(ctl);
     TIP_HIP_TRY(hipGetLastError());
     if (n_live <= 0) return;
-    k_range_start<<<grid1(n_live, 4096), kT, 0, s>>>(pb.live[cur_live], n_live, pb.live[1 - cur_live], pb.state,
+    k_range_start<<<scan_grid(n_live), kScanThreads, 0, s>>>(pb.live[cur_live], n_live, pb.live[1 - cur_live], pb.state,
                                                       pb.supp, pb.init, pb.wprox, ctl);
     TIP_HIP_TRY(hipGetLastError());
 }
