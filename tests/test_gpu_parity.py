@@ -306,3 +306,20 @@ def test_full_size_against_golden(gpu_lib, name):
         np.testing.assert_array_equal(th[s["index"]], s["value"])
         assert int(th.max()) == rec[key]["max"] and int(th.sum()) == rec[key]["sum"]
         assert digest(th) == rec[key]["sha256"]
+
+
+def test_batch_with_large_subsets_against_golden(gpu_lib):
+    """A batch holding graphs whose first subsets are large enough for the
+    fine-grained help board (4,096+ vertices): the single fine-grained launch
+    then publishes levels of jobs taken from the job list.  Results equal the
+    stored golden ones and the oracle."""
+    rec = _golden("cl-1m")
+    big = gg.config_graph("cl-1m")
+    small = gg.chung_lu(2000, 500, 15000, 2.2, 2.1, seed=71)
+    ex = tip.decompose_ex(big, 0)
+    sizes = np.bincount(ex["subset"], minlength=ex["n_subsets"])
+    assert sizes.max() >= 4096
+    out = tip.decompose_batch([small, big, big], [0, 0, 1])
+    np.testing.assert_array_equal(out[0], oracle.bup(small, 0)[0])
+    assert digest(out[1]) == rec["theta_u"]["sha256"]
+    assert digest(out[2]) == rec["theta_v"]["sha256"]
