@@ -784,7 +784,9 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
         // with at most one pair per lane through one cross-lane permute, else
         // staged in the 64 counter quads the wave has just read (256 packed
         // (key offset, c) words per round); then the quads are cleared.  n4
-        // is a multiple of NT (tk is a multiple of 16K keys).
+        // is a multiple of 256 (tk is a multiple of 16K keys); with n4 < NT
+        // the threads past n4 read quads outside this pass, inside the
+        // counter array and zero, so their waves stage nothing.
         const int32_t n4 = (int32_t)((int64_t)(p1 - p0) * tk / PER_WORD / 4);
         for (int32_t base = 0; base < n4; base += NT) {
             const int32_t w4 = base + tid;

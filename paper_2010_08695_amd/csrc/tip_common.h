@@ -31,8 +31,8 @@ constexpr int kBmTile = 1 << 19;           // keys per bitmap-path tile (64 KiB 
 constexpr int kBmRep = 8192;               // bitmap-path repeat slots (64 KiB)
 constexpr int kBmRuns = 1024;              // neighbour runs staged per pass by the bitmap path
 constexpr int kUnit = 128;                 // consecutive list entries per traversal unit
-constexpr int kDenseThreads = 256;         // threads of the dense (vertex, key range) kernel
-constexpr int kDenseLdsBytes = 32768;      // counter bytes per dense workgroup (four per CU)
+constexpr int kDenseThreads = 512;         // threads of the dense (vertex, key range) kernel
+constexpr int kDenseLdsBytes = 65536;      // counter bytes per dense workgroup (two per CU)
 // Update bins: wave path, bitmap path, and the dense path per counter width
 // (2, 4, 8, 16 bits) split into light and heavy vertices; a heavy vertex is
 // cut into kHeavySplit times more (smaller) work items.
