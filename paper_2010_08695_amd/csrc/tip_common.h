@@ -45,7 +45,7 @@ constexpr int kApplyBatch = 4;             // (key, c) pairs a lane gathers befo
 constexpr int64_t kItemWedges = 16384;     // a dense item of a light vertex has at most about this many wedges
 constexpr int kHeavySplit = 8;
 constexpr int kDensePasses = 4;            // key-range passes of one light dense work item
-constexpr int64_t kDense16Stage = 64;      // 16-bit dense: wedges >= this * degree * key-range passes
+constexpr int64_t kDense16Stage = 4;       // 16-bit dense: wedges >= this * degree * key-range passes
 // CD lists are compacted at a range start once the entries of vertices
 // assigned since the last compaction reach this share (per mille) of the
 // entries left (tip_opts.tune[2]).
