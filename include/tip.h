@@ -95,7 +95,16 @@ typedef struct {
                         range start once the entries of vertices peeled
                         since the last compaction reach tune[2] per mille of
                         the entries left (0 = 125);
-                        tune[0..2] >= 0; tune[3..7] reserved, must be 0 */
+                        tune[3]: HUC (Section 4.1): a coarse-grained round
+                        whose peel work (wedge proxy of its activeSet) exceeds
+                        tune[3] percent of the re-count work (counting wedges
+                        scaled by the live share of the side) re-counts the
+                        live vertices' supports instead of applying the
+                        round's decrements; 0 = never (the default; on the
+                        GPU a re-count costs about nine times a peel per
+                        wedge), 100 = the rule of the paper; the results do
+                        not change;
+                        tune[0..3] >= 0; tune[4..7] reserved, must be 0 */
 } tip_opts;
 
 /* Work and time accounting of one decomposition (NULL = not wanted). */
@@ -119,6 +128,7 @@ typedef struct {
     int64_t peel_pairs;    /* support decrements it applied */
     double peel_ms;        /* summed launch time (TIP_FLAG_TIME_KERNELS), else 0 */
     double t_ingest_ms, t_count_ms, t_cd_ms, t_fd_ms, t_total_ms; /* device time per phase */
+    int64_t huc_rounds;    /* coarse-grained rounds that re-counted instead of peeling (tune[3]) */
 } tip_stats;
 
 /* Per-vertex butterfly counts of both sides (Alg. 1, Section 2.1) and the

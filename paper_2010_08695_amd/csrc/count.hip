@@ -107,7 +107,10 @@ __global__ void k_count_bins(const int64_t* __restrict__ work, int64_t n, int32_
 
 __global__ void __launch_bounds__(kSmallThreads)
 k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, const int64_t* __restrict__ work,
-              int64_t* bfly_a, int64_t* bfly_b) {
+              int64_t* bfly_a, int64_t* bfly_b, const int32_t* __restrict__ live_a) {
+    // live_a (re-count of the live graph, HUC): only when the round asks for
+    // it; side-A vertices count only while live, side-B counts are not kept
+    if (live_a && !ctl->huc_now) return;
     __shared__ WaveLds WL[kSmallThreads / kWave];
     __shared__ HotCounts hot;
     const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
@@ -122,10 +125,13 @@ k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, con
         const bool side_b = item >= g.n_a;
         const int own = side_b ? 1 : 0;
         const int32_t x = side_b ? item - g.n_a : item;
+        if (live_a && !side_b && live_a[x] != kLive) continue;
         const SideView sv = side_view(g, side_b, bfly_a, bfly_b);
         const int64_t e0 = sv.own_off[x], d = sv.own_off[x + 1] - e0;
         const uint32_t slots = wave_slots(work[item]);
         const uint32_t mask = slots - 1;
+        const bool mid_dead_check = live_a && side_b;   // middle vertices on side A
+        const bool end_dead_check = live_a && !side_b;  // end vertices on side A
         // pass 1: wedge counts c(x, z)
         for (int64_t g0 = 0; g0 < d; g0 += kWave) {
             const int gs = (int)min<int64_t>(kWave, d - g0);
@@ -134,20 +140,21 @@ k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, con
                 const int64_t e = e0 + g0 + lane;
                 const int32_t y = sv.own_adj[e];
                 W.sbeg[lane] = sv.oth_off[y];
-                len = min(sv.oth_cut[y], sv.own_rev[e]);
+                len = (mid_dead_check && live_a[y] != kLive) ? 0 : min(sv.oth_cut[y], sv.own_rev[e]);
             }
             const int64_t tot = wave_scan_lengths(W, len);
             int j = 0;
             for (int64_t i = lane; i < tot; i += kWave) {
                 while (j + 1 < gs && W.pre[j + 1] <= i) ++j;
-                wave_insert(W, (uint32_t)sv.oth_adj[W.sbeg[j] + (i - W.pre[j])], mask);
+                const uint32_t z = (uint32_t)sv.oth_adj[W.sbeg[j] + (i - W.pre[j])];
+                if (!end_dead_check || live_a[z] == kLive) wave_insert(W, z, mask);
             }
             wave_sync();
         }
         // pass 2: middle vertices gain c - 1 per wedge; with one chunk of
         // neighbours the runs staged by pass 1 are still in LDS
         const bool one_chunk = d <= kWave;
-        for (int64_t g0 = 0; g0 < d; g0 += kWave) {
+        for (int64_t g0 = 0; g0 < (end_dead_check ? 0 : d); g0 += kWave) {
             const int gs = (int)min<int64_t>(kWave, d - g0);
             int64_t len = 0;
             int32_t y = 0;
@@ -160,7 +167,7 @@ k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, con
                     const int64_t e = e0 + g0 + lane;
                     y = sv.own_adj[e];
                     W.sbeg[lane] = sv.oth_off[y];
-                    len = min(sv.oth_cut[y], sv.own_rev[e]);
+                    len = (mid_dead_check && live_a[y] != kLive) ? 0 : min(sv.oth_cut[y], sv.own_rev[e]);
                 }
                 tot = wave_scan_lengths(W, len);
             }
@@ -182,7 +189,7 @@ k_count_small(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, con
             const unsigned long long v = W.tab[s];
             if (v) {
                 const int64_t c = (int64_t)(v & 0xffffffffull);
-                if (c >= 2) {
+                if (c >= 2 && !mid_dead_check) {
                     const int64_t b = choose2(c);
                     hot.add(sv.own_bfly, own, (int64_t)(v >> 32) - 1, b);
                     local += b;
@@ -216,7 +223,8 @@ struct CountSlice {
 
 __global__ void __launch_bounds__(kBigThreads)
 k_count_big(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64_t* bfly_a, int64_t* bfly_b,
-            SpillArena spa, Ctl* ctl_rw) {
+            SpillArena spa, Ctl* ctl_rw, const int32_t* __restrict__ live_a) {
+    if (live_a && !ctl->huc_now) return;
     __shared__ BigLds L;
     __shared__ HotCounts hot;
     constexpr int NT = kBigThreads;
@@ -233,9 +241,12 @@ k_count_big(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64
         const bool side_b = item >= g.n_a;
         const int own = side_b ? 1 : 0;
         const int32_t x = side_b ? item - g.n_a : item;
+        if (live_a && !side_b && live_a[x] != kLive) continue;
         const SideView sv = side_view(g, side_b, bfly_a, bfly_b);
         const int64_t e0 = sv.own_off[x], d = sv.own_off[x + 1] - e0;
         const bool multi = x > kBmBits;
+        const bool mid_dead_check = live_a && side_b;
+        const bool end_dead_check = live_a && !side_b;
         for (int32_t klo = 0; klo < x; klo += kBmBits) {
             const int32_t khi = (int32_t)min<int64_t>(x, (int64_t)klo + kBmBits);
             // pass 1
@@ -245,12 +256,14 @@ k_count_big(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64
                 if (tid < gs) {
                     int64_t s0;
                     CountSlice::get(sv, e0 + g0 + tid, multi, klo, khi, s0, len);
+                    if (mid_dead_check && live_a[sv.own_adj[e0 + g0 + tid]] != kLive) len = 0;
                     L.sbeg[tid] = s0;
                 }
                 const int64_t tot = block_scan_lengths<NT>(L, gs, len);
                 for (int64_t i = tid; i < tot; i += NT) {
                     const int j = find_slice(L, gs, i);
-                    bm_mark(L, sp, (uint32_t)(sv.oth_adj[L.sbeg[j] + (i - L.pre[j])] - klo));
+                    const int32_t z = sv.oth_adj[L.sbeg[j] + (i - L.pre[j])];
+                    if (!end_dead_check || live_a[z] == kLive) bm_mark(L, sp, (uint32_t)(z - klo));
                 }
                 __syncthreads();
             }
@@ -258,7 +271,7 @@ k_count_big(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64
             // pass 2; with one group of neighbours the runs staged by pass 1
             // are still in LDS
             const bool one_group = d <= kGroup;
-            for (int64_t g0 = 0; g0 < d; g0 += kGroup) {
+            for (int64_t g0 = 0; g0 < (end_dead_check ? 0 : d); g0 += kGroup) {
                 const int gs = (int)min<int64_t>(kGroup, d - g0);
                 int64_t len = 0;
                 int64_t tot;
@@ -270,6 +283,7 @@ k_count_big(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64
                     if (tid < gs) {
                         int64_t s0;
                         CountSlice::get(sv, e0 + g0 + tid, multi, klo, khi, s0, len);
+                        if (mid_dead_check && live_a[sv.own_adj[e0 + g0 + tid]] != kLive) len = 0;
                         L.sbeg[tid] = s0;
                         L.acc[tid] = 0;
                     }
@@ -289,7 +303,7 @@ k_count_big(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64
             int64_t local = 0;
             for (int s = tid; s < kRepSlots; s += NT) {
                 const unsigned long long v = L.rep[s];
-                if (v) {
+                if (v && !mid_dead_check) {
                     const int64_t c = 1 + (int64_t)(v & 0xffffffffull);
                     const int64_t b = choose2(c);
                     hot.add(sv.own_bfly, own, klo + (int64_t)(v >> 32) - 1, b);
@@ -300,9 +314,11 @@ k_count_big(DevGraph g, const int32_t* __restrict__ items, const Ctl* ctl, int64
             spills += (tid == 0) ? (unsigned long long)nsp : 0ull;
             for (int32_t i = tid; i < nsp; i += NT) {
                 const int32_t k = sp.list[i];
-                const int64_t b = choose2(1 + (int64_t)sp.dense[k]);
-                hot.add(sv.own_bfly, own, klo + (int64_t)k, b);
-                local += b;
+                if (!mid_dead_check) {
+                    const int64_t b = choose2(1 + (int64_t)sp.dense[k]);
+                    hot.add(sv.own_bfly, own, klo + (int64_t)k, b);
+                    local += b;
+                }
                 sp.dense[k] = 0;
             }
             const int64_t total = block_sum_i64<NT>(L, local);
@@ -335,9 +351,31 @@ void launch_count(const DevGraph& g, CountBuffers& cb, Ctl* ctl, const SpillAren
     TIP_HIP_TRY(hipGetLastError());
     k_count_bins<<<grid1(n_tot, 4096), kT, 0, s>>>(cb.work, n_tot, cb.items_small, cb.items_big, ctl);
     TIP_HIP_TRY(hipGetLastError());
-    k_count_small<<<2048, kSmallThreads, 0, s>>>(g, cb.items_small, ctl, cb.work, cb.bfly_a, cb.bfly_b);
+    k_count_small<<<2048, kSmallThreads, 0, s>>>(g, cb.items_small, ctl, cb.work, cb.bfly_a, cb.bfly_b, nullptr);
     TIP_HIP_TRY(hipGetLastError());
-    k_count_big<<<big_grid, kBigThreads, 0, s>>>(g, cb.items_big, ctl, cb.bfly_a, cb.bfly_b, spill, ctl);
+    k_count_big<<<big_grid, kBigThreads, 0, s>>>(g, cb.items_big, ctl, cb.bfly_a, cb.bfly_b, spill, ctl, nullptr);
+    TIP_HIP_TRY(hipGetLastError());
+}
+
+// HUC (Section 4.1): when the control block says so for this round, the
+// side-A counts are computed again on the graph of live side-A vertices
+// (state == kLive) and all of side B, into bfly_a, which then holds every
+// live vertex's support.  Reuses the work items of the first count; every
+// kernel returns at once otherwise, so the launches can sit in a captured
+// round.
+__global__ void k_clear_if_huc(int64_t* a, int64_t n, const Ctl* ctl) {
+    if (!ctl->huc_now) return;
+    GRID_STRIDE(i, n) a[i] = 0;
+}
+
+void launch_recount(const DevGraph& g, CountBuffers& cb, const int32_t* state, Ctl* ctl, const SpillArena& spill,
+                    int big_grid, hipStream_t s) {
+    if (g.m == 0) return;
+    k_clear_if_huc<<<grid1(g.n_a, 1024), kT, 0, s>>>(cb.bfly_a, g.n_a, ctl);
+    TIP_HIP_TRY(hipGetLastError());
+    k_count_small<<<2048, kSmallThreads, 0, s>>>(g, cb.items_small, ctl, cb.work, cb.bfly_a, cb.bfly_b, state);
+    TIP_HIP_TRY(hipGetLastError());
+    k_count_big<<<big_grid, kBigThreads, 0, s>>>(g, cb.items_big, ctl, cb.bfly_a, cb.bfly_b, spill, ctl, state);
     TIP_HIP_TRY(hipGetLastError());
 }
 

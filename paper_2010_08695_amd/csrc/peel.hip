@@ -448,6 +448,8 @@ __global__ void k_frontier_scan(FrontSet fs, const int32_t* live0, const int32_t
 }
 
 __global__ void k_set_range(Ctl* ctl, long long hi, int32_t label, int32_t live, int32_t n_live) {
+    ctl->huc_now = 0;
+    ctl->huc_w_prev = 0;
     ctl->range_hi = hi;
     ctl->range_label = label;
     ctl->range_live = live;
@@ -532,7 +534,7 @@ struct PeelCounters {
 __global__ void __launch_bounds__(kSmallThreads)
 k_peel_wave(DevGraph g, FrontSet fs, const int64_t* __restrict__ wprox, CdApply ap, Ctl* ctl) {
     const int64_t n_front = ctl->n_front[kBinWave];
-    if (n_front == 0) return;
+    if (n_front == 0 || ctl->huc_now) return;
     const int32_t* __restrict__ front = fs.list[ctl->front_buf][kBinWave];
     __shared__ WaveLds WL[kSmallThreads / kWave];
     const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
@@ -614,7 +616,7 @@ __global__ void __launch_bounds__(kBmThreads)
 k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, FrontSet fs, CdApply ap,
               SpillArena spa, Ctl* ctl) {
     const int64_t n_front = ctl->n_front[kBinBitmap];
-    if (n_front == 0) return;
+    if (n_front == 0 || ctl->huc_now) return;
     const int32_t* __restrict__ front = fs.list[ctl->front_buf][kBinBitmap];
     __shared__ BmLds L;
     constexpr int NT = kBmThreads;
@@ -883,6 +885,7 @@ __global__ void __launch_bounds__(kDenseThreads)
 k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt, FrontSet fs, ItemKeys g_max,
              int64_t slots, CdApply ap, Ctl* ctl) {
     constexpr int NT = kDenseThreads;
+    if (ctl->huc_now) return;
     // only tiles below the live key bound can hold a key to update; ntt
     // itself stays the row stride of the tile-bound table
     const int32_t ntk = min(ntt, (int32_t)((max(ctl->key_hi, 1) + (int64_t)tk - 1) / tk));
@@ -979,6 +982,30 @@ void launch_dense(const DevGraph& g, PeelBuffers& pb, const FrontSet& fs, CdAppl
     TIP_HIP_TRY(hipGetLastError());
 }
 
+// HUC (Section 4.1): the round about to run re-counts the live supports
+// instead of peeling when the peel work of its activeSet (its wedge proxy,
+// added to the range by the frontier scan) exceeds huc_pct percent of the
+// re-count work, estimated as the counting wedges scaled by the share of
+// side A still live at the range start.  Either way the supports after the
+// round are the same.
+__device__ inline void huc_decide(Ctl* ctl) {
+    unsigned long long w = 0;
+    for (int i = 0; i < kSpread; ++i) w += ctl->spread[i][kScWRange];
+    const unsigned long long peel = w - ctl->huc_w_prev;
+    ctl->huc_w_prev = w;
+    const double rcnt = (double)ctl->wedges_count * (double)ctl->range_n_live / (double)max(ctl->huc_n_a, 1);
+    ctl->huc_now = (ctl->huc_pct > 0 && peel > 0 && (double)peel * 100.0 > (double)ctl->huc_pct * rcnt) ? 1 : 0;
+    ctl->huc_rounds += (unsigned long long)ctl->huc_now;
+}
+
+__global__ void k_huc_decide(Ctl* ctl) { huc_decide(ctl); }
+
+__global__ void k_set_huc(Ctl* ctl, long long pct, int32_t n_a) {
+    ctl->huc_pct = pct;
+    ctl->huc_n_a = n_a;
+    ctl->huc_now = 0;
+}
+
 __global__ void k_ctl_swap_front(Ctl* ctl) {
     int32_t any = 0;
     for (int b = 0; b < kBins; ++b) {
@@ -991,6 +1018,7 @@ __global__ void k_ctl_swap_front(Ctl* ctl) {
         ++ctl->rounds_done;
         ctl->front_buf ^= 1;
     }
+    if (ctl->huc_pct > 0) huc_decide(ctl);
 }
 
 __global__ void k_assign_live(const int32_t* __restrict__ live, int32_t n_live, int32_t* state, int32_t label) {
@@ -1151,6 +1179,8 @@ void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers
         TIP_HIP_TRY(hipMemcpyAsync(pb.cd_adj, g.b_adj, sizeof(int32_t) * g.m, hipMemcpyDeviceToDevice, s));
         TIP_HIP_TRY(hipMemcpyAsync(pb.cd_row, g.b_row, sizeof(int32_t) * g.m, hipMemcpyDeviceToDevice, s));
     }
+    k_set_huc<<<1, 1, 0, s>>>(ctl, (long long)tune.huc_pct, g.n_a);
+    TIP_HIP_TRY(hipGetLastError());
     k_set_cd_m<<<1, 1, 0, s>>>(ctl, (long long)g.m, g.n_a);
     TIP_HIP_TRY(hipGetLastError());
     const int64_t n_tb = (int64_t)g.n_b * (pb.ntt + 1);
@@ -1223,13 +1253,17 @@ void launch_select(PeelBuffers& pb, int cur_live, int32_t n_live, uint64_t max_s
 }
 
 void launch_range_begin(const DevGraph& g, PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi,
-                        int32_t label, Ctl* ctl, hipStream_t s) {
+                        int32_t label, Ctl* ctl, hipStream_t s, bool huc) {
     k_set_range<<<1, 1, 0, s>>>(ctl, (long long)hi, label, cur_live, n_live);
     TIP_HIP_TRY(hipGetLastError());
     if (n_live <= 0) return;
     k_frontier_scan<<<grid1(n_live, 4096), kT, 0, s>>>(front_set(pb), pb.live[0], pb.live[1], pb.supp, pb.state,
                                                         pb.wprox, pb.bin, g.a_off, 0, ctl);
     TIP_HIP_TRY(hipGetLastError());
+    if (huc) {
+        k_huc_decide<<<1, 1, 0, s>>>(ctl);
+        TIP_HIP_TRY(hipGetLastError());
+    }
 }
 
 // Resident workgroups of the bitmap-path kernel on the current device.
@@ -1241,7 +1275,7 @@ int bitmap_grid() {
 }
 
 void launch_round(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena& spill, int big_grid,
-                  hipStream_t s, hipEvent_t* ev_big, const int32_t* n_cur) {
+                  hipStream_t s, hipEvent_t* ev_big, const int32_t* n_cur, CountBuffers* cb) {
     const CdApply ap{pb.supp};
     const FrontSet fs = front_set(pb);
     if (g.n_a <= 0) return;
@@ -1253,6 +1287,9 @@ void launch_round(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena
     // returns at once when it has none.  With the frontier sizes known on the
     // host (n_cur), kernels without work are not launched at all.
     const auto has = [&](int b) { return !n_cur || n_cur[b] > 0; };
+    // HUC: a round the control block marks re-counts (the update kernels
+    // below then return at once); uses the original lists and their cuts
+    if (cb) launch_recount(g, *cb, pb.state, ctl, spill, big_grid, s);
     if (has(kBinWave)) {
         k_peel_wave<<<2048, kSmallThreads, 0, s>>>(gc, fs, pb.wlive, ap, ctl);
         TIP_HIP_TRY(hipGetLastError());

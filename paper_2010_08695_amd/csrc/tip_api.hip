@@ -150,10 +150,11 @@ struct RoundGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 
-    void build(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena& spill, int big_grid) {
+    void build(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena& spill, int big_grid,
+               CountBuffers* cb) {
         TIP_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         TIP_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < kRoundsPerGraph; ++k) launch_round(g, pb, ctl, spill, big_grid, cs, nullptr, nullptr);
+        for (int k = 0; k < kRoundsPerGraph; ++k) launch_round(g, pb, ctl, spill, big_grid, cs, nullptr, nullptr, cb);
         TIP_HIP_TRY(hipStreamEndCapture(cs, &graph));
         TIP_HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     }
@@ -328,6 +329,8 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
     } else {
         // Coarse-grained decomposition (Alg. 3).
         PeelBuffers& pb = w.pb;
+        // HUC re-count launches join the rounds only when asked for
+        CountBuffers* huc_cb = tune.huc_pct > 0 ? &w.cb : nullptr;
         launch_peel_setup(g, w.aux.deg_b, pb, tune, w.ctl, s);
         const CompactScratch cscr{w.ib.flags, reinterpret_cast<int64_t*>(w.ib.keys), w.ib.scan_tmp, w.ib.ea, w.ib.eb};
         fill_i32(pb.state, kLive, n_a, s);
@@ -367,7 +370,7 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
                 hi = c1.sel_found ? (int64_t)c1.sel_prefix + 1 : (int64_t)max_supp + 1;
             }
             bounds.push_back(hi);
-            launch_range_begin(g, pb, cur_live, n_live, hi, label, w.ctl, s);
+            launch_range_begin(g, pb, cur_live, n_live, hi, label, w.ctl, s, huc_cb != nullptr);
             for (;;) {
                 const Ctl& c2 = read_ctl(w, s);
                 int32_t n_cur[kBins];
@@ -377,14 +380,15 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
                 if (!eager) {
                     if (!rg) {
                         rg.reset(new RoundGraph);
-                        rg->build(g, pb, w.ctl, w.spill, big_grid);
+                        rg->build(g, pb, w.ctl, w.spill, big_grid, huc_cb);
                     }
                     TIP_HIP_TRY(hipGraphLaunch(rg->exec, s));
                     continue;
                 }
                 int32_t nb = 0;  // vertices for the timed (dense) update kernel
                 for (int b = dense_bin_of_kind(0, false); b < kBins; ++b) nb += n_cur[b];
-                launch_round(g, pb, w.ctl, w.spill, big_grid, s, time_kernels && nb > 0 ? kev.e : nullptr, n_cur);
+                launch_round(g, pb, w.ctl, w.spill, big_grid, s, time_kernels && nb > 0 ? kev.e : nullptr, n_cur,
+                             huc_cb);
                 if (nb > 0) {
                     ++peel_launches;
                     if (time_kernels) {
@@ -461,6 +465,7 @@ void run_back(Work& w, int32_t n_a, int32_t n_b, bool decompose, RunOut& out, Ru
         st->wedges_fd = (int64_t)cf.wedges_fd;
         st->pair_updates = (int64_t)(cf.pair_updates + spread_sum(cf, kScPairs));
         st->rounds = (int64_t)cf.rounds_done;
+        st->huc_rounds = (int64_t)cf.huc_rounds;
         st->subsets = S;
         st->fd_levels = (int64_t)cf.fd_levels;
         st->spills = (int64_t)(cf.spills + spread_sum(cf, kScSpills));
@@ -528,10 +533,10 @@ int32_t check_opts(const tip_opts* opt) {
     if (opt->P < 0 || opt->P > kMaxP) throw InvalidArg("P must be in [0, 65535]");
     if (opt->flags & ~(TIP_FLAG_TIME_KERNELS | TIP_FLAG_NO_GRAPH | TIP_FLAG_BATCH_PLAIN | TIP_FLAG_NO_COMPACT))
         throw InvalidArg("unknown flag bits");
-    for (int i = 0; i < 3; ++i)
-        if (opt->tune[i] < 0) throw InvalidArg("tune[0..2] must be >= 0");
-    for (int i = 3; i < 8; ++i)
-        if (opt->tune[i] != 0) throw InvalidArg("tune[3..7] must be 0");
+    for (int i = 0; i < 4; ++i)
+        if (opt->tune[i] < 0) throw InvalidArg("tune[0..3] must be >= 0");
+    for (int i = 4; i < 8; ++i)
+        if (opt->tune[i] != 0) throw InvalidArg("tune[4..7] must be 0");
     return opt->P == 0 ? kDefaultP : opt->P;
 }
 
@@ -540,6 +545,7 @@ Tune tune_of(const tip_opts* opt) {
     if (opt && opt->tune[0] > 0) t.dense_div = opt->tune[0];
     if (opt && opt->tune[1] > 0) t.bitmap_max = opt->tune[1];
     if (opt && opt->tune[2] > 0) t.compact_permille = opt->tune[2];
+    if (opt) t.huc_pct = opt->tune[3];
     if (opt && (opt->flags & TIP_FLAG_NO_COMPACT)) t.compact_permille = 0;
     return t;
 }

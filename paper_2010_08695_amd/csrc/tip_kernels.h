@@ -54,6 +54,13 @@ struct Ctl {
     int32_t range_n_live;    // its length
     int32_t front_buf;       // which frontier buffer is current
     unsigned long long rounds_done;  // rounds with a non-empty activeSet
+    // HUC (Section 4.1): huc_now asks this round to re-count instead of
+    // peeling; decided from the wedge proxy its activeSet added to the range
+    int32_t huc_now;
+    int32_t huc_n_a;              // vertices of side A
+    long long huc_pct;            // re-count when peel work > huc_pct % of re-count work; 0 = never
+    unsigned long long huc_w_prev;  // range wedge proxy at the previous decision
+    unsigned long long huc_rounds;  // rounds that re-counted
 };
 
 __device__ inline void spread_add(Ctl* ctl, int c, unsigned long long v) {
@@ -149,6 +156,7 @@ struct Tune {
     int64_t dense_div = kDefaultDenseDiv;
     int64_t bitmap_max = kDefaultBitmapMax;
     int64_t compact_permille = kDefaultCompactPermille;  // 0: never compact
+    int64_t huc_pct = 0;  // tip_opts.tune[3]
 };
 
 // counting
@@ -169,7 +177,7 @@ void launch_select(PeelBuffers& pb, int cur_live, int32_t n_live, uint64_t max_s
                    hipStream_t s);
 // Sets the range state and builds the range's first activeSet.
 void launch_range_begin(const DevGraph& g, PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi,
-                        int32_t label, Ctl* ctl, hipStream_t s);
+                        int32_t label, Ctl* ctl, hipStream_t s, bool huc);
 // One coarse-grained round, driven entirely by the control block: update
 // kernels over the current activeSet, then the next activeSet and the buffer
 // swap.  Fixed grids, no host synchronisation, so it can be graph-captured.
@@ -178,8 +186,12 @@ void launch_range_begin(const DevGraph& g, PeelBuffers& pb, int cur_live, int32_
 // n_cur: the frontier sizes per bin when the host knows them (kernels
 // without work are then skipped), or nullptr (graph capture: every kernel
 // is launched and checks its own work).
+// HUC re-count of the live side-A supports, when the control block asks for it.
+void launch_recount(const DevGraph& g, CountBuffers& cb, const int32_t* state, Ctl* ctl, const SpillArena& spill,
+                    int big_grid, hipStream_t s);
+// One coarse-grained round; cb != nullptr adds the HUC re-count launches.
 void launch_round(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena& spill, int big_grid,
-                  hipStream_t s, hipEvent_t* ev_big, const int32_t* n_cur);
+                  hipStream_t s, hipEvent_t* ev_big, const int32_t* n_cur, CountBuffers* cb);
 void launch_assign_live(PeelBuffers& pb, int cur_live, int32_t n_live, int32_t label, hipStream_t s);
 // One graph's part of a fine-grained launch.
 struct FdJob {

@@ -323,3 +323,27 @@ def test_batch_with_large_subsets_against_golden(gpu_lib):
     np.testing.assert_array_equal(out[0], oracle.bup(small, 0)[0])
     assert digest(out[1]) == rec["theta_u"]["sha256"]
     assert digest(out[2]) == rec["theta_v"]["sha256"]
+
+
+@pytest.mark.parametrize("P", [5, 150])
+def test_huc_recount_changes_nothing(gpu_lib, P):
+    """HUC (Section 4.1): with a threshold of 1% nearly every coarse-grained
+    round re-counts the live supports (Alg. 1 on the live graph) instead of
+    peeling; the subsets, their initial supports and the tip numbers are
+    those of peeling, in graph replay and in host-launched rounds."""
+    g = gg.chung_lu(6000, 1200, 60000, 2.2, 2.0, seed=43)
+    th = oracle.bup(g, 0)[0]
+    ref = tip.decompose_ex(g, 0, P=P)
+    for flags in (0, tip.TIP_FLAG_NO_GRAPH):
+        got = tip.decompose_ex(g, 0, P=P, flags=flags, tune=[0, 0, 0, 1])
+        np.testing.assert_array_equal(got["theta"], th)
+        np.testing.assert_array_equal(got["subset"], ref["subset"])
+        np.testing.assert_array_equal(got["init"], ref["init"])
+        np.testing.assert_array_equal(got["bounds"], ref["bounds"])
+        assert got["stats"]["huc_rounds"] > 0
+        assert got["stats"]["rounds"] == ref["stats"]["rounds"]
+    assert ref["stats"]["huc_rounds"] == 0
+    # side V and a degenerate graph
+    np.testing.assert_array_equal(tip.decompose(g, 1, tune=[0, 0, 0, 1]), oracle.bup(g, 1)[0])
+    k = gg.complete_bipartite(30, 20)
+    np.testing.assert_array_equal(tip.decompose(k, 0, tune=[0, 0, 0, 1]), np.full(30, 29 * comb(20, 2)))
