@@ -135,11 +135,28 @@ __device__ inline void traverse_units(const Stage<NT, NR>& S, int gs, int32_t nu
 // ---------------------------------------------------------------------------
 
 // w[u]: wedges of G with endpoint u (the range-sizing proxy), i.e. the sum
-// over v in N_u of d_v - 1.
+// over v in N_u of d_v - 1.  CSR rows are contiguous, so the terms are summed
+// per row inside each wave and one atomic goes out per row piece (a hub row
+// would otherwise take one atomic per edge on one address).
 __global__ void k_wproxy(DevGraph g, const int32_t* __restrict__ deg_b, int64_t* wprox) {
-    GRID_STRIDE(p, g.m) {
-        const int32_t dv = deg_b[g.a_adj[p]];
-        if (dv > 1) atomic_add_i64(&wprox[g.a_row[p]], dv - 1);
+    const int lane = threadIdx.x & (kWave - 1);
+    UNIFORM_STRIDE(base, g.m) {
+        const int64_t p = base + threadIdx.x;
+        int32_t u = -1;
+        int64_t x = 0;
+        if (p < g.m) {
+            u = g.a_row[p];
+            const int32_t dv = deg_b[g.a_adj[p]];
+            x = dv > 1 ? dv - 1 : 0;
+        }
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int64_t y = __shfl_up(x, d, kWave);
+            const int32_t uy = __shfl_up(u, d, kWave);
+            if (lane >= d && uy == u) x += y;
+        }
+        const int32_t un = __shfl_down(u, 1, kWave);
+        if (u >= 0 && (lane == kWave - 1 || un != u) && x) atomic_add_i64(&wprox[u], x);
     }
 }
 
