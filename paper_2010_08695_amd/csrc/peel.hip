@@ -166,10 +166,12 @@ __global__ void k_wproxy(DevGraph g, const int32_t* __restrict__ deg_b, int64_t*
 // above that the dense kernel, unless its counter bytes (n_a * bits / 8,
 // bits from the degree so that c(u, w) <= d_u fits) are large against the
 // wedges (w <= n_a * bits / dense_div), or one table tile of its counters
-// does not fit the workgroup's LDS (sides of more than 8M keys).  With 16-bit
+// does not fit the workgroup's LDS (sides of more than 64M keys).  With 16-bit
 // counters an item covers one list tile, so every pass stages all of u's
 // neighbours again: such a vertex takes the dense path only when its wedges
-// are at least kDense16Stage times its degree times the passes.  A dense
+// are at least kDense16Stage times its degree times the passes, or when they
+// are more than one bitmap workgroup takes without spilling (late hubs whose
+// live wedges have shrunk would otherwise run on one workgroup).  A dense
 // vertex is heavy when a light-sized item (item_keys[kind] keys) would hold
 // more than kItemWedges of its wedges.
 struct ItemKeys {
@@ -189,7 +191,7 @@ __global__ void k_peel_bins(const int64_t* __restrict__ a_off, const int64_t* __
             b = kBinWave;
         } else if (bits && ik.k[dense_kind(bits)] * bits <= (int64_t)kDenseLdsBytes * 8 &&
                    w > max<int64_t>(bm_max, nk * bits / dense_div) &&
-                   (bits < 16 ||
+                   (bits < 16 || w > kBmHubWedges ||
                     w >= kDense16Stage * d * ((nk + ik.k[dense_kind(bits)] - 1) / ik.k[dense_kind(bits)]))) {
             const bool heavy = (double)w * (double)ik.k[dense_kind(bits)] > (double)kItemWedges * (double)nk;
             b = (uint8_t)dense_bin(bits, heavy);

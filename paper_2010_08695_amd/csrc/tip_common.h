@@ -46,6 +46,7 @@ constexpr int64_t kItemWedges = 16384;     // a dense item of a light vertex has
 constexpr int kHeavySplit = 8;
 constexpr int kDensePasses = 4;            // key-range passes of one light dense work item
 constexpr int64_t kDense16Stage = 4;       // 16-bit dense: wedges >= this * degree * key-range passes
+constexpr int64_t kBmHubWedges = 16384;    // ... or more wedges than one bitmap workgroup takes without spilling
 // CD lists are compacted at a range start once the entries of vertices
 // assigned since the last compaction reach this share (per mille) of the
 // entries left (tip_opts.tune[2]).
@@ -61,10 +62,13 @@ __host__ __device__ inline int dense_bin_of_kind(int kind, bool heavy) { return 
 __host__ __device__ inline int dense_bin(int bits, bool heavy) { return dense_bin_of_kind(dense_kind(bits), heavy); }
 
 // Granularity (keys) of the per-list tile-bound table for a side of n keys:
-// 16K keys, or coarser so that there are at most 512 tiles.
+// 16K keys, or coarser so that there are at most 512 tiles; but 32K keys (one
+// tile of 16-bit dense counters fills a dense workgroup's LDS) while that
+// keeps at most 2048 tiles, so that sides of up to 64M keys keep the 16-bit
+// dense path.
 inline int32_t dense_tile_keys(int64_t n) {
     int64_t t = 16384;
-    while (t * 512 < n) t <<= 1;
+    while (t * 512 < n && !(t == 32768 && t * 2048 >= n)) t <<= 1;
     return (int32_t)t;
 }
 

@@ -115,19 +115,21 @@ def test_decompose_chung_lu_medium(gpu_lib):
             np.testing.assert_array_equal(tip.decompose(g, side), oracle.bup(g, side)[0])
 
 
-def test_side_above_eight_million_keys(gpu_lib):
-    """A side of more than 2^23 keys makes the list tiles 32K keys wide: one
-    tile of 16-bit counters no longer fits a dense workgroup's LDS, so such
-    vertices must take the bitmap path.  K_{300,3000} (theta = 299 * C(3000, 2)
-    for every U vertex, closed form) beside a Chung-Lu part checked by the
-    oracle on its own, padded with isolated U vertices."""
+@pytest.mark.parametrize("n_side", [8_500_000, 17_000_000])
+def test_side_above_eight_million_keys(gpu_lib, n_side):
+    """Sides of more than 2^23 keys make the list tiles 32K keys wide, so that
+    one tile of 16-bit counters fills a dense workgroup's LDS; above 2^24 keys
+    the tile-bound table has more than 512 tiles per list.  K_{300,3000}
+    (theta = 299 * C(3000, 2) for every U vertex, closed form; degree 3000
+    takes 16-bit counters) beside a Chung-Lu part checked by the oracle on its
+    own, padded with isolated U vertices."""
     k = gg.complete_bipartite(300, 3000)
     r = gg.chung_lu(3000, 800, 30000, 2.2, 2.0, seed=91)
-    n_pad = 8_500_000 - k.n_u - r.n_u
+    n_pad = n_side - k.n_u - r.n_u
     pad = gg.Graph(n_pad, 1, np.zeros(0, np.int32), np.zeros(0, np.int32), "pad")
     g = gg.disjoint_union(k, r, pad)
     th = tip.decompose(g, 0)
-    assert len(th) == 8_500_000
+    assert len(th) == n_side
     assert (th[:300] == 299 * comb(3000, 2)).all()
     np.testing.assert_array_equal(th[300:300 + r.n_u], oracle.bup(r, 0)[0])
     assert not th[300 + r.n_u:].any()
