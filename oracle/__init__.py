@@ -9,6 +9,9 @@ product library never imports it.
 * ``bup(g, side)``        tip numbers by sequential bottom-up peeling (Alg. 2)
 * ``support_in(g, side, member, query)``
                           f_x(S) for sampled vertices, for property checks
+* ``support_levels(g, side, theta, query)``
+                          f_x(S) for S = the side, theta >= theta_x and
+                          theta > theta_x, from one build of the adjacency
 * ``brute``               exponential brute force for tiny graphs
 """
 from __future__ import annotations
@@ -55,6 +58,8 @@ def _load(path: str | None = None):
     lib.oracle_bup.restype = ctypes.c_int
     lib.oracle_support_in.argtypes = [i32, i32, i64, p, p, i32, p, p, i64, p]
     lib.oracle_support_in.restype = ctypes.c_int
+    lib.oracle_support_levels.argtypes = [i32, i32, i64, p, p, i32, p, p, i64, p]
+    lib.oracle_support_levels.restype = ctypes.c_int
     return lib
 
 
@@ -107,4 +112,21 @@ def support_in(g, side: int, member: np.ndarray, query: np.ndarray, lib=None) ->
                                _ptr(query), query.shape[0], _ptr(out))
     if rc != 0:
         raise ValueError("oracle_support_in: invalid argument")
+    return out
+
+
+def support_levels(g, side: int, theta: np.ndarray, query: np.ndarray, lib=None) -> np.ndarray:
+    """int64[len(query), 3]: f_x(S) for each x in ``query`` with S = all of
+    the side, {w : theta_w >= theta_x} and {w : theta_w > theta_x}."""
+    lib = lib or _load()
+    eu, ev = _edges(g)
+    theta = np.ascontiguousarray(theta, dtype=np.int64)
+    if theta.shape != ((g.n_u if side == 0 else g.n_v),):
+        raise ValueError("support_levels: theta must hold one value per vertex of the side")
+    query = np.ascontiguousarray(query, dtype=np.int32)
+    out = np.zeros((query.shape[0], 3), np.int64)
+    rc = lib.oracle_support_levels(g.n_u, g.n_v, g.m, _ptr(eu), _ptr(ev), side, _ptr(theta),
+                                   _ptr(query), query.shape[0], _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle_support_levels: invalid argument")
     return out

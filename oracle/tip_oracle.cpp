@@ -17,7 +17,9 @@
 //     support as its tip number, and lower every remaining vertex u' by the
 //     butterflies it shares with it, never below the recorded value.
 //   * f_u(S): the butterflies of u inside the subgraph induced on S and the
-//     whole other side, for sampled property checks at any size.
+//     whole other side, for sampled property checks at any size; also for
+//     the three sets a tip-number array defines around u at once (all of the
+//     side, theta >= theta_u, theta > theta_u).
 //
 // Readings of the paper taken here:
 //   * Vertices already peeled are not updated (the update has no effect on
@@ -227,6 +229,44 @@ int oracle_support_in(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu,
             cnt[w] = 0;
         }
         out[q] = s;
+    }
+    return 0;
+}
+
+// For each query x, three values of f_x(S) from one walk of x's wedges:
+// out[3q] with S = all of side A, out[3q+1] with S = {w : theta[w] >= theta[x]}
+// and out[3q+2] with S = {w : theta[w] > theta[x]} (x itself never counts).
+int oracle_support_levels(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu,
+                          const int32_t* ev, int32_t side, const int64_t* theta,
+                          const int32_t* query, int64_t n_query, int64_t* out) {
+    if (n_u < 0 || n_v < 0 || m < 0 || (m > 0 && (!eu || !ev)) || !theta || !out) return -1;
+    if (side != 0 && side != 1) return -1;
+    if (n_query > 0 && !query) return -1;
+    Adjacency g;
+    if (!build(n_u, n_v, m, eu, ev, side, g)) return -1;
+    std::vector<int32_t> cnt(g.n_a, 0);
+    std::vector<int32_t> touched;
+    for (int64_t q = 0; q < n_query; ++q) {
+        const int32_t x = query[q];
+        if (x < 0 || x >= g.n_a) return -1;
+        touched.clear();
+        for (int32_t y : g.a_to_b[x])
+            for (int32_t w : g.b_to_a[y])
+                if (w != x) {
+                    if (cnt[w] == 0) touched.push_back(w);
+                    ++cnt[w];
+                }
+        int64_t all = 0, ge = 0, gt = 0;
+        for (int32_t w : touched) {
+            const int64_t f = choose2(cnt[w]);
+            all += f;
+            if (theta[w] >= theta[x]) ge += f;
+            if (theta[w] > theta[x]) gt += f;
+            cnt[w] = 0;
+        }
+        out[3 * q] = all;
+        out[3 * q + 1] = ge;
+        out[3 * q + 2] = gt;
     }
     return 0;
 }

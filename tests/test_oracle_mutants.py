@@ -36,6 +36,8 @@ MUTANTS = {
     "bup_counts_self_wedge": ("if (w == u) continue;\n                ++visited;",
                               "++visited;\n                if (w == u) continue;"),
     "support_in_ignores_member": ("if (w != x && member[w]) {", "if (w != x) {"),
+    "support_levels_ge_strict": ("if (theta[w] >= theta[x]) ge += f;", "if (theta[w] > theta[x]) ge += f;"),
+    "support_levels_gt_loose": ("if (theta[w] > theta[x]) gt += f;", "if (theta[w] >= theta[x]) gt += f;"),
 }
 
 
@@ -76,6 +78,12 @@ def _pins_pass(lib) -> bool:
         h = np.nonzero(member)[0].astype(np.int32)
         f = oracle.support_in(g, 0, member, h, lib=lib)
         assert int(f.min()) == int(th[h].min())
+        # tip numbers satisfy the certificate f_x(theta >= theta_x) >= theta_x
+        # and, at x's peel, f_x(theta > theta_x) <= theta_x; counts match
+        q = np.arange(g.n_u, dtype=np.int32)
+        lv = oracle.support_levels(g, 0, th, q, lib=lib)
+        assert (lv[:, 0] == oracle.count(g, lib=lib)[0]).all()
+        assert (lv[:, 1] >= th).all() and (lv[:, 2] <= th).all()
         return True
     except AssertionError:
         return False

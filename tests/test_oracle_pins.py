@@ -52,6 +52,24 @@ def test_bup_matches_subset_brute_force(side):
         np.testing.assert_array_equal(th, brute.tip_numbers(g, side), err_msg=g.name)
 
 
+@pytest.mark.parametrize("side", [0, 1])
+def test_support_levels_matches_pair_brute_force(side):
+    """f_x(S) for the three theta-defined sets against the butterflies each
+    pair {x, w} shares, found by enumerating column pairs (Section 2.1);
+    theta here is an arbitrary labelling with ties, not tip numbers."""
+    rng = np.random.default_rng(17 + side)
+    for g in _tiny_cases(40, 9, 8, 31 + side):
+        a = brute.dense(g) if side == 0 else brute.dense(g).T
+        pair = brute._pair_butterflies(a)
+        n = a.shape[0]
+        theta = rng.integers(0, 4, n)
+        q = np.arange(n, dtype=np.int32)
+        got = oracle.support_levels(g, side, theta, q)
+        for x in range(n):
+            want = (pair[x].sum(), pair[x][theta >= theta[x]].sum(), pair[x][theta > theta[x]].sum())
+            assert tuple(got[x]) == want, (g.name, x, got[x], want)
+
+
 def test_bup_matches_brute_force_on_denser_tiny_graphs():
     # 12-vertex sides with a biclique planted inside a sparse background, so
     # several distinct tip levels appear
