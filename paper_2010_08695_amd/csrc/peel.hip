@@ -466,7 +466,12 @@ __global__ void k_frontier_scan(FrontSet fs, const int32_t* live0, const int32_t
     }
 }
 
-__global__ void k_set_range(Ctl* ctl, long long hi, int32_t label, int32_t live, int32_t n_live) {
+// hi < 0: the bound is the select's result, read here on the device so that
+// the host need not wait for it (findHi's answer, or max_supp + 1 when no
+// prefix reached the target).
+__global__ void k_set_range(Ctl* ctl, long long hi, long long max_supp, int32_t label, int32_t live,
+                            int32_t n_live) {
+    if (hi < 0) hi = ctl->sel_found ? (long long)ctl->sel_prefix + 1 : max_supp + 1;
     ctl->huc_now = 0;
     ctl->huc_w_prev = 0;
     ctl->range_hi = hi;
@@ -1272,8 +1277,8 @@ void launch_select(PeelBuffers& pb, int cur_live, int32_t n_live, uint64_t max_s
 }
 
 void launch_range_begin(const DevGraph& g, PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi,
-                        int32_t label, Ctl* ctl, hipStream_t s, bool huc) {
-    k_set_range<<<1, 1, 0, s>>>(ctl, (long long)hi, label, cur_live, n_live);
+                        uint64_t max_supp, int32_t label, Ctl* ctl, hipStream_t s, bool huc) {
+    k_set_range<<<1, 1, 0, s>>>(ctl, (long long)hi, (long long)max_supp, label, cur_live, n_live);
     TIP_HIP_TRY(hipGetLastError());
     if (n_live <= 0) return;
     k_frontier_scan<<<grid1(n_live, 4096), kT, 0, s>>>(front_set(pb), pb.live[0], pb.live[1], pb.supp, pb.state,

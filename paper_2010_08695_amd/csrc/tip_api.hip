@@ -338,7 +338,6 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
         int cur_live = 0;
         int32_t n_live = n_a;
         double scale = 1.0;
-        int64_t lo = 0;
         std::vector<int64_t>& bounds = rs.bounds;
         bounds.assign(1, 0);
         int32_t label = 0;
@@ -361,30 +360,28 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
             // scaled by how far the previous subset overshot its target
             double tgt_d = std::ceil(scale * (double)w_rem / (double)(P - label));
             int64_t tgt = tgt_d < 1.0 ? 1 : (int64_t)tgt_d;
-            int64_t hi;
-            if (max_supp == 0) {
-                hi = 1;
-            } else {
-                launch_select(pb, cur_live, n_live, max_supp, tgt, w.ctl, s);
-                const Ctl& c1 = read_ctl(w, s);
-                hi = c1.sel_found ? (int64_t)c1.sel_prefix + 1 : (int64_t)max_supp + 1;
-            }
-            bounds.push_back(hi);
-            launch_range_begin(g, pb, cur_live, n_live, hi, label, w.ctl, s, huc_cb != nullptr);
+            // the range's upper bound stays on the device (k_set_range takes
+            // the select's result); the host learns it at the next read
+            int64_t hi = -1;
+            if (max_supp == 0) hi = 1;
+            else launch_select(pb, cur_live, n_live, max_supp, tgt, w.ctl, s);
+            launch_range_begin(g, pb, cur_live, n_live, hi, max_supp, label, w.ctl, s, huc_cb != nullptr);
+            // replayed rounds go out before the frontier is read: rounds past
+            // the end of a range do nothing, so a read per replay suffices
             for (;;) {
-                const Ctl& c2 = read_ctl(w, s);
-                int32_t n_cur[kBins];
-                int64_t n_tot = 0;
-                for (int b = 0; b < kBins; ++b) n_tot += (n_cur[b] = c2.n_front[b]);
-                if (n_tot == 0) break;
                 if (!eager) {
                     if (!rg) {
                         rg.reset(new RoundGraph);
                         rg->build(g, pb, w.ctl, w.spill, big_grid, huc_cb);
                     }
                     TIP_HIP_TRY(hipGraphLaunch(rg->exec, s));
-                    continue;
                 }
+                const Ctl& c2 = read_ctl(w, s);
+                int32_t n_cur[kBins];
+                int64_t n_tot = 0;
+                for (int b = 0; b < kBins; ++b) n_tot += (n_cur[b] = c2.n_front[b]);
+                if (n_tot == 0) break;
+                if (!eager) continue;
                 int32_t nb = 0;  // vertices for the timed (dense) update kernel
                 for (int b = dense_bin_of_kind(0, false); b < kBins; ++b) nb += n_cur[b];
                 launch_round(g, pb, w.ctl, w.spill, big_grid, s, time_kernels && nb > 0 ? kev.e : nullptr, n_cur,
@@ -403,12 +400,12 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
                     }
                 }
             }
-            const Ctl& c3 = read_ctl(w, s);
+            // the loop ends on a read with nothing launched after it
+            const Ctl& c3 = *host_ctl();
+            bounds.push_back((int64_t)c3.range_hi);
             const long long w_range = (long long)spread_sum(c3, kScWRange);
             if (w_range > 0) scale = std::min(1.0, (double)tgt / (double)w_range);
-            lo = hi;
         }
-        (void)lo;
         // Vertices left after P ranges form one more subset.
         launch_range_start(pb, cur_live, n_live, w.ctl, s);
         const Ctl& c4 = read_ctl(w, s);

@@ -176,8 +176,9 @@ void launch_compact(const DevGraph& g, PeelBuffers& pb, const CompactScratch& cs
 void launch_select(PeelBuffers& pb, int cur_live, int32_t n_live, uint64_t max_supp, int64_t tgt, Ctl* ctl,
                    hipStream_t s);
 // Sets the range state and builds the range's first activeSet.
+// hi < 0 takes the bound from the select launched just before.
 void launch_range_begin(const DevGraph& g, PeelBuffers& pb, int cur_live, int32_t n_live, int64_t hi,
-                        int32_t label, Ctl* ctl, hipStream_t s, bool huc);
+                        uint64_t max_supp, int32_t label, Ctl* ctl, hipStream_t s, bool huc);
 // One coarse-grained round, driven entirely by the control block: update
 // kernels over the current activeSet, then the next activeSet and the buffer
 // swap.  Fixed grids, no host synchronisation, so it can be graph-captured.
