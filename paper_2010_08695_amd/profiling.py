@@ -136,6 +136,50 @@ def cmd_traffic(args) -> int:
     return 0
 
 
+LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12   # 128 B per clock per CU, 256 CUs, 2.4 GHz
+LDS_CONFLICT_COUNTERS = ["SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "SQ_INSTS_LDS", "SQ_ACTIVE_INST_LDS",
+                         "SQ_WAVE_CYCLES", "SQ_BUSY_CU_CYCLES", "GRBM_GUI_ACTIVE"]
+LDS_BYTE_COUNTERS = ["SQ_INSTS_LDS_LOAD_BANDWIDTH", "SQ_INSTS_LDS_STORE_BANDWIDTH", "SQ_INSTS_LDS_ATOMIC_BANDWIDTH",
+                     "SQ_INSTS_LDS_ATOMIC"]
+
+
+def cmd_lds(args) -> int:
+    """LDS bank conflicts and LDS bytes of the top kernels from two counter
+    runs of the same program, with kernel times from a trace of it."""
+    va = {c: counter_per_dispatch(args.conflicts, c) for c in LDS_CONFLICT_COUNTERS}
+    vb = {c: counter_per_dispatch(args.bytes, c) for c in LDS_BYTE_COUNTERS}
+    times = {r["name"]: r["total_ns"] for r in kernel_stats(args.trace)}
+    lines = [f"# LDS bank conflicts and LDS traffic per kernel ({args.workload})",
+             f"command: {args.cmd}", "",
+             "conflict rate = SQ_LDS_BANK_CONFLICT / (SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT) (stall cycles per",
+             "conflict-free LDS cycle); LDS share of wave time = SQ_ACTIVE_INST_LDS / SQ_WAVE_CYCLES; LDS bytes =",
+             "64 x (SQ_INSTS_LDS_LOAD_BANDWIDTH + _STORE_ + _ATOMIC_) over the kernel's time in the trace;",
+             f"LDS peak {LDS_PEAK_TBS:.1f} TB/s (128 B per clock per CU, 256 CUs, 2.4 GHz)", "",
+             f"{'kernel':<18}{'disp':>6}{'LDS instr':>12}{'conflict rate':>15}{'LDS share':>11}"
+             f"{'LDS GB':>9}{'ms':>9}{'LDS TB/s':>10}{'of peak':>9}"]
+    for k in args.kernels.split(","):
+        tot = {c: sum(va[c].get(k, [])) for c in LDS_CONFLICT_COUNTERS}
+        tb = {c: sum(vb[c].get(k, [])) for c in LDS_BYTE_COUNTERS}
+        n = len(va["SQ_LDS_IDX_ACTIVE"].get(k, []))
+        if n == 0:
+            continue
+        bc, idx = tot["SQ_LDS_BANK_CONFLICT"], tot["SQ_LDS_IDX_ACTIVE"]
+        rate = bc / (idx - bc) if idx > bc else float("nan")
+        share = tot["SQ_ACTIVE_INST_LDS"] / tot["SQ_WAVE_CYCLES"] if tot["SQ_WAVE_CYCLES"] else float("nan")
+        lds_bytes = 64.0 * (tb["SQ_INSTS_LDS_LOAD_BANDWIDTH"] + tb["SQ_INSTS_LDS_STORE_BANDWIDTH"] +
+                            tb["SQ_INSTS_LDS_ATOMIC_BANDWIDTH"])
+        ms = times.get(k, 0.0) / 1e6
+        tbs = lds_bytes / (ms / 1e3) / 1e12 if ms > 0 else float("nan")
+        lines.append(f"{k:<18}{n:>6}{tot['SQ_INSTS_LDS']:>12.4g}{rate:>15.3f}{share:>11.3f}"
+                     f"{lds_bytes / 1e9:>9.2f}{ms:>9.2f}{tbs:>10.2f}{tbs / LDS_PEAK_TBS:>9.1%}")
+    text = "\n".join(lines) + "\n"
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -157,6 +201,15 @@ def main(argv=None) -> int:
     p.add_argument("--cmd", default="")
     p.add_argument("--out", default="")
     p.set_defaults(fn=cmd_traffic)
+    p = sub.add_parser("lds")
+    p.add_argument("--conflicts", required=True, help="counter run of LDS_CONFLICT_COUNTERS")
+    p.add_argument("--bytes", required=True, help="counter run of LDS_BYTE_COUNTERS")
+    p.add_argument("--trace", required=True, help="kernel-trace run of the same program")
+    p.add_argument("--kernels", default="k_peel_dense,k_fd_peel,k_count_big,k_peel_bitmap,k_count_small,k_peel_wave")
+    p.add_argument("--workload", default="cl-10m")
+    p.add_argument("--cmd", default="")
+    p.add_argument("--out", default="")
+    p.set_defaults(fn=cmd_lds)
     args = ap.parse_args(argv)
     return args.fn(args)
 
