@@ -86,8 +86,9 @@ typedef struct {
                         a vertex of degree d with w wedges in its 2-hop
                         neighbourhood is updated by the dense key-range
                         kernel when w > tune[1] and w > k * bits(d) /
-                        tune[0] (bits(d) = 2, 4, 8, 16 for d <= 3, 15, 255,
-                        65535; k = ids below the largest live one), and one
+                        tune[0] (bits(d) = 2, 4, 8, 16, 32 for d <= 3, 15,
+                        255, 65535, above; k = ids below the largest live
+                        one), and one
                         list tile of such counters fits the LDS, else by a
                         per-vertex kernel;
                         tune[0]: 0 = 1024; tune[1]: 0 = 2048;

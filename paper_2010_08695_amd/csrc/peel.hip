@@ -21,7 +21,7 @@
 //   * bitmap path: one workgroup per vertex, one LDS bit per key of a key
 //     tile, keys reached again go to an LDS table of repeat counts;
 //   * dense path: 2-hop neighbourhoods that cover a large share of the key
-//     space; one small workgroup per (vertex, key tile) with an 8- or 16-bit
+//     space; one workgroup per (vertex, key tiles) with a 2- to 32-bit
 //     counter per key, so a heavy vertex is spread over many workgroups.
 // All lists of the other side are sorted, so the part of N_v inside a key
 // tile is a contiguous run whose bounds come from a per-list table.
@@ -166,8 +166,9 @@ __global__ void k_wproxy(DevGraph g, const int32_t* __restrict__ deg_b, int64_t*
 // above that the dense kernel, unless its counter bytes (n_a * bits / 8,
 // bits from the degree so that c(u, w) <= d_u fits) are large against the
 // wedges (w <= n_a * bits / dense_div), or one table tile of its counters
-// does not fit the workgroup's LDS (sides of more than 64M keys).  With 16-bit
-// counters an item covers one list tile, so every pass stages all of u's
+// does not fit the workgroup's LDS (16-bit counters on sides of more than
+// 64M keys, 32-bit ones above 8M keys).  With 16- or 32-bit counters an item
+// covers one list tile, so every pass stages all of u's
 // neighbours again: such a vertex takes the dense path only when its wedges
 // are at least kDense16Stage times its degree times the passes, or when they
 // are more than one bitmap workgroup takes without spilling (late hubs whose
@@ -727,6 +728,7 @@ k_peel_bitmap(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t nt
 // every such field is set in the result.
 template <int BITS>
 __device__ inline uint32_t ge2_mask(uint32_t x) {
+    if (BITS == 32) return x >= 2 ? 0x80000000u : 0u;
     if (BITS == 2) return x & 0xaaaaaaaau;
     if (BITS == 4) {
         const uint32_t t = x & 0xeeeeeeeeu;
@@ -751,7 +753,7 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
                                   Stage<kDenseThreads>& S, const CdApply& ap, PeelCounters& pc) {
     constexpr int NT = kDenseThreads;
     constexpr int PER_WORD = 32 / BITS;          // counters per 32-bit word
-    constexpr uint32_t FMASK = BITS == 16 ? 0xffffu : ((1u << BITS) - 1);
+    constexpr uint32_t FMASK = BITS == 32 ? 0xffffffffu : BITS == 16 ? 0xffffu : ((1u << (BITS % 32)) - 1);
     constexpr int32_t kStageWords = 4 * kWave;  // one quad per lane of the wave
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -847,6 +849,15 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
                     atomic_add_i64(&ap.supp[k2], -choose2(c2v));
                     ++pc.pairs;
                 }
+            } else if (has != 0 && BITS == 32) {
+                // 32-bit counts do not fit the window's 16-bit field: each
+                // lane applies its own quad (consecutive keys across lanes)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (xs[q] >= 2) {
+                        atomic_add_i64(&ap.supp[klo + w4 * 4 + q], -choose2((int64_t)xs[q]));
+                        ++pc.pairs;
+                    }
             } else if (has != 0) {
                 // denser: stage the pairs through the quad window
                 uint32_t* win = reinterpret_cast<uint32_t*>(cnt4 + (w4 - lane));
@@ -899,7 +910,7 @@ struct DensePlan {
     int32_t gl[kDenseKinds], gh[kDenseKinds], ngl[kDenseKinds], ngh[kDenseKinds], np[kDenseKinds];
 };
 
-constexpr int kDenseOrder[kDenseKinds] = {3, 2, 1, 0};  // kinds of 16, 8, 4, 2 bits
+constexpr int kDenseOrder[kDenseKinds] = {4, 3, 2, 1, 0};  // kinds of 32, 16, 8, 4, 2 bits
 
 // One launch for every dense vertex of the round, whatever its counter
 // width: a single work queue, one tail.  g_max[kind]: widest light item
@@ -981,6 +992,7 @@ k_peel_dense(DevGraph g, const int32_t* __restrict__ tb, int32_t tk, int32_t ntt
             t_end = min(ntk, t_begin + gpass * pl.np[o]);
         }
         switch (k) {
+            case 4: dense_item<32>(g, tb, tk, ntt, u, t_begin, t_end, gpass, cnt, S, ap, pc); break;
             case 3: dense_item<16>(g, tb, tk, ntt, u, t_begin, t_end, gpass, cnt, S, ap, pc); break;
             case 2: dense_item<8>(g, tb, tk, ntt, u, t_begin, t_end, gpass, cnt, S, ap, pc); break;
             case 1: dense_item<4>(g, tb, tk, ntt, u, t_begin, t_end, gpass, cnt, S, ap, pc); break;

@@ -34,9 +34,9 @@ constexpr int kUnit = 128;                 // consecutive list entries per trave
 constexpr int kDenseThreads = 512;         // threads of the dense (vertex, key range) kernel
 constexpr int kDenseLdsBytes = 65536;      // counter bytes per dense workgroup (two per CU)
 // Update bins: wave path, bitmap path, and the dense path per counter width
-// (2, 4, 8, 16 bits) split into light and heavy vertices; a heavy vertex is
-// cut into kHeavySplit times more (smaller) work items.
-constexpr int kDenseKinds = 4;
+// (2, 4, 8, 16, 32 bits) split into light and heavy vertices; a heavy vertex
+// is cut into kHeavySplit times more (smaller) work items.
+constexpr int kDenseKinds = 5;
 constexpr int kBins = 2 + 2 * kDenseKinds;
 constexpr int kBinWave = 0, kBinBitmap = 1;
 constexpr int kDefaultDenseDiv = 1024;     // dense needs w[u] > n * bits / div (tip_opts.tune[0])
@@ -55,9 +55,11 @@ constexpr int64_t kDefaultCompactPermille = 125;
 // Counter width (bits) of the dense kernel for a vertex of degree d: c(u, w)
 // <= d_u must fit; 0 = too wide for the dense kernel.
 __host__ __device__ inline int dense_bits(int64_t d) {
-    return d <= 3 ? 2 : d <= 15 ? 4 : d <= 255 ? 8 : d <= 65535 ? 16 : 0;
+    return d <= 3 ? 2 : d <= 15 ? 4 : d <= 255 ? 8 : d <= 65535 ? 16 : d <= INT32_MAX ? 32 : 0;
 }
-__host__ __device__ inline int dense_kind(int bits) { return bits == 2 ? 0 : bits == 4 ? 1 : bits == 8 ? 2 : 3; }
+__host__ __device__ inline int dense_kind(int bits) {
+    return bits == 2 ? 0 : bits == 4 ? 1 : bits == 8 ? 2 : bits == 16 ? 3 : 4;
+}
 __host__ __device__ inline int dense_bin_of_kind(int kind, bool heavy) { return 2 + 2 * kind + (heavy ? 1 : 0); }
 __host__ __device__ inline int dense_bin(int bits, bool heavy) { return dense_bin_of_kind(dense_kind(bits), heavy); }
 

@@ -349,3 +349,16 @@ def test_huc_recount_changes_nothing(gpu_lib, P):
     np.testing.assert_array_equal(tip.decompose(g, 1, tune=[0, 0, 0, 1]), oracle.bup(g, 1)[0])
     k = gg.complete_bipartite(30, 20)
     np.testing.assert_array_equal(tip.decompose(k, 0, tune=[0, 0, 0, 1]), np.full(30, 29 * comb(20, 2)))
+
+
+def test_hubs_above_sixteen_bit_counts(gpu_lib):
+    """Vertices of degree above 65,535 share more than 65,535 neighbours with
+    others, so the dense path counts them with 32-bit counters.  K_{2,70000}
+    (theta = C(70000, 2) for both U vertices, closed form), and a Chung-Lu
+    graph whose V side has three hubs of degree about 82K, peeled on V and
+    checked against the oracle."""
+    k = gg.complete_bipartite(2, 70000)
+    np.testing.assert_array_equal(tip.decompose(k, 0), np.full(2, comb(70000, 2)))
+    g = gg.chung_lu(200000, 300, 1_000_000, 2.5, 1.8, seed=61, cap_v=1.5e5)
+    assert (np.bincount(g.ev, minlength=g.n_v) > 65535).sum() == 3
+    np.testing.assert_array_equal(tip.decompose(g, 1), oracle.bup(g, 1)[0])
