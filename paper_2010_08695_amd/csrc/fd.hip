@@ -113,6 +113,8 @@ __global__ void k_fd_reset_board(FdBoard* b) {
 // LDS of the fine-grained kernel.  The per-wave hash tables (light peeled
 // vertices) and the bitmap + repeat table (heavy ones) are used in separate
 // phases of a level and share storage; both are all zero between uses.
+constexpr int kFdHeavyPre = 512;  // heavy vertices of a level whose rows are loaded together
+
 struct FdLds {
     union Shared {
         struct {
@@ -129,6 +131,8 @@ struct FdLds {
     int32_t spill_n;
     int32_t flag;
     int32_t wave_head;   // next per-wave update of the level
+    int64_t hx_off[kFdHeavyPre];  // row offset and degree of a level's heavy vertices
+    int32_t hx_deg[kFdHeavyPre];
 };
 
 // Next entry of the level's per-wave update list for the calling wavefront.
@@ -385,14 +389,13 @@ __device__ inline void fd_update_wave_dense(const DevGraph& g, const FdBuffers& 
 // per key of a kFdBits-key tile, repeats in the LDS table (spilling to HBM).
 template <class St>
 __device__ inline void fd_update_heavy(const DevGraph& g, const FdBuffers& fb, FdLds& L, const Spill& sp,
-                                       int32_t x, int32_t n_i, const St& st, unsigned long long& wedges,
-                                       unsigned long long& pairs, unsigned long long& spills) {
+                                       int32_t x, int64_t e0, int64_t d, int32_t n_i, const St& st,
+                                       unsigned long long& wedges, unsigned long long& pairs,
+                                       unsigned long long& spills) {
     constexpr int NT = kFdThreads;
     constexpr int NW = NT / kWave;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const bool multi = n_i > kFdBits;
-    const int32_t ux = st.vtx(x);
-    const int64_t e0 = g.a_off[ux], d = g.a_off[ux + 1] - e0;
     for (int32_t klo = 0; klo < n_i; klo += kFdBits) {
         const int32_t khi = (int32_t)min<int64_t>(n_i, (int64_t)klo + kFdBits);
         const bool self_in = x >= klo && x < khi;
@@ -468,6 +471,32 @@ __device__ inline void fd_update_heavy(const DevGraph& g, const FdBuffers& fb, F
         for (int w = tid; w < words; w += NT) L.u.big.bm[w] = 0;
         for (int sl = tid; sl < kFdRep; sl += NT) L.u.big.rep[sl] = 0;
         if (tid == 0) L.spill_n = 0;
+        __syncthreads();
+    }
+}
+
+// The heavy vertices of a level, updated one after another by the whole
+// workgroup.  Their row offsets and degrees are loaded first, for up to
+// kFdHeavyPre of them in parallel, so that each update starts from its
+// neighbour runs instead of a chain of dependent loads.  All threads call,
+// after a barrier.
+template <class St, class T>
+__device__ inline void fd_heavy_level(const DevGraph& g, const FdBuffers& fb, FdLds& L, const Spill& sp,
+                                      const T* ph, int32_t n_heavy, int32_t n_i, const St& st,
+                                      unsigned long long& wedges, unsigned long long& pairs,
+                                      unsigned long long& spills) {
+    for (int32_t q0 = 0; q0 < n_heavy; q0 += kFdHeavyPre) {
+        const int32_t nq = min(kFdHeavyPre, n_heavy - q0);
+        for (int32_t q = threadIdx.x; q < nq; q += kFdThreads) {
+            const int32_t ux = st.vtx((int32_t)ph[q0 + q]);
+            const int64_t a = g.a_off[ux];
+            L.hx_off[q] = a;
+            L.hx_deg[q] = (int32_t)(g.a_off[ux + 1] - a);
+        }
+        __syncthreads();
+        for (int32_t q = 0; q < nq; ++q)
+            fd_update_heavy(g, fb, L, sp, (int32_t)ph[q0 + q], L.hx_off[q], (int64_t)L.hx_deg[q], n_i, st, wedges,
+                            pairs, spills);
         __syncthreads();
     }
 }
@@ -614,7 +643,7 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
             }
         }
         __syncthreads();
-        for (int32_t q = 0; q < n_heavy; ++q) fd_update_heavy(g, fb, L, sp, ph[q], n_i, st, wedges, pairs, spills);
+        fd_heavy_level(g, fb, L, sp, ph, n_heavy, n_i, st, wedges, pairs, spills);
         int32_t* tmp = lc;
         lc = ln;
         ln = tmp;
@@ -709,7 +738,7 @@ __device__ inline void fd_peel_lds(const DevGraph& g, const FdBuffers& fb, const
         for (int32_t q = fd_next_wave_item(L); q < n_light; q = fd_next_wave_item(L))
             fd_update_wave_dense(g, fb, L, wcnt, (int32_t)S.pl[q], n_i, st, wedges, pairs);
         __syncthreads();
-        for (int32_t q = 0; q < n_heavy; ++q) fd_update_heavy(g, fb, L, sp, (int32_t)S.ph[q], n_i, st, wedges, pairs, spills);
+        fd_heavy_level(g, fb, L, sp, S.ph, n_heavy, n_i, st, wedges, pairs, spills);
         __syncthreads();
         mn = min<int64_t>(bmin, (int64_t)S.upd_min);
         uint16_t* tmp = lc;
