@@ -143,7 +143,7 @@ const Ctl& read_ctl(const Work& w, hipStream_t s) {
 // rounds take all their state from the device control block, and rounds
 // past the end of a range do nothing, so the host reads one flag per replay
 // instead of one per round.
-constexpr int kRoundsPerGraph = 4;
+constexpr int kRoundsPerGraph = 3;
 
 struct RoundGraph {
     hipStream_t cs = nullptr;
