@@ -68,6 +68,18 @@ def load_traffic(workload: str):
     return rec.get("bytes_per_launch")
 
 
+def host_cpu_model() -> str:
+    """The host CPU's model name from /proc/cpuinfo ("unknown" elsewhere)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(g, seconds: float) -> dict:
     """The oracle's 2-hop aggregation (the update step of bottom-up peeling)
     on random U vertices of the same graph, sized to ~`seconds` of CPU work."""
@@ -98,6 +110,7 @@ def cpu_baseline(g, seconds: float) -> dict:
     dt = time.perf_counter() - t0 - t_build
     wedges = int(per_u[order[:k]].sum())
     return {"value": wedges / dt, "unit": "wedges/s", "cores": 1, "kind": "oracle",
+            "host": {"cpu": host_cpu_model(), "nproc": os.cpu_count()},
             "sample": (f"oracle 2-hop aggregation (the update step of sequential bottom-up peeling) for {k} "
                        f"random U vertices of {g.name}: {wedges} wedges in {dt:.1f} s on one host core; "
                        f"adjacency build ({t_build:.1f} s) excluded; heap upkeep of the full oracle not "
