@@ -6,6 +6,7 @@ product library never imports it.
 
 * ``count(g)``            per-vertex butterfly counts of both sides + total
                           (plain 2-hop definition, notation table of the paper)
+* ``count_side(g, side)`` per-vertex butterfly counts of one side only
 * ``bup(g, side)``        tip numbers by sequential bottom-up peeling (Alg. 2)
 * ``support_in(g, side, member, query)``
                           f_x(S) for sampled vertices, for property checks
@@ -54,6 +55,8 @@ def _load(path: str | None = None):
     p = ctypes.c_void_p
     lib.oracle_count.argtypes = [i32, i32, i64, p, p, p, p, p]
     lib.oracle_count.restype = ctypes.c_int
+    lib.oracle_count_side.argtypes = [i32, i32, i64, p, p, i32, p]
+    lib.oracle_count_side.restype = ctypes.c_int
     lib.oracle_bup.argtypes = [i32, i32, i64, p, p, i32, p, p, p]
     lib.oracle_bup.restype = ctypes.c_int
     lib.oracle_support_in.argtypes = [i32, i32, i64, p, p, i32, p, p, i64, p]
@@ -84,6 +87,17 @@ def count(g, lib=None):
     if rc != 0:
         raise ValueError("oracle_count: invalid graph")
     return bu, bv, int(tot[0])
+
+
+def count_side(g, side: int, lib=None) -> np.ndarray:
+    """Per-vertex butterfly counts of one side: int64[n_u] or int64[n_v]."""
+    lib = lib or _load()
+    eu, ev = _edges(g)
+    out = np.zeros(g.n_u if side == 0 else g.n_v, np.int64)
+    rc = lib.oracle_count_side(g.n_u, g.n_v, g.m, _ptr(eu), _ptr(ev), side, _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle_count_side: invalid graph or side")
+    return out
 
 
 def bup(g, side: int = 0, lib=None):

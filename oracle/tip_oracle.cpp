@@ -13,9 +13,10 @@
 //     trick of Alg. 1 is deliberately NOT used here, so the oracle stays
 //     independent of the GPU's counting method.
 //   * tip numbers by sequential bottom-up peeling (Alg. 2, BUP, Section 2.2):
-//     repeatedly take the remaining vertex of minimum support, record its
-//     support as its tip number, and lower every remaining vertex u' by the
-//     butterflies it shares with it, never below the recorded value.
+//     vertices leave the graph in order of least support; each gets the
+//     support it has when it leaves (never less than any earlier tip number)
+//     as its tip number, and the vertices that remain lose the butterflies
+//     they shared with it.
 //   * f_u(S): the butterflies of u inside the subgraph induced on S and the
 //     whole other side, for sampled property checks at any size; also for
 //     the three sets a tip-number array defines around u at once (all of the
@@ -24,8 +25,8 @@
 // Readings of the paper taken here:
 //   * Vertices already peeled are not updated (the update has no effect on
 //     them; Lemma 2 makes the same remark for the parallel case).
-//   * Ties in the minimum support are broken by vertex id; tip numbers do not
-//     depend on the tie order.
+//   * Among vertices of equal least support, the one filed first leaves
+//     first; tip numbers do not depend on that order.
 //   * Duplicate input edges are merged (the datasets are simple graphs).
 //   * All counts are exact 64-bit integers.
 //
@@ -33,8 +34,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
-#include <functional>
-#include <queue>
+#include <map>
 #include <utility>
 #include <vector>
 
@@ -121,11 +121,38 @@ int oracle_count(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu, const i
     return 0;
 }
 
-// Tip numbers of side `side` (0 = U, 1 = V) by bottom-up peeling, Alg. 2.
+// Per-vertex butterfly counts of side `side` only (0 = U, 1 = V): the same
+// plain definition as oracle_count, for graphs whose other side would take
+// far longer to count.  Returns 0, or -1 on an invalid argument.
+int oracle_count_side(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu, const int32_t* ev,
+                      int32_t side, int64_t* bfly) {
+    if (n_u < 0 || n_v < 0 || m < 0 || (m > 0 && (!eu || !ev)) || !bfly) return -1;
+    if (side != 0 && side != 1) return -1;
+    Adjacency g;
+    if (!build(n_u, n_v, m, eu, ev, side, g)) return -1;
+    count_side(g, bfly);
+    return 0;
+}
+
+// Tip numbers of side `side` (0 = U, 1 = V) by sequential bottom-up peeling
+// (Alg. 2, Section 2.2).
+//
+// The vertices of the side wait in a bucket queue keyed by support: `queue`
+// maps a support value to the vertices filed under it.  An entry is stale
+// once its vertex has left the graph or been re-filed under a smaller value;
+// only entries whose key equals the vertex's present support count.  The
+// smallest key is the current level.  Vertices at the level leave the graph
+// one at a time, each with tip number = level.  When x leaves, every vertex
+// w that remains loses the butterflies it shared with x: C(co[w], 2), where
+// co[w] is the co-degree |N_x intersect N_w| gathered by walking x's 2-hop
+// neighbourhood.  A support never drops below the level (the tip number just
+// assigned), so a vertex lowered that far joins the level's own bag and
+// leaves later in the same level.
+//
 //   theta  [n_side]  output tip numbers
-//   order  [n_side]  optional: vertices in the order they were peeled
-//   wedges           optional: number of (u, v, u') triples with u' != u that
-//                    the update routine visited
+//   order  [n_side]  optional: vertices in the order they left the graph
+//   wedges           optional: number of (x, y, w) paths with w != x walked
+//                    while removing vertices
 // Returns 0, or -1 on an invalid argument.
 int oracle_bup(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu, const int32_t* ev,
                int32_t side, int64_t* theta, int32_t* order, int64_t* wedges) {
@@ -135,68 +162,71 @@ int oracle_bup(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu, const int
     if (!build(n_u, n_v, m, eu, ev, side, g)) return -1;
     const int32_t n = g.n_a;
 
-    // Initial count (Alg. 2 first line).
-    std::vector<int64_t> support(n);
-    count_side(g, support.data());
+    // every vertex starts with its butterfly count in the whole graph
+    std::vector<int64_t> supp(n);
+    count_side(g, supp.data());
 
-    // Minimum-support retrieval: a binary heap of (support, id) entries; an
-    // entry is current only if it matches the vertex's present support.
-    using Entry = std::pair<int64_t, int32_t>;
-    std::priority_queue<Entry, std::vector<Entry>, std::greater<Entry>> heap;
-    for (int32_t x = 0; x < n; ++x) heap.emplace(support[x], x);
+    std::map<int64_t, std::vector<int32_t>> queue;
+    for (int32_t x = 0; x < n; ++x) queue[supp[x]].push_back(x);
+    int64_t filed = n;  // entries held by `queue`, stale ones included
 
-    std::vector<char> remaining(n, 1);
-    std::vector<int32_t> wdg_arr(n, 0);
-    std::vector<int32_t> touched;
-    int64_t visited = 0;
-    int32_t peeled = 0;
+    std::vector<char> gone(n, 0);
+    std::vector<int32_t> co(n, 0);
+    std::vector<int32_t> met;  // vertices with co > 0 for the vertex leaving
+    int64_t walked = 0;
+    int32_t left_graph = 0;
 
-    while (!heap.empty()) {
-        Entry top = heap.top();
-        heap.pop();
-        const int32_t u = top.second;
-        if (!remaining[u] || top.first != support[u]) continue;  // stale entry
-        // theta_u <- support_u; remove u from U
-        const int64_t theta_u = support[u];
-        theta[u] = theta_u;
-        remaining[u] = 0;
-        if (order) order[peeled] = u;
-        ++peeled;
+    while (!queue.empty()) {
+        const int64_t level = queue.begin()->first;
+        std::vector<int32_t> bag = std::move(queue.begin()->second);
+        queue.erase(queue.begin());
+        filed -= static_cast<int64_t>(bag.size());
+        for (size_t i = 0; i < bag.size(); ++i) {
+            const int32_t x = bag[i];
+            if (gone[x] || supp[x] != level) continue;  // stale entry
+            gone[x] = 1;
+            theta[x] = level;
+            if (order) order[left_graph] = x;
+            ++left_graph;
 
-        // update(u, theta_u): aggregate wedge counts over the 2-hop
-        // neighbourhood of u ...
-        touched.clear();
-        for (int32_t v : g.a_to_b[u])
-            for (int32_t w : g.b_to_a[v]) {
-                if (w == u) continue;
-                ++visited;
-                if (wdg_arr[w] == 0) touched.push_back(w);
-                ++wdg_arr[w];
+            met.clear();
+            for (int32_t y : g.a_to_b[x])
+                for (int32_t w : g.b_to_a[y]) {
+                    if (w == x) continue;
+                    ++walked;
+                    if (co[w]++ == 0) met.push_back(w);
+                }
+            for (int32_t w : met) {
+                const int64_t shared = choose2(co[w]);
+                co[w] = 0;
+                if (gone[w] || shared == 0) continue;
+                const int64_t lowered = std::max(level, supp[w] - shared);
+                if (lowered == supp[w]) continue;
+                supp[w] = lowered;
+                if (lowered == level) {
+                    bag.push_back(w);
+                } else {
+                    queue[lowered].push_back(w);
+                    ++filed;
+                }
             }
-        // ... then lower each remaining neighbour by the shared butterflies,
-        // never below theta_u.
-        for (int32_t w : touched) {
-            const int64_t shared = choose2(wdg_arr[w]);
-            wdg_arr[w] = 0;
-            if (!remaining[w] || shared == 0) continue;
-            const int64_t lowered = std::max(theta_u, support[w] - shared);
-            if (lowered != support[w]) {
-                support[w] = lowered;
-                heap.emplace(lowered, w);
+
+            // Bound the queue's memory: once stale entries dominate, file
+            // every remaining vertex above the level afresh (those at the
+            // level are already in the bag).
+            const int64_t remaining = static_cast<int64_t>(n) - left_graph;
+            if (filed > 4 * remaining + 4096) {
+                queue.clear();
+                filed = 0;
+                for (int32_t z = 0; z < n; ++z)
+                    if (!gone[z] && supp[z] > level) {
+                        queue[supp[z]].push_back(z);
+                        ++filed;
+                    }
             }
-        }
-        // Keep the heap's memory bounded: once stale entries dominate,
-        // rebuild it with one current entry per remaining vertex.
-        const int64_t left = static_cast<int64_t>(n) - peeled;
-        if (static_cast<int64_t>(heap.size()) > 4 * left + 4096) {
-            std::vector<Entry> fresh;
-            fresh.reserve(static_cast<size_t>(left));
-            for (int32_t x = 0; x < n; ++x)
-                if (remaining[x]) fresh.emplace_back(support[x], x);
-            heap = decltype(heap)(decltype(heap)::value_compare(), std::move(fresh));
         }
     }
-    if (wedges) *wedges = visited;
+    if (wedges) *wedges = walked;
     return 0;
 }
 

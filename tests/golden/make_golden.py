@@ -7,12 +7,24 @@ the GPU tests can check full-size results exactly without re-running a
 minutes-long oracle.
 
     python tests/golden/make_golden.py plain-small cl-1m cl-10m
+    python tests/golden/make_golden.py batch-64 [--procs 6]
+    python tests/golden/make_golden.py cl-100m-skew     # V side only
+
+``batch-64`` holds one record per graph of the 64-graph batch workload (U
+side), computed in parallel, one oracle per process.  ``cl-100m-skew``
+holds the V side only: the oracle's U side walks about 9e12 wedges there,
+far beyond what the CPU can do.  Every timing is stored with the date, the
+host's CPU model and the number of cores the oracle used (one).
 """
 from __future__ import annotations
 
+import argparse
+import datetime
 import hashlib
 import json
+import multiprocessing
 import os
+import platform
 import sys
 import time
 
@@ -37,16 +49,41 @@ def sample(a: np.ndarray, k: int = 64, seed: int = 0) -> dict:
     return {"index": idx.tolist(), "value": a[idx].tolist()}
 
 
-def make(name: str, sides=(0, 1)) -> dict:
-    g = graphgen.config_graph(name)
+def host() -> dict:
+    """Where and when the oracle ran: date, CPU model, cores it used."""
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"date": datetime.date.today().isoformat(), "cpu": cpu, "machine": platform.machine(),
+            "nproc": os.cpu_count(), "cores_used": 1}
+
+
+def make(name: str, sides=(0, 1), g=None) -> dict:
+    g = g if g is not None else graphgen.config_graph(name)
     rec = {"config": name, "graph_sha256": graphgen.graph_sha256(g),
-           "n_u": g.n_u, "n_v": g.n_v, "m": g.m, "source": "oracle/tip_oracle.cpp"}
+           "n_u": g.n_u, "n_v": g.n_v, "m": g.m, "source": "oracle/tip_oracle.cpp", "host": host()}
     t0 = time.time()
-    bu, bv, tot = oracle.count(g)
-    rec["count"] = {"total": tot, "sum_u": int(bu.sum()), "sum_v": int(bv.sum()),
-                    "sha256_u": digest(bu), "sha256_v": digest(bv),
-                    "sample_u": sample(bu, seed=1), "sample_v": sample(bv, seed=2),
-                    "seconds": round(time.time() - t0, 2)}
+    if tuple(sides) == (0, 1):
+        bu, bv, tot = oracle.count(g)
+        rec["count"] = {"total": tot, "sum_u": int(bu.sum()), "sum_v": int(bv.sum()),
+                        "sha256_u": digest(bu), "sha256_v": digest(bv),
+                        "sample_u": sample(bu, seed=1), "sample_v": sample(bv, seed=2)}
+    else:
+        # one side only: its counts, and the total they imply
+        rec["count"] = {}
+        for side in sides:
+            b = oracle.count_side(g, side)
+            k = "uv"[side]
+            rec["count"].update({f"sum_{k}": int(b.sum()), f"sha256_{k}": digest(b),
+                                 f"sample_{k}": sample(b, seed=1 + side)})
+            rec["count"]["total"] = int(b.sum()) // 2
+    rec["count"]["seconds"] = round(time.time() - t0, 2)
     print(name, "count", rec["count"]["seconds"], "s", flush=True)
     for side in sides:
         t0 = time.time()
@@ -64,10 +101,38 @@ def make(name: str, sides=(0, 1)) -> dict:
     return rec
 
 
+def _batch_one(p: dict) -> dict:
+    g = graphgen.batch_graph(p)
+    rec = make(g.name, sides=(0,), g=g)
+    rec["params"] = p
+    return rec
+
+
+def make_batch(count: int, procs: int) -> dict:
+    params = graphgen.batch_params(count)
+    # largest graphs first, so the pool's tail is short
+    order = sorted(range(count), key=lambda i: -params[i]["m_t"])
+    with multiprocessing.Pool(procs) as pool:
+        recs = pool.map(_batch_one, [params[i] for i in order], chunksize=1)
+    graphs = [None] * count
+    for i, r in zip(order, recs):
+        graphs[i] = r
+    return {"config": f"batch-{count}", "source": "oracle/tip_oracle.cpp", "host": host(),
+            "graphs": graphs}
+
+
 def main(argv):
-    names = argv or ["plain-small", "cl-1m"]
-    for name in names:
-        rec = make(name)
+    ap = argparse.ArgumentParser()
+    ap.add_argument("names", nargs="*", default=["plain-small", "cl-1m"])
+    ap.add_argument("--procs", type=int, default=6)
+    args = ap.parse_args(argv)
+    for name in args.names:
+        if name.startswith("batch-"):
+            rec = make_batch(int(name.split("-")[1]), args.procs)
+        elif name == "cl-100m-skew":
+            rec = make(name, sides=(1,))
+        else:
+            rec = make(name)
         path = os.path.join(HERE, f"{name}.json")
         with open(path, "w") as f:
             json.dump(rec, f, indent=1)

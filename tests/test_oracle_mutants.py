@@ -28,13 +28,17 @@ MUTANTS = {
     "count_self_pair": ("if (w > x) {", "if (w >= x) {"),
     "count_drop_far_end": ("            out[w] += b;\n", ""),
     "choose2_sign": ("return c * (c - 1) / 2;", "return c * (c + 1) / 2;"),
-    "bup_no_cap": ("std::max(theta_u, support[w] - shared)", "(support[w] - shared)"),
-    "bup_linear_shared": ("const int64_t shared = choose2(wdg_arr[w]);",
-                          "const int64_t shared = wdg_arr[w] > 1 ? wdg_arr[w] : 0;"),
-    "bup_max_heap": ("std::priority_queue<Entry, std::vector<Entry>, std::greater<Entry>> heap;",
-                     "std::priority_queue<Entry, std::vector<Entry>, std::less<Entry>> heap;"),
-    "bup_counts_self_wedge": ("if (w == u) continue;\n                ++visited;",
-                              "++visited;\n                if (w == u) continue;"),
+    "bup_no_cap": ("std::max(level, supp[w] - shared)", "(supp[w] - shared)"),
+    "bup_linear_shared": ("const int64_t shared = choose2(co[w]);",
+                          "const int64_t shared = co[w] > 1 ? co[w] : 0;"),
+    "bup_largest_level_first": ("const int64_t level = queue.begin()->first;\n"
+                                "        std::vector<int32_t> bag = std::move(queue.begin()->second);\n"
+                                "        queue.erase(queue.begin());",
+                                "const int64_t level = queue.rbegin()->first;\n"
+                                "        std::vector<int32_t> bag = std::move(queue.rbegin()->second);\n"
+                                "        queue.erase(std::prev(queue.end()));"),
+    "bup_counts_self_wedge": ("if (w == x) continue;\n                    ++walked;",
+                              "++walked;\n                    if (w == x) continue;"),
     "support_in_ignores_member": ("if (w != x && member[w]) {", "if (w != x) {"),
     "support_levels_ge_strict": ("if (theta[w] >= theta[x]) ge += f;", "if (theta[w] > theta[x]) ge += f;"),
     "support_levels_gt_loose": ("if (theta[w] > theta[x]) gt += f;", "if (theta[w] >= theta[x]) gt += f;"),
