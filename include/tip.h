@@ -38,7 +38,10 @@ enum {
     TIP_EINVAL = -1,    /* NULL required pointer, id out of range, bad side, negative or too large size */
     TIP_ENOMEM = -2,    /* device or host allocation failed, or the workspace is too small */
     TIP_EDEVICE = -3,   /* a HIP runtime error; tip_last_error() holds the HIP message */
-    TIP_EOVERFLOW = -4, /* counts could exceed INT64_MAX (checked before counting) */
+    TIP_EOVERFLOW = -4, /* reserved: no call returns it.  With m <= 2^31 - 1 no count can
+                           overflow: the counts of either side sum to at most
+                           1/2 * sum over edges (x, y) of (d_x - 1)(d_y - 1) < m^2 / 2 < 2^61
+                           (c(x, w) <= d_x bounds every shared-butterfly term C(c, 2)) */
     TIP_EBUSY = -5      /* reserved */
 };
 
@@ -76,6 +79,12 @@ typedef struct {
  * section; on by default).  Same results, more wedges traversed. */
 #define TIP_FLAG_NO_COMPACT 8
 
+/* TIP_FLAG_OPTS_PER_GRAPH (tip_decompose_batch only): `opt` points to n
+ * tip_opts, one per graph, instead of one for all; graph k runs with
+ * opt[k].P and opt[k].tune (for example each graph's autotuned values).
+ * Every opt[k].flags must be equal and carry this bit. */
+#define TIP_FLAG_OPTS_PER_GRAPH 16
+
 /* Options.  Zero-initialised means defaults. */
 typedef struct {
     int32_t P;       /* number of tip-number ranges of the coarse-grained step
@@ -105,7 +114,14 @@ typedef struct {
                         GPU a re-count costs about nine times a peel per
                         wedge), 100 = the rule of the paper; the results do
                         not change;
-                        tune[0..3] >= 0; tune[4..7] reserved, must be 0 */
+                        tune[4..6]: the fine-grained step's help board
+                        (Alg. 4 subsets large enough let idle workgroups
+                        take their per-wave updates): tune[4] updates taken
+                        per claim (0 = 16, at most 2^20), tune[5] fewest
+                        updates of a level worth publishing (0 = 256),
+                        tune[6] smallest subset that opens a slot (0 =
+                        4096); the results do not change;
+                        tune[0..6] >= 0; tune[7] reserved, must be 0 */
 } tip_opts;
 
 /* Work and time accounting of one decomposition (NULL = not wanted). */

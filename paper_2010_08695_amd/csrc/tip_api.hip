@@ -39,7 +39,6 @@ struct Work {
     Ctl* ctl = nullptr;
     SpillArena spill;
     int64_t* total = nullptr;
-    double* ovf = nullptr;
 };
 
 int resident_workgroups() {
@@ -106,7 +105,6 @@ void plan(Arena& ar, int32_t n_a, int32_t n_b, int64_t m, int32_t P, int slots, 
     w.fb.board = ar.take<FdBoard>(1);
     w.ctl = ar.take<Ctl>(1);
     w.total = ar.take<int64_t>(2);
-    w.ovf = ar.take<double>(8);
     const int64_t keys = std::max<int64_t>(std::max(na, nb), 1);
     w.spill.stride = std::min<int64_t>(kBmBits, (keys + 63) & ~int64_t(63));
     w.spill.slots = slots;
@@ -189,43 +187,6 @@ struct Events {
     }
 };
 
-__global__ void k_overflow_terms(const int32_t* deg_a, int32_t n_a, const int32_t* deg_b, int32_t n_b, double* out) {
-    // out[0] = sum C(d_a, 2), out[1] = sum C(d_b, 2), out[2] = max d_a, out[3] = max d_b
-    double sa = 0, sb = 0;
-    int32_t ma = 0, mb = 0;
-    for (int64_t i = threadIdx.x; i < n_a; i += blockDim.x) {
-        const double d = deg_a[i];
-        sa += d * (d - 1) * 0.5;
-        ma = max(ma, deg_a[i]);
-    }
-    for (int64_t i = threadIdx.x; i < n_b; i += blockDim.x) {
-        const double d = deg_b[i];
-        sb += d * (d - 1) * 0.5;
-        mb = max(mb, deg_b[i]);
-    }
-    __shared__ double r0[1024], r1[1024];
-    __shared__ int32_t r2[1024], r3[1024];
-    r0[threadIdx.x] = sa;
-    r1[threadIdx.x] = sb;
-    r2[threadIdx.x] = ma;
-    r3[threadIdx.x] = mb;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double a = 0, b = 0;
-        int32_t x = 0, y = 0;
-        for (int i = 0; i < (int)blockDim.x; ++i) {
-            a += r0[i];
-            b += r1[i];
-            x = max(x, r2[i]);
-            y = max(y, r3[i]);
-        }
-        out[0] = a;
-        out[1] = b;
-        out[2] = x;
-        out[3] = y;
-    }
-}
-
 __global__ void k_sum_i64(const int64_t* a, int32_t n, int64_t* out) {
     __shared__ unsigned long long r[1024];
     unsigned long long s = 0;
@@ -237,22 +198,6 @@ __global__ void k_sum_i64(const int64_t* a, int32_t n, int64_t* out) {
         for (int i = 0; i < (int)blockDim.x; ++i) t += r[i];
         out[0] = (int64_t)t;
     }
-}
-
-// Butterfly-count bound: every butterfly is a pair of neighbours of one of
-// its U vertices plus another common neighbour of that pair, counted from
-// both U vertices, so B <= 1/2 * sum_u C(d_u, 2) * (max d_V - 1); likewise
-// from V.  Every per-vertex count and every per-side sum is at most 2B.
-bool counts_may_overflow(Work& w, hipStream_t s) {
-    k_overflow_terms<<<1, 1024, 0, s>>>(w.aux.deg_a, w.g.n_a, w.aux.deg_b, w.g.n_b, w.ovf);
-    TIP_HIP_TRY(hipGetLastError());
-    double h[4];
-    TIP_HIP_TRY(hipMemcpyAsync(h, w.ovf, sizeof(h), hipMemcpyDeviceToHost, s));
-    TIP_HIP_TRY(hipStreamSynchronize(s));
-    const double ba = 0.5 * h[0] * std::max(0.0, h[3] - 1.0);
-    const double bb = 0.5 * h[1] * std::max(0.0, h[2] - 1.0);
-    const double bound = std::min(ba, bb);
-    return 2.0 * bound * 1.0001 >= 9.2e18;
 }
 
 struct RunOut {
@@ -310,10 +255,10 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
         set_error("an edge endpoint id is out of range");
         return TIP_EINVAL;
     }
-    if (counts_may_overflow(w, s)) {
-        set_error("butterfly counts of this graph could exceed INT64_MAX");
-        return TIP_EOVERFLOW;
-    }
+    // No count can overflow: with c(x, w) <= d_x, the butterflies of x are at
+    // most (d_x - 1) / 2 * sum_{y in N_x} (d_y - 1), so either side's counts
+    // sum to at most 1/2 * sum over edges (x, y) of (d_x - 1)(d_y - 1) <
+    // m^2 / 2 < 2^61 for m < 2^31 (the largest m the boundary accepts).
     TIP_HIP_TRY(hipEventRecord(ev.e[1], s));
     const DevGraph& g = w.g;
     const int big_grid = w.spill.slots;
@@ -422,7 +367,7 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
         // Fine-grained decomposition (Alg. 4).
         if (fd_inline) {
             if (S > 0)
-                launch_fd(g, pb, w.fb, S, w.ctl, w.spill, big_grid, w.ib.keys2, w.ib.vals2, w.ib.hist,
+                launch_fd(g, pb, w.fb, S, w.ctl, tune, w.spill, big_grid, w.ib.keys2, w.ib.vals2, w.ib.hist,
                           w.ib.scan_tmp, w.ib.keys, w.ib.vals, s);
             TIP_HIP_TRY(hipEventRecord(ev.e[4], s));
         } else {
@@ -525,15 +470,19 @@ void check_edges(const tip_edges* g) {
     }
 }
 
-int32_t check_opts(const tip_opts* opt) {
+constexpr int32_t kKnownFlags =
+    TIP_FLAG_TIME_KERNELS | TIP_FLAG_NO_GRAPH | TIP_FLAG_BATCH_PLAIN | TIP_FLAG_NO_COMPACT | TIP_FLAG_OPTS_PER_GRAPH;
+
+int32_t check_opts(const tip_opts* opt, bool batch = false) {
     if (!opt) return kDefaultP;
     if (opt->P < 0 || opt->P > kMaxP) throw InvalidArg("P must be in [0, 65535]");
-    if (opt->flags & ~(TIP_FLAG_TIME_KERNELS | TIP_FLAG_NO_GRAPH | TIP_FLAG_BATCH_PLAIN | TIP_FLAG_NO_COMPACT))
-        throw InvalidArg("unknown flag bits");
-    for (int i = 0; i < 4; ++i)
-        if (opt->tune[i] < 0) throw InvalidArg("tune[0..3] must be >= 0");
-    for (int i = 4; i < 8; ++i)
-        if (opt->tune[i] != 0) throw InvalidArg("tune[4..7] must be 0");
+    if (opt->flags & ~kKnownFlags) throw InvalidArg("unknown flag bits");
+    if (!batch && (opt->flags & TIP_FLAG_OPTS_PER_GRAPH))
+        throw InvalidArg("TIP_FLAG_OPTS_PER_GRAPH is for tip_decompose_batch only");
+    for (int i = 0; i < 7; ++i)
+        if (opt->tune[i] < 0) throw InvalidArg("tune[0..6] must be >= 0");
+    if (opt->tune[4] > (1 << 20)) throw InvalidArg("tune[4] must be at most 2^20");
+    if (opt->tune[7] != 0) throw InvalidArg("tune[7] is reserved and must be 0");
     return opt->P == 0 ? kDefaultP : opt->P;
 }
 
@@ -543,6 +492,9 @@ Tune tune_of(const tip_opts* opt) {
     if (opt && opt->tune[1] > 0) t.bitmap_max = opt->tune[1];
     if (opt && opt->tune[2] > 0) t.compact_permille = opt->tune[2];
     if (opt) t.huc_pct = opt->tune[3];
+    if (opt && opt->tune[4] > 0) t.fd_help_chunk = opt->tune[4];
+    if (opt && opt->tune[5] > 0) t.fd_help_level_min = opt->tune[5];
+    if (opt && opt->tune[6] > 0) t.fd_help_min = opt->tune[6];
     if (opt && (opt->flags & TIP_FLAG_NO_COMPACT)) t.compact_permille = 0;
     return t;
 }
@@ -636,6 +588,8 @@ struct BatchItem {
     int32_t n_a = 0, n_b = 0;
     int64_t m = 0;
     bool a_is_u = true;
+    int32_t P = kDefaultP;
+    Tune tune;
     Work w;
     DeviceBuffer buf;
     RunState rs;
@@ -644,8 +598,10 @@ struct BatchItem {
     std::string err;
 };
 
-tip_status decompose_batched(int32_t n, const tip_edges* gs, const int32_t* sides, int64_t* const* thetas, int32_t P,
-                             int32_t flags, const Tune& tune, tip_stats* st) {
+// Graph k runs with Ps[k] ranges and tunes[k].
+tip_status decompose_batched(int32_t n, const tip_edges* gs, const int32_t* sides, int64_t* const* thetas,
+                             const std::vector<int32_t>& Ps, int32_t flags, const std::vector<Tune>& tunes,
+                             tip_stats* st) {
     if (n == 0) return TIP_OK;
     int dev = 0;
     TIP_HIP_TRY(hipGetDevice(&dev));
@@ -672,6 +628,9 @@ tip_status decompose_batched(int32_t n, const tip_edges* gs, const int32_t* side
             BatchItem& b = *it;
             try {
                 const tip_edges* g = &gs[k];
+                b.P = Ps[k];
+                b.tune = tunes[k];
+                const int32_t P = b.P;
                 b.a_is_u = sides[k] == TIP_SIDE_U;
                 b.n_a = b.a_is_u ? g->n_u : g->n_v;
                 b.n_b = b.a_is_u ? g->n_v : g->n_u;
@@ -693,7 +652,7 @@ tip_status decompose_batched(int32_t n, const tip_edges* gs, const int32_t* side
                     TIP_HIP_TRY(hipMemcpyAsync(d_b, b.a_is_u ? g->ev : g->eu, sizeof(int32_t) * b.m,
                                                hipMemcpyHostToDevice, s));
                 }
-                b.rc = run_front(b.w, d_a, d_b, b.n_a, b.n_b, b.m, b.a_is_u, P, flags, tune, true, false, b.rs, s);
+                b.rc = run_front(b.w, d_a, d_b, b.n_a, b.n_b, b.m, b.a_is_u, P, flags, b.tune, true, false, b.rs, s);
                 if (b.rc != TIP_OK) b.err = last_error();
                 TIP_HIP_TRY(hipStreamSynchronize(s));
             } catch (const AllocFailure& e) {
@@ -743,7 +702,8 @@ tip_status decompose_batched(int32_t n, const tip_edges* gs, const int32_t* side
         TIP_HIP_TRY(hipMemcpyAsync(tw.data(), b.w.fb.task_w, sizeof(int64_t) * b.rs.S, hipMemcpyDeviceToHost, s));
         TIP_HIP_TRY(hipStreamSynchronize(s));
         const int64_t j = (int64_t)jobs.size();
-        jobs.push_back(FdJob{b.w.g, b.w.fb, b.w.pb.init, b.w.ctl});
+        jobs.push_back(FdJob{b.w.g, b.w.fb, b.w.pb.init, b.w.ctl, b.tune.fd_help_min, b.tune.fd_help_chunk,
+                             b.tune.fd_help_level_min});
         for (int32_t i = 0; i < b.rs.S; ++i) tasks.emplace_back(tw[i], (j << 32) | i);
         stride = std::max(stride, b.w.spill.stride);
     }
@@ -873,19 +833,29 @@ tip_status tip_decompose_batch(int32_t n, const tip_edges* gs, const int32_t* si
     return guard([&]() -> tip_status {
         if (n < 0) throw InvalidArg("negative batch size");
         if (n > 0 && (!gs || !sides || !thetas)) throw InvalidArg("batch arrays are NULL");
-        const int32_t P = check_opts(opt);
+        const int32_t flags = opt ? opt->flags : 0;
+        const bool per_graph = (flags & TIP_FLAG_OPTS_PER_GRAPH) != 0;
+        // options of graph k: opt[k] with TIP_FLAG_OPTS_PER_GRAPH, else *opt
+        std::vector<int32_t> Ps(std::max(n, 0));
+        std::vector<Tune> tunes(std::max(n, 0));
+        for (int32_t k = 0; k < n; ++k) {
+            const tip_opts* ok = per_graph ? &opt[k] : opt;
+            if (per_graph && ok->flags != flags) throw InvalidArg("per-graph options must carry the same flags");
+            Ps[k] = check_opts(ok, true);
+            tunes[k] = tune_of(ok);
+        }
+        if (!per_graph) check_opts(opt, true);
         for (int32_t k = 0; k < n; ++k) {
             check_edges(&gs[k]);
             if (sides[k] != TIP_SIDE_U && sides[k] != TIP_SIDE_V) throw InvalidArg("side must be 0 or 1");
             const int32_t n_side = sides[k] == TIP_SIDE_U ? gs[k].n_u : gs[k].n_v;
             if (n_side > 0 && !thetas[k]) throw InvalidArg("theta is NULL");
         }
-        const int32_t flags = opt ? opt->flags : 0;
-        if (!(flags & TIP_FLAG_BATCH_PLAIN))
-            return decompose_batched(n, gs, sides, thetas, P, flags, tune_of(opt), st);
+        const int32_t run_flags = flags & ~TIP_FLAG_OPTS_PER_GRAPH;
+        if (!(flags & TIP_FLAG_BATCH_PLAIN)) return decompose_batched(n, gs, sides, thetas, Ps, run_flags, tunes, st);
         // the plain form: one full decomposition after another
         for (int32_t k = 0; k < n; ++k) {
-            const tip_status rc = decompose_host(&gs[k], sides[k], thetas[k], P, flags, tune_of(opt),
+            const tip_status rc = decompose_host(&gs[k], sides[k], thetas[k], Ps[k], run_flags, tunes[k],
                                                  st ? &st[k] : nullptr, nullptr, nullptr, nullptr, nullptr);
             if (rc != TIP_OK) return rc;
         }

@@ -362,3 +362,44 @@ def test_hubs_above_sixteen_bit_counts(gpu_lib):
     g = gg.chung_lu(200000, 300, 1_000_000, 2.5, 1.8, seed=61, cap_v=1.5e5)
     assert (np.bincount(g.ev, minlength=g.n_v) > 65535).sum() == 3
     np.testing.assert_array_equal(tip.decompose(g, 1), oracle.bup(g, 1)[0])
+
+
+def test_two_hub_stars_are_not_refused(gpu_lib):
+    """A U hub and a V hub of degree 2.7M each (m = 5.4M) hold no butterfly.
+    Every count and tip number is 0 and every call returns TIP_OK: no count
+    bound is applied that could refuse a valid graph."""
+    k = 2_700_000
+    eu = np.concatenate([np.zeros(k, np.int32), np.arange(1, k + 1, dtype=np.int32)])
+    ev = np.concatenate([np.arange(1, k + 1, dtype=np.int32), np.zeros(k, np.int32)])
+    g = gg.Graph(k + 1, k + 1, eu, ev, "two-stars")
+    bu, bv, tot = tip.count_butterflies(g)
+    assert tot == 0 and not bu.any() and not bv.any()
+    for side in (0, 1):
+        th = tip.decompose(g, side)
+        assert th.shape == (k + 1,) and not th.any()
+
+
+def test_help_board_tunables_change_nothing(gpu_lib):
+    """The fine-grained help-board parameters (tune[4..6]) only change which
+    workgroups apply a level's updates: with every subset opening a slot,
+    every level published and one update per claim, cl-1m's tip numbers on
+    both sides equal the oracle's stored digests, as with the defaults."""
+    rec = _golden("cl-1m")
+    g = gg.config_graph("cl-1m")
+    for side, key in ((0, "theta_u"), (1, "theta_v")):
+        for tune in ([0, 0, 0, 0, 1, 1, 1], [0, 0, 0, 0, 64, 4096, 100000]):
+            assert digest(tip.decompose(g, side, tune=tune)) == rec[key]["sha256"], (side, tune)
+
+
+def test_batch_with_per_graph_tunings(gpu_lib):
+    """tip_decompose_batch with one tip_opts per graph (each graph its own
+    tuning, as the autotuner stores them): batched and plain forms equal the
+    oracle."""
+    params = gg.batch_params(6, seed_base=3100, m_lo=3e3, m_hi=3e4)
+    gs = [gg.batch_graph(p) for p in params]
+    tunes = [None, [256, 1024, 0, 0, 8, 128, 0, 0], [2048, 8192, 0, 0, 64, 512, 0, 0],
+             [512, 4096, 0, 0, 1, 1, 1, 0], None, [1024, 2048, 0, 0, 32, 256, 0, 0]]
+    for flags in (0, tip.TIP_FLAG_BATCH_PLAIN):
+        out = tip.decompose_batch(gs, [0] * len(gs), flags=flags, tunes=tunes)
+        for g, th in zip(gs, out):
+            np.testing.assert_array_equal(th, oracle.bup(g, 0)[0])
