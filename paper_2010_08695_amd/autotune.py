@@ -1,16 +1,26 @@
-"""Autotuner for libtip's update-kernel selection thresholds.
+"""Autotuner for libtip's run-time tunables (tip_opts.tune).
 
-The coarse-grained update kernels are chosen per vertex by two thresholds
-(tip_opts.tune): tune[0] = D, the divisor of the dense-kernel threshold
-(a vertex goes to the dense key-range kernel only when its wedges exceed
-n_side * bits / D), and tune[1] = the largest wedge count handled by the
-bitmap kernel.  Which setting is fastest depends on the degree distribution,
-so the tuner times full decompositions of a representative graph over a
-small grid of settings.  Every trial must give the same tip numbers (any
-setting is exact; a mismatch is a library error and aborts the tuning).  The
-winner is cached in a JSON file keyed by device name and graph size class.
+Which setting is fastest depends on the graph's size and degree
+distribution, so the tuner times full decompositions of a representative
+graph and keeps the fastest.  The search is staged (coordinate descent):
+
+1. the coarse-grained update-kernel selection: tune[0] = D, the divisor of
+   the dense-kernel threshold (a vertex goes to the dense key-range kernel
+   with its LDS counter table only when its wedges exceed n_side * bits / D),
+   and tune[1], the largest wedge count handled by the bitmap kernel with its
+   LDS bitmap and repeat table;
+2. the fine-grained step's work queue (its help board, with stage 1's winner
+   fixed): tune[4] updates taken per claim of a queue slot and tune[5] the
+   fewest per-wave updates of a level worth publishing.
+
+Every trial must give the same tip numbers (any setting is exact; a mismatch
+is a library error and aborts the tuning).  Winners are stored per device
+name and graph size class.  Lookups read the user's cache first, then the
+table that ships with the package (``tuning.json``, written on an MI355X by
+``--batch``).
 
     python -m paper_2010_08695_amd.autotune --workload cl-1m [--side 0]
+    python -m paper_2010_08695_amd.autotune --batch 64 --out tuning.json
 """
 from __future__ import annotations
 
@@ -25,8 +35,13 @@ import numpy as np
 
 from . import graphgen, tip
 
-DEFAULT_GRID = {"dense_div": [256, 512, 1024, 2048], "bitmap_max": [1024, 2048, 4096, 8192]}
+STAGES = [
+    {"dense_div": (0, [256, 512, 1024, 2048]), "bitmap_max": (1, [1024, 2048, 4096, 8192])},
+    {"help_chunk": (4, [8, 16, 32, 64]), "help_level_min": (5, [128, 256, 512])},
+]
+N_TUNE = 8
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "libtip_autotune.json")
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 
 
 def size_class(n_u: int, n_v: int, m: int, side: int) -> str:
@@ -37,18 +52,31 @@ def size_class(n_u: int, n_v: int, m: int, side: int) -> str:
 
 
 def choose(trials: list[dict]) -> dict:
-    """The fastest trial (median time); ties go to the earlier grid point."""
+    """The fastest trial (best time); ties go to the earlier grid point."""
     if not trials:
         raise ValueError("no trials")
     best = min(range(len(trials)), key=lambda i: (trials[i]["ms"], i))
     return trials[best]
 
 
-def tune_graph(g, side: int = 0, grid: dict | None = None, reps: int = 3, P: int = 0, timer=None) -> dict:
-    """Times every grid point on graph g; returns {"tune": [D, bm], "ms": ...,
-    "trials": [...]}.  timer(g, side, tune) -> (theta, ms) can replace the
-    library call (tests)."""
-    grid = grid or DEFAULT_GRID
+def _grid(stage: dict, base: list[int]) -> list[list[int]]:
+    points = [list(base)]
+    for _name, (idx, values) in stage.items():
+        nxt = []
+        for p in points:
+            for v in values:
+                q = list(p)
+                q[idx] = v
+                nxt.append(q)
+        points = nxt
+    return points
+
+
+def tune_graph(g, side: int = 0, stages: list | None = None, reps: int = 3, P: int = 0, timer=None) -> dict:
+    """Times the staged grid on graph g; returns {"tune": [...8 ints], "ms":
+    ..., "trials": [...]}.  timer(g, side, tune) -> (theta, ms) can replace
+    the library call (tests)."""
+    stages = STAGES if stages is None else stages
 
     def lib_timer(g, side, tune):
         best, th = None, None
@@ -62,15 +90,20 @@ def tune_graph(g, side: int = 0, grid: dict | None = None, reps: int = 3, P: int
     timer = timer or lib_timer
     ref = None
     trials = []
-    for d in grid["dense_div"]:
-        for bm in grid["bitmap_max"]:
-            th, ms = timer(g, side, [d, bm])
+    base = [0] * N_TUNE
+    win = None
+    for stage in stages:
+        stage_trials = []
+        for point in _grid(stage, base):
+            th, ms = timer(g, side, point)
             if ref is None:
                 ref = th
             elif not np.array_equal(ref, th):
-                raise RuntimeError(f"tip numbers differ between tunings ({d}, {bm}): library error")
-            trials.append({"tune": [d, bm], "ms": float(ms)})
-    win = choose(trials)
+                raise RuntimeError(f"tip numbers differ between tunings ({point}): library error")
+            stage_trials.append({"tune": point, "ms": float(ms)})
+        win = choose(stage_trials)
+        base = list(win["tune"])
+        trials += stage_trials
     return {"tune": win["tune"], "ms": win["ms"], "trials": trials}
 
 
@@ -90,17 +123,37 @@ def load_cache(path: str = CACHE) -> dict:
         return {}
 
 
-def lookup(g, side: int, path: str = CACHE):
-    """Cached tune list for graphs of g's size class on this device, or None."""
-    key = f"{device_name()}|{size_class(g.n_u, g.n_v, g.m, side)}"
-    rec = load_cache(path).get(key)
-    return rec["tune"] if rec else None
+def _key(g, side: int, device: str | None = None) -> str:
+    return f"{device or device_name()}|{size_class(g.n_u, g.n_v, g.m, side)}"
 
 
-def store(g, side: int, result: dict, path: str = CACHE) -> None:
+def lookup(g, side: int, path: str | None = CACHE, table: str | None = TABLE, device: str | None = None):
+    """Stored tune list for graphs of g's size class on this device (the
+    user's cache first, then the package table), or None."""
+    key = _key(g, side, device)
+    for p in (path, table):
+        if p is None:
+            continue
+        rec = load_cache(p).get(key)
+        if rec:
+            t = list(rec["tune"]) + [0] * N_TUNE
+            return t[:N_TUNE]
+    return None
+
+
+def batch_tunes(graphs, sides, path: str | None = CACHE, table: str | None = TABLE):
+    """Per-graph tune lists (None where nothing is stored) for
+    tip.decompose_batch(..., tunes=...)."""
+    dev = device_name()
+    return [lookup(g, s, path, table, dev) for g, s in zip(graphs, sides)]
+
+
+def store(g, side: int, result: dict, path: str = CACHE, device: str | None = None) -> None:
     cache = load_cache(path)
-    cache[f"{device_name()}|{size_class(g.n_u, g.n_v, g.m, side)}"] = {"tune": result["tune"], "ms": result["ms"]}
-    os.makedirs(os.path.dirname(path), exist_ok=True)
+    cache[_key(g, side, device)] = {"tune": list(result["tune"]), "ms": result["ms"]}
+    d = os.path.dirname(path)
+    if d:
+        os.makedirs(d, exist_ok=True)
     tmp = path + f".tmp{os.getpid()}"
     with open(tmp, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
@@ -112,11 +165,24 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="cl-1m")
     ap.add_argument("--side", type=int, default=0)
     ap.add_argument("--reps", type=int, default=3)
-    ap.add_argument("--cache", default=CACHE)
+    ap.add_argument("--batch", type=int, default=0, help="tune one graph per size class of the N-graph batch")
+    ap.add_argument("--out", default=CACHE)
     args = ap.parse_args(argv)
+    if args.batch:
+        graphs = [graphgen.batch_graph(p) for p in graphgen.batch_params(args.batch)]
+        seen = {}
+        for g in graphs:
+            seen.setdefault(size_class(g.n_u, g.n_v, g.m, 0), g)
+        for cls, g in sorted(seen.items()):
+            res = tune_graph(g, 0, reps=args.reps)
+            store(g, 0, res, args.out)
+            dflt = [t["ms"] for t in res["trials"] if t["tune"][:2] == [1024, 2048] and not any(t["tune"][2:])]
+            print(json.dumps({"class": cls, "graph": g.name, "tune": res["tune"], "ms": res["ms"],
+                              "default_ms": dflt[0] if dflt else None}), flush=True)
+        return 0
     g = graphgen.config_graph(args.workload)
     res = tune_graph(g, args.side, reps=args.reps)
-    store(g, args.side, res, args.cache)
+    store(g, args.side, res, args.out)
     print(json.dumps({"workload": args.workload, "side": args.side, "device": device_name(), **res}))
     return 0
 

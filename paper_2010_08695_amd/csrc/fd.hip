@@ -502,22 +502,22 @@ __device__ inline void fd_heavy_level(const DevGraph& g, const FdBuffers& fb, Fd
 }
 
 // Per-wave updates taken from a help-board slot until its published list is
-// exhausted: one atomic on the slot word hands out kFdHelpChunk entries;
+// exhausted: one atomic on the slot word hands out `chunk` entries;
 // finished entries are counted in `done` after their decrements are visible
 // device-wide.
 template <class St>
 __device__ inline void fd_help_slot(const DevGraph& g, const FdBuffers& fb, FdLds& L, unsigned long long* tab,
                                     uint32_t* wcnt, const int32_t* pl, const int64_t* fw, int32_t n_i,
-                                    FdHelpSlot* hs, const St& st, unsigned long long& wedges,
+                                    FdHelpSlot* hs, int32_t chunk, const St& st, unsigned long long& wedges,
                                     unsigned long long& pairs) {
     const int lane = threadIdx.x & (kWave - 1);
     for (;;) {
         unsigned long long wv = 0;
-        if (lane == 0) wv = atomicAdd(&hs->word, (unsigned long long)kFdHelpChunk);
+        if (lane == 0) wv = atomicAdd(&hs->word, (unsigned long long)chunk);
         wv = __shfl(wv, 0, kWave);
         const uint32_t q0 = (uint32_t)wv, nl = (uint32_t)(wv >> 32);
         if (q0 >= nl) break;
-        const uint32_t q1 = min(nl, q0 + (uint32_t)kFdHelpChunk);
+        const uint32_t q1 = min(nl, q0 + (uint32_t)chunk);
         __threadfence();
         for (uint32_t q = q0; q < q1; ++q) {
             const int32_t x = pl[q];
@@ -547,7 +547,8 @@ __device__ inline bool fd_heavy(const DevGraph& g, const FdBuffers& fb, int64_t 
 // Level loop of a subset whose state lives in HBM.
 __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const int64_t* __restrict__ init,
                                    int64_t P0, int32_t n_i, FdLds& L, unsigned long long* tab, const Spill& sp,
-                                   FdHelpSlot* hs, unsigned long long& wedges, unsigned long long& pairs,
+                                   FdHelpSlot* hs, int32_t help_chunk, int32_t help_level_min,
+                                   unsigned long long& wedges, unsigned long long& pairs,
                                    unsigned long long& levels, unsigned long long& spills) {
     constexpr int NT = kFdThreads;
     constexpr int NW = NT / kWave;
@@ -615,7 +616,7 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
             }
         }
         levels += tid == 0;
-        if (hs && n_light >= kFdHelpLevelMin) {
+        if (hs && n_light >= help_level_min) {
             // publish the level's per-wave updates on the help board, take
             // entries like the helpers do, then wait for every taken entry
             // (levels with fewer updates are not worth the fences)
@@ -627,7 +628,7 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
                 atomicExch(&hs->word, (unsigned long long)n_light << 32);
             }
             __syncthreads();
-            fd_help_slot(g, fb, L, tab, wcnt, pl, fw, n_i, hs, st, wedges, pairs);
+            fd_help_slot(g, fb, L, tab, wcnt, pl, fw, n_i, hs, help_chunk, st, wedges, pairs);
             __syncthreads();
             if (tid == 0)
                 while (__hip_atomic_load(&hs->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n_light)
@@ -790,7 +791,7 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
         } else {
             // a large subset opens a help-board slot for its per-wave updates
             FdHelpSlot* hs = nullptr;
-            if (n_i >= kFdHelpMin) {
+            if (n_i >= J.help_min) {
                 if (tid == 0) {
                     const int32_t k = atomicAdd(&board->n_slots, 1);
                     L.flag = k;
@@ -809,7 +810,8 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
                 if (L.flag < kFdHelpSlots) hs = &board->slot[L.flag];
                 __syncthreads();
             }
-            fd_peel_hbm(J.g, fb, J.init, P0, n_i, L, tab, sp, hs, wedges, pairs, levels, spills);
+            fd_peel_hbm(J.g, fb, J.init, P0, n_i, L, tab, sp, hs, J.help_chunk, J.help_level_min, wedges, pairs,
+                        levels, spills);
             if (hs && tid == 0) atomicExch(&hs->state, 2);
         }
         wedges = (unsigned long long)wave_sum_i64((int64_t)wedges);
@@ -855,7 +857,8 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
             const FdHbmState st{fb.supp_fd + P0, fb.alive + P0, fb.fd_vert + P0};
             uint32_t* wcnt = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(&L.u) + (size_t)wid * kFdWaveKeys);
             unsigned long long wedges = 0, pairs = 0;
-            fd_help_slot(J.g, fb, L, tab, wcnt, fb.lst[2] + P0, fb.fd_w + P0, hs->n_i, hs, st, wedges, pairs);
+            fd_help_slot(J.g, fb, L, tab, wcnt, fb.lst[2] + P0, fb.fd_w + P0, hs->n_i, hs, J.help_chunk, st, wedges,
+                         pairs);
             wedges = (unsigned long long)wave_sum_i64((int64_t)wedges);
             pairs = (unsigned long long)wave_sum_i64((int64_t)pairs);
             if (lane == 0) {
@@ -911,15 +914,15 @@ void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t 
     TIP_HIP_TRY(hipGetLastError());
 }
 
-void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl, const SpillArena& spill,
-               int big_grid, uint64_t* tmp_keys, int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp,
+void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl, const Tune& tune,
+               const SpillArena& spill, int big_grid, uint64_t* tmp_keys, int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp,
                uint64_t* keys_scratch, int32_t* vals_scratch, hipStream_t s) {
     if (g.n_a <= 0) return;
     launch_fd_setup(g, pb, fb, S, tmp_keys, tmp_vals, hist, scan_tmp, keys_scratch, vals_scratch, s);
     k_fd_reset_board<<<1, 256, 0, s>>>(fb.board);
     TIP_HIP_TRY(hipGetLastError());
     FdJobs jobs{};
-    jobs.one = FdJob{g, fb, pb.init, ctl};
+    jobs.one = FdJob{g, fb, pb.init, ctl, tune.fd_help_min, tune.fd_help_chunk, tune.fd_help_level_min};
     // every resident workgroup: those without a task of their own help
     // with the large subsets
     const int grid = std::max(1, big_grid);

@@ -157,6 +157,10 @@ struct Tune {
     int64_t bitmap_max = kDefaultBitmapMax;
     int64_t compact_permille = kDefaultCompactPermille;  // 0: never compact
     int64_t huc_pct = 0;  // tip_opts.tune[3]
+    // fine-grained help board (tip_opts.tune[4..6])
+    int32_t fd_help_chunk = kFdHelpChunk;
+    int32_t fd_help_level_min = kFdHelpLevelMin;
+    int32_t fd_help_min = kFdHelpMin;
 };
 
 // counting
@@ -200,6 +204,9 @@ struct FdJob {
     FdBuffers fb;
     const int64_t* init;  // [n_a] support at the start of each vertex's range
     Ctl* ctl;             // receives the job's work counters
+    int32_t help_min;        // subsets of at least this many vertices open a help-board slot
+    int32_t help_chunk;      // per-wave updates taken at once from a slot
+    int32_t help_level_min;  // levels with fewer per-wave updates are not published
 };
 
 // The jobs of one launch: a device array, or (list == nullptr) one job
@@ -220,7 +227,8 @@ void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t 
 // head (reset here).
 void launch_fd_batch(const FdJob* d_jobs, const int64_t* d_tasks, int32_t n_tasks, FdBoard* d_board,
                      const SpillArena& spill, int big_grid, hipStream_t s);
-void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl, const SpillArena& spill,
+void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl, const Tune& tune,
+               const SpillArena& spill,
                int big_grid, uint64_t* tmp_keys, int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp,
                uint64_t* keys_scratch, int32_t* vals_scratch, hipStream_t s);
 // output

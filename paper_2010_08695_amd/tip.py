@@ -23,6 +23,7 @@ TIP_FLAG_TIME_KERNELS = 1
 TIP_FLAG_NO_GRAPH = 2
 TIP_FLAG_BATCH_PLAIN = 4
 TIP_FLAG_NO_COMPACT = 8
+TIP_FLAG_OPTS_PER_GRAPH = 16
 SIDE_U, SIDE_V = 0, 1
 STATUS_NAMES = {0: "TIP_OK", -1: "TIP_EINVAL", -2: "TIP_ENOMEM", -3: "TIP_EDEVICE",
                 -4: "TIP_EOVERFLOW", -5: "TIP_EBUSY"}
@@ -189,9 +190,21 @@ def decompose_ex(g, side: int = SIDE_U, P: int = 0, flags: int = 0, tune=None) -
             "n_subsets": k, "stats": st.to_dict()}
 
 
-def decompose_batch(graphs, sides=None, P: int = 0, with_stats: bool = False, flags: int = 0):
+def batch_opts(n: int, P: int, flags: int, tunes) -> ctypes.Array:
+    """tip_opts[n] for tip_decompose_batch with TIP_FLAG_OPTS_PER_GRAPH:
+    graph k gets tunes[k] (None = the library defaults)."""
+    if len(tunes) != n:
+        raise ValueError("one tune entry per graph")
+    arr = (Opts * max(n, 1))()
+    for k in range(n):
+        arr[k] = _opts(P, flags | TIP_FLAG_OPTS_PER_GRAPH, 0, tunes[k])
+    return arr
+
+
+def decompose_batch(graphs, sides=None, P: int = 0, with_stats: bool = False, flags: int = 0, tunes=None):
     """Tip numbers of many graphs in one call (batched form unless flags has
-    TIP_FLAG_BATCH_PLAIN)."""
+    TIP_FLAG_BATCH_PLAIN).  tunes: None, or one tip_opts.tune list (or None
+    for the defaults) per graph, passed with TIP_FLAG_OPTS_PER_GRAPH."""
     lib = load()
     n = len(graphs)
     sides = [SIDE_U] * n if sides is None else list(sides)
@@ -205,9 +218,8 @@ def decompose_batch(graphs, sides=None, P: int = 0, with_stats: bool = False, fl
     sides_a = np.ascontiguousarray(sides, dtype=np.int32)
     ptrs = (ctypes.c_void_p * max(n, 1))(*[t.ctypes.data for t in thetas])
     sts = (Stats * max(n, 1))()
-    o = _opts(P, flags)
-    _check(lib, lib.tip_decompose_batch(n, es, _ptr(sides_a), ctypes.cast(ptrs, ctypes.c_void_p),
-                                        ctypes.byref(o), sts))
+    popt = batch_opts(n, P, flags, tunes) if tunes is not None else ctypes.byref(_opts(P, flags))
+    _check(lib, lib.tip_decompose_batch(n, es, _ptr(sides_a), ctypes.cast(ptrs, ctypes.c_void_p), popt, sts))
     if with_stats:
         return thetas, [sts[k].to_dict() for k in range(n)]
     return thetas

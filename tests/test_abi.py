@@ -103,7 +103,16 @@ def test_decompose_rejects_bad_arguments(lib):
     o.tune[3] = -1                                # HUC threshold must be >= 0
     _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
     o = tip.Opts()
-    o.tune[4] = 2                                 # reserved
+    o.tune[7] = 2                                 # reserved
+    _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
+    o = tip.Opts()
+    o.tune[4] = 2**20 + 1                         # help-board claim too large
+    _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
+    o = tip.Opts()
+    o.tune[6] = -1
+    _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
+    o = tip.Opts()
+    o.flags = tip.TIP_FLAG_OPTS_PER_GRAPH         # batch-only flag
     _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
     e, k = _edges(3, 3, [0, 5], [1, 2])
     _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, None, None))
@@ -122,6 +131,16 @@ def test_batch_and_workspace_reject_bad_arguments(lib):
     ptrs = (ctypes.c_void_p * 1)(th.ctypes.data)
     _expect_einval(lib, lib.tip_decompose_batch(1, es, sides.ctypes.data_as(ctypes.c_void_p),
                                                 ctypes.cast(ptrs, ctypes.c_void_p), None, None))
+    # per-graph options whose flags differ between graphs
+    es2 = (tip.Edges * 2)()
+    e0, k0 = _edges(2, 2, [0, 1], [0, 1])
+    es2[0] = es2[1] = e0
+    th2 = [np.zeros(2, np.int64), np.zeros(2, np.int64)]
+    ptrs2 = (ctypes.c_void_p * 2)(th2[0].ctypes.data, th2[1].ctypes.data)
+    opts = tip.batch_opts(2, 0, 0, [None, None])
+    opts[1].flags = tip.TIP_FLAG_OPTS_PER_GRAPH | tip.TIP_FLAG_NO_COMPACT
+    _expect_einval(lib, lib.tip_decompose_batch(2, es2, np.zeros(2, np.int32).ctypes.data_as(ctypes.c_void_p),
+                                                ctypes.cast(ptrs2, ctypes.c_void_p), opts, None))
     out = ctypes.c_size_t(0)
     _expect_einval(lib, lib.tip_workspace_size(2, 2, 4, 0, None, None))
     _expect_einval(lib, lib.tip_workspace_size(2, 2, -4, 0, None, ctypes.byref(out)))
