@@ -44,6 +44,8 @@ class Job:
     t_done: float = -1.0
     theta: np.ndarray | None = None
     wedges: int = 0
+    status: str = "pending"  # "ok", "failed" (the executor raised) or "rejected" (waited too long)
+    error: str = ""
 
     @property
     def latency(self) -> float:
@@ -123,11 +125,17 @@ class Executor:
         stream.synchronize()
 
 
-def replay(jobs: list[Job], run_job, slots: int, budget_bytes: int, streams=None) -> dict:
+def replay(jobs: list[Job], run_job, slots: int, budget_bytes: int, streams=None,
+           max_wait_s: float | None = None) -> dict:
     """Replays the trace in real time.  run_job(job, stream) executes one job
-    (blocking); up to `slots` run at once.  Returns the summary."""
+    (blocking); up to `slots` run at once.  A job whose executor raises is
+    recorded as failed (its error kept on the job) and its slot, memory and
+    stream are released; the replay goes on.  With `max_wait_s`, a job still
+    waiting for admission that long after its arrival is rejected without
+    running.  Returns the summary."""
     for j in jobs:
         j.t_admit = j.t_done = -1.0
+        j.status, j.error = "pending", ""
     adm = Admission(budget_bytes, slots)
     pending = collections.deque(sorted(jobs, key=lambda j: (j.arrival, j.id)))
     waiting: collections.deque[Job] = collections.deque()
@@ -142,6 +150,9 @@ def replay(jobs: list[Job], run_job, slots: int, budget_bytes: int, streams=None
     def task(job, stream):
         try:
             run_job(job, stream)
+            job.status = "ok"
+        except Exception as e:  # noqa: BLE001 - a job's failure is recorded, not fatal to the loop
+            job.status, job.error = "failed", f"{type(e).__name__}: {e}"
         finally:
             with lock:
                 job.t_done = now()
@@ -151,6 +162,10 @@ def replay(jobs: list[Job], run_job, slots: int, budget_bytes: int, streams=None
             t = now()
             while pending and pending[0].arrival <= t:
                 waiting.append(pending.popleft())
+            if max_wait_s is not None:
+                while waiting and t - waiting[0].arrival > max_wait_s:
+                    job = waiting.popleft()
+                    job.status, job.t_done = "rejected", t
             while waiting and adm.fits(waiting[0]):
                 job = waiting.popleft()
                 adm.admit(job)
@@ -164,7 +179,6 @@ def replay(jobs: list[Job], run_job, slots: int, budget_bytes: int, streams=None
                 done, _ = wait(list(running), timeout=timeout, return_when=FIRST_COMPLETED)
                 for f in done:
                     job, stream = running.pop(f)
-                    f.result()  # re-raises a failed job's error
                     adm.release(job)
                     free_streams.append(stream)
             elif timeout:
@@ -173,13 +187,23 @@ def replay(jobs: list[Job], run_job, slots: int, budget_bytes: int, streams=None
 
 
 def summarize(jobs: list[Job]) -> dict:
-    lat = np.array([j.latency for j in jobs])
+    """Latency percentiles and throughput over the jobs that completed;
+    failed and rejected jobs are counted, with the first errors."""
+    ok = [j for j in jobs if j.status == "ok"]
+    failed = [j for j in jobs if j.status == "failed"]
+    rejected = [j for j in jobs if j.status == "rejected"]
+    out = {"jobs": len(jobs), "completed": len(ok), "failed": len(failed), "rejected": len(rejected),
+           "errors": [f"job {j.id}: {j.error}" for j in failed[:5]]}
+    if not ok:
+        return out
+    lat = np.array([j.latency for j in ok])
     end = max(j.t_done for j in jobs)
     start = min(j.arrival for j in jobs)
-    wedges = sum(j.wedges for j in jobs)
-    return {"jobs": len(jobs), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-            "mean_s": float(lat.mean()), "makespan_s": end - start, "jobs_per_s": len(jobs) / (end - start),
-            "wedges_per_s": wedges / (end - start), "edges": int(sum(j.graph.m for j in jobs))}
+    wedges = sum(j.wedges for j in ok)
+    out.update({"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                "mean_s": float(lat.mean()), "makespan_s": end - start, "jobs_per_s": len(ok) / (end - start),
+                "wedges_per_s": wedges / (end - start), "edges": int(sum(j.graph.m for j in ok))})
+    return out
 
 
 def main(argv=None) -> int:

@@ -97,3 +97,42 @@ def test_results_alone_equal_results_in_the_mix(gpu_lib):
     for j in jobs:
         np.testing.assert_array_equal(mixed[j.id], j.theta)
         np.testing.assert_array_equal(j.theta, oracle.bup(j.graph, j.side)[0])
+
+
+def test_failed_job_releases_its_slot_and_the_loop_goes_on():
+    """A job whose executor raises is recorded as failed; its slot, memory and
+    stream are released, and the jobs behind it are still admitted and
+    finish."""
+    jobs = [_job(i, 0.005 * i, 60) for i in range(6)]
+    streams = ["s0", "s1"]
+    used = []
+
+    def run(job, stream):
+        used.append(stream)
+        time.sleep(0.01)
+        if job.id in (1, 4):
+            raise RuntimeError(f"device error in job {job.id}")
+        job.wedges = 5
+
+    s = serve.replay(jobs, run, slots=2, budget_bytes=100, streams=streams)
+    assert [j.status for j in jobs] == ["ok", "failed", "ok", "ok", "failed", "ok"]
+    assert "device error in job 1" in jobs[1].error
+    assert s["completed"] == 4 and s["failed"] == 2 and s["rejected"] == 0
+    assert len(s["errors"]) == 2 and s["jobs_per_s"] > 0
+    assert set(used) <= set(streams) and len(used) == 6
+    # a 60-byte job at a time under a 100-byte budget: never two at once,
+    # so the failed jobs must have released their memory for later ones
+    assert all(j.t_done >= j.t_admit >= 0 for j in jobs)
+
+
+def test_jobs_waiting_too_long_are_rejected():
+    jobs = [_job(i, 0.0, 10) for i in range(4)]
+
+    def run(job, stream):
+        time.sleep(0.05)
+        job.wedges = 1
+
+    s = serve.replay(jobs, run, slots=1, budget_bytes=100, max_wait_s=0.07)
+    assert s["completed"] >= 2 and s["rejected"] >= 1
+    assert s["completed"] + s["rejected"] == 4
+    assert all(j.status in ("ok", "rejected") for j in jobs)
