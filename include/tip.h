@@ -199,6 +199,27 @@ tip_status tip_decompose_async(const int32_t* d_eu, const int32_t* d_ev, int32_t
                                int32_t side, int64_t* d_theta, void* d_workspace, size_t ws_bytes, void* stream,
                                const tip_opts* opt, tip_stats* st);
 
+/* For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc): tip_decompose_async without a workspace
+ * argument.  The library's scratch is a static device array of 512 MiB per
+ * device, created when the library's device code is loaded and held until
+ * the process ends; the call itself allocates nothing (no device, pinned or
+ * library memory, no HIP graph, no events).
+ *   d_eu, d_ev  device COO arrays [m]; d_theta device output [n_u or n_v]
+ *   stream      a hipStream_t (NULL = the default stream); all work is issued
+ *               on it and the call returns once the decomposition is done
+ *               (the coarse-grained step reads a few control words back
+ *               between rounds, so the call cannot be captured in a graph)
+ *   opt, st     as for tip_decompose_async; TIP_FLAG_TIME_KERNELS is
+ *               rejected and the t_*_ms times of st read 0
+ * Graphs whose tip_workspace_size exceeds 512 MiB are refused with
+ * TIP_ENOMEM before any device work.  Every call on one device shares that
+ * device's scratch and leaves its contents behind: calls that overlap on one
+ * device (from several host threads or streams) race and must be
+ * serialised by the caller. */
+tip_status tip_decompose_noalloc(const int32_t* d_eu, const int32_t* d_ev, int32_t n_u, int32_t n_v, int64_t m,
+                                 int32_t side, int64_t* d_theta, void* stream, const tip_opts* opt, tip_stats* st);
+
 /* Message of the last failed call on this thread ("" if none).  Valid until
  * the next tip_* call on this thread. */
 const char* tip_last_error(void);

@@ -15,6 +15,13 @@
 #include "tip_ingest.h"
 #include "tip_kernels.h"
 
+// Scratch of tip_decompose_noalloc: one copy per device, held until the
+// process ends.  Host code never uses this name as an address (on the host it
+// is only a stand-in for the symbol); it takes the device address that
+// hipGetSymbolAddress returns for the current device (noalloc_scratch).
+constexpr size_t kNoAllocScratchBytes = size_t(512) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace tip {
 
 namespace {
@@ -39,6 +46,9 @@ struct Work {
     Ctl* ctl = nullptr;
     SpillArena spill;
     int64_t* total = nullptr;
+    // set by tip_decompose_noalloc: no HIP graph, no events, no pinned host
+    // memory (every coarse-grained round is launched from the host)
+    bool no_alloc = false;
 };
 
 int resident_workgroups() {
@@ -120,7 +130,10 @@ struct PinnedCtl {
     }
 };
 
-Ctl* host_ctl() {
+// pinned = false: a plain host mirror, for calls that must not allocate
+Ctl* host_ctl(bool pinned) {
+    thread_local Ctl plain;
+    if (!pinned) return &plain;
     thread_local PinnedCtl pc;
     if (!pc.h) {
         void* p = nullptr;
@@ -131,7 +144,7 @@ Ctl* host_ctl() {
 }
 
 const Ctl& read_ctl(const Work& w, hipStream_t s) {
-    Ctl* h = host_ctl();
+    Ctl* h = host_ctl(!w.no_alloc);
     TIP_HIP_TRY(hipMemcpyAsync(h, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     TIP_HIP_TRY(hipStreamSynchronize(s));
     return *h;
@@ -171,18 +184,24 @@ struct RoundGraph {
     }
 };
 
+// Phase events; not created (records do nothing, times read 0) for calls
+// that must not allocate.
 struct Events {
     hipEvent_t e[6] = {};
-    Events() {
-        for (auto& x : e) TIP_HIP_TRY(hipEventCreate(&x));
+    explicit Events(bool create = true) {
+        if (create)
+            for (auto& x : e) TIP_HIP_TRY(hipEventCreate(&x));
     }
     ~Events() {
         for (auto& x : e)
             if (x) (void)hipEventDestroy(x);
     }
+    void rec(int i, hipStream_t s) {
+        if (e[i]) TIP_HIP_TRY(hipEventRecord(e[i], s));
+    }
     double ms(int a, int b) const {
         float t = 0;
-        if (hipEventElapsedTime(&t, e[a], e[b]) != hipSuccess) return 0.0;
+        if (!e[a] || !e[b] || hipEventElapsedTime(&t, e[a], e[b]) != hipSuccess) return 0.0;
         return t;
     }
 };
@@ -220,6 +239,7 @@ __global__ void k_scatter_i32(const int32_t* by_rank, const int32_t* orig, int32
 // State carried from the first part of a run (ingest, count, CD, FD set-up
 // or all of FD) to the second (outputs and statistics).
 struct RunState {
+    explicit RunState(bool events = true) : ev(events), kev(events) {}
     Events ev;
     Events kev;  // [0], [1]: around the dense update kernel of one round
     double peel_ms = 0.0;
@@ -247,9 +267,9 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
     int64_t& peel_launches = rs.peel_launches;
     // rounds run eagerly (one launch sequence per round, host-timed) when
     // kernels are timed or graphs are disabled, else from a replayed graph
-    const bool eager = time_kernels || (flags & TIP_FLAG_NO_GRAPH) != 0;
+    const bool eager = time_kernels || (flags & TIP_FLAG_NO_GRAPH) != 0 || w.no_alloc;
     std::unique_ptr<RoundGraph> rg;
-    TIP_HIP_TRY(hipEventRecord(ev.e[0], s));
+    ev.rec(0, s);
     TIP_HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s));
     if (!ingest(d_a, d_b, n_a, n_b, m, a_is_u, w.ib, w.g, w.aux, s)) {
         set_error("an edge endpoint id is out of range");
@@ -259,18 +279,18 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
     // most (d_x - 1) / 2 * sum_{y in N_x} (d_y - 1), so either side's counts
     // sum to at most 1/2 * sum over edges (x, y) of (d_x - 1)(d_y - 1) <
     // m^2 / 2 < 2^61 for m < 2^31 (the largest m the boundary accepts).
-    TIP_HIP_TRY(hipEventRecord(ev.e[1], s));
+    ev.rec(1, s);
     const DevGraph& g = w.g;
     const int big_grid = w.spill.slots;
 
     // Per-vertex butterfly counting (Alg. 1).
     launch_count(g, w.cb, w.ctl, w.spill, big_grid, s);
-    TIP_HIP_TRY(hipEventRecord(ev.e[2], s));
+    ev.rec(2, s);
 
     int32_t& S = rs.S;
     if (!decompose) {
-        TIP_HIP_TRY(hipEventRecord(ev.e[3], s));
-        TIP_HIP_TRY(hipEventRecord(ev.e[4], s));
+        ev.rec(3, s);
+        ev.rec(4, s);
     } else {
         // Coarse-grained decomposition (Alg. 3).
         PeelBuffers& pb = w.pb;
@@ -346,7 +366,7 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
                 }
             }
             // the loop ends on a read with nothing launched after it
-            const Ctl& c3 = *host_ctl();
+            const Ctl& c3 = *host_ctl(!w.no_alloc);
             bounds.push_back((int64_t)c3.range_hi);
             const long long w_range = (long long)spread_sum(c3, kScWRange);
             if (w_range > 0) scale = std::min(1.0, (double)tgt / (double)w_range);
@@ -363,13 +383,13 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
         } else {
             S = label;
         }
-        TIP_HIP_TRY(hipEventRecord(ev.e[3], s));
+        ev.rec(3, s);
         // Fine-grained decomposition (Alg. 4).
         if (fd_inline) {
             if (S > 0)
                 launch_fd(g, pb, w.fb, S, w.ctl, tune, w.spill, big_grid, w.ib.keys2, w.ib.vals2, w.ib.hist,
                           w.ib.scan_tmp, w.ib.keys, w.ib.vals, s);
-            TIP_HIP_TRY(hipEventRecord(ev.e[4], s));
+            ev.rec(4, s);
         } else {
             launch_fd_setup(g, pb, w.fb, S, w.ib.keys2, w.ib.vals2, w.ib.hist, w.ib.scan_tmp, w.ib.keys, w.ib.vals,
                             s);
@@ -398,7 +418,7 @@ void run_back(Work& w, int32_t n_a, int32_t n_b, bool decompose, RunOut& out, Ru
         if (out.bounds) *out.bounds = rs.bounds;
         if (out.n_subsets) *out.n_subsets = S;
     }
-    TIP_HIP_TRY(hipEventRecord(ev.e[5], s));
+    ev.rec(5, s);
     const Ctl& cf = read_ctl(w, s);
     if (st) {
         std::memset(st, 0, sizeof(*st));
@@ -429,7 +449,7 @@ void run_back(Work& w, int32_t n_a, int32_t n_b, bool decompose, RunOut& out, Ru
 tip_status run(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_a, int32_t n_b, int64_t m, bool a_is_u,
                int32_t P, int32_t flags, const Tune& tune, bool decompose, RunOut& out, tip_stats* st,
                hipStream_t s) {
-    RunState rs;
+    RunState rs(!w.no_alloc);
     const tip_status rc = run_front(w, d_a, d_b, n_a, n_b, m, a_is_u, P, flags, tune, decompose, true, rs, s);
     if (rc != TIP_OK) return rc;
     run_back(w, n_a, n_b, decompose, out, rs, st, s);
@@ -733,7 +753,7 @@ tip_status decompose_batched(int32_t n, const tip_edges* gs, const int32_t* side
         TIP_HIP_TRY(hipMemsetAsync(spill.dense, 0, sizeof(int32_t) * stride * slots, s));
         launch_fd_batch(d_jobs, d_tasks, (int32_t)tasks.size(), d_board, spill, slots, s);
     }
-    for (int32_t k = 0; k < n; ++k) TIP_HIP_TRY(hipEventRecord(items[k]->rs.ev.e[4], s));
+    for (int32_t k = 0; k < n; ++k) items[k]->rs.ev.rec(4, s);
     for (int32_t k = 0; k < n; ++k) {
         BatchItem& b = *items[k];
         RunOut out;
@@ -744,6 +764,26 @@ tip_status decompose_batched(int32_t n, const tip_edges* gs, const int32_t* side
     }
     TIP_HIP_TRY(hipStreamSynchronize(s));
     return TIP_OK;
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+constexpr int kMaxDevices = 64;
+
+void* noalloc_scratch() {
+    static std::mutex mu;
+    static void* ptr[kMaxDevices] = {};
+    int dev = 0;
+    TIP_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw InvalidArg("device ordinal beyond the supported range");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        TIP_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw HipFailure("hipGetSymbolAddress returned no address for the scratch array");
+        ptr[dev] = p;
+    }
+    return ptr[dev];
 }
 
 }  // namespace
@@ -860,6 +900,40 @@ tip_status tip_decompose_batch(int32_t n, const tip_edges* gs, const int32_t* si
             if (rc != TIP_OK) return rc;
         }
         return TIP_OK;
+    });
+}
+
+tip_status tip_decompose_noalloc(const int32_t* d_eu, const int32_t* d_ev, int32_t n_u, int32_t n_v, int64_t m,
+                                 int32_t side, int64_t* d_theta, void* stream, const tip_opts* opt, tip_stats* st) {
+    return guard([&]() -> tip_status {
+        if (n_u < 0 || n_v < 0 || m < 0 || m > INT32_MAX) throw InvalidArg("bad graph size");
+        if (m > 0 && (!d_eu || !d_ev)) throw InvalidArg("edge arrays are NULL");
+        if (side != TIP_SIDE_U && side != TIP_SIDE_V) throw InvalidArg("side must be 0 or 1");
+        const int32_t P = check_opts(opt);
+        const int32_t flags = opt ? opt->flags : 0;
+        if (flags & TIP_FLAG_TIME_KERNELS) throw InvalidArg("TIP_FLAG_TIME_KERNELS needs events, which this call does not create");
+        const bool a_is_u = side == TIP_SIDE_U;
+        const int32_t n_a = a_is_u ? n_u : n_v, n_b = a_is_u ? n_v : n_u;
+        if (n_a > 0 && !d_theta) throw InvalidArg("theta is NULL");
+        Work w;
+        w.no_alloc = true;
+        Arena sizer;
+        const int slots = resident_workgroups();
+        plan(sizer, n_a, n_b, m, P, slots, w);
+        if (sizer.off > kNoAllocScratchBytes)
+            throw AllocFailure("graph needs " + std::to_string(sizer.off) + " bytes of scratch; tip_decompose_noalloc "
+                               "holds " + std::to_string(kNoAllocScratchBytes) + " (use tip_decompose_async)");
+        Arena ar{static_cast<char*>(noalloc_scratch()), kNoAllocScratchBytes, 0};
+        plan(ar, n_a, n_b, m, P, slots, w);
+        const hipStream_t s = static_cast<hipStream_t>(stream);
+        // the scratch keeps the previous call's contents: the repeat-count
+        // spill area must start at zero (everything else is written before
+        // it is read, as with a fresh workspace)
+        fill_i32(w.spill.dense, 0, w.spill.stride * w.spill.slots, s);
+        RunOut out;
+        out.theta = d_theta;
+        return run(w, a_is_u ? d_eu : d_ev, a_is_u ? d_ev : d_eu, n_a, n_b, m, a_is_u, P, flags, tune_of(opt), true,
+                   out, st, s);
     });
 }
 

@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "TIP_OK", -1: "TIP_EINVAL", -2: "TIP_ENOMEM", -3: "TIP_EDEVIC
 
 # Every symbol declared in include/tip.h.
 EXPORTS = ["tip_count_butterflies", "tip_decompose", "tip_decompose_ex", "tip_decompose_batch",
-           "tip_workspace_size", "tip_decompose_async", "tip_last_error", "tip_device_count"]
+           "tip_workspace_size", "tip_decompose_async", "tip_decompose_noalloc", "tip_last_error",
+           "tip_device_count"]
 
 
 class TipError(RuntimeError):
@@ -100,7 +101,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
                                            ctypes.POINTER(ctypes.c_size_t)]
         lib.tip_decompose_async.argtypes = [vp, vp, i32, i32, i64, i32, vp, vp, ctypes.c_size_t, vp,
                                             ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
-        for name in EXPORTS[:6]:
+        lib.tip_decompose_noalloc.argtypes = [vp, vp, i32, i32, i64, i32, vp, vp, ctypes.POINTER(Opts),
+                                              ctypes.POINTER(Stats)]
+        for name in EXPORTS[:7]:
             getattr(lib, name).restype = ctypes.c_int32
         lib.tip_last_error.argtypes = []
         lib.tip_last_error.restype = ctypes.c_char_p
@@ -254,5 +257,29 @@ def decompose_async(d_eu, d_ev, n_u: int, n_v: int, side: int, d_theta, workspac
         ctypes.c_void_p(d_eu.data_ptr()), ctypes.c_void_p(d_ev.data_ptr()), int(n_u), int(n_v), m, int(side),
         ctypes.c_void_p(d_theta.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
         int(workspace.numel() * workspace.element_size()), ctypes.c_void_p(s), ctypes.byref(o),
+        ctypes.byref(st)))
+    return st.to_dict()
+
+
+NOALLOC_SCRATCH_BYTES = 512 << 20
+
+
+def decompose_noalloc(d_eu, d_ev, n_u: int, n_v: int, side: int, d_theta, stream=None, P: int = 0,
+                      flags: int = 0, tune=None) -> dict:
+    """tip_decompose_noalloc: like decompose_async, with the library's static
+    device scratch instead of a workspace (graphs whose workspace exceeds
+    NOALLOC_SCRATCH_BYTES are refused with TIP_ENOMEM).  Returns the stats."""
+    lib = load()
+    m = int(d_eu.numel())
+    if int(d_ev.numel()) != m:
+        raise ValueError("eu and ev differ in length")
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    st = Stats()
+    o = _opts(P, flags, 0, tune)
+    _check(lib, lib.tip_decompose_noalloc(
+        ctypes.c_void_p(d_eu.data_ptr()), ctypes.c_void_p(d_ev.data_ptr()), int(n_u), int(n_v), m, int(side),
+        ctypes.c_void_p(d_theta.data_ptr()), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(o),
         ctypes.byref(st)))
     return st.to_dict()
