@@ -13,6 +13,13 @@ product library never imports it.
 * ``support_levels(g, side, theta, query)``
                           f_x(S) for S = the side, theta >= theta_x and
                           theta > theta_x, from one build of the adjacency
+* ``canonical_edges(g)``  the simple edge list (duplicates merged, sorted by
+                          (u, v)); the edge order of the three calls below
+* ``edge_count(g)``       butterflies containing each canonical edge
+* ``wing(g)``             wing numbers by sequential bottom-up edge peeling
+* ``ktip(g, side, theta, k)``
+                          k-tips (Def. 1): butterfly-connected components of
+                          {theta >= k}, labelled by their smallest vertex id
 * ``brute``               exponential brute force for tiny graphs
 """
 from __future__ import annotations
@@ -25,7 +32,7 @@ import threading
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "tip_oracle.cpp")
+_SRCS = [os.path.join(_HERE, "tip_oracle.cpp"), os.path.join(_HERE, "wing_oracle.cpp")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -34,10 +41,10 @@ _lib = None
 def build(force: bool = False) -> str:
     """Compile the oracle with the host C++ compiler; returns the .so path."""
     if force or not os.path.exists(_LIB_PATH) or \
-            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(s) for s in _SRCS):
         tmp = _LIB_PATH + f".tmp{os.getpid()}"
         subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC",
-                               _SRC, "-o", tmp])
+                               *_SRCS, "-o", tmp])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -63,6 +70,14 @@ def _load(path: str | None = None):
     lib.oracle_support_in.restype = ctypes.c_int
     lib.oracle_support_levels.argtypes = [i32, i32, i64, p, p, i32, p, p, i64, p]
     lib.oracle_support_levels.restype = ctypes.c_int
+    lib.oracle_canonical_edges.argtypes = [i32, i32, i64, p, p, p, p, p]
+    lib.oracle_canonical_edges.restype = ctypes.c_int
+    lib.oracle_edge_count.argtypes = [i32, i32, i64, p, p, p]
+    lib.oracle_edge_count.restype = ctypes.c_int
+    lib.oracle_wing.argtypes = [i32, i32, i64, p, p, p, p, p]
+    lib.oracle_wing.restype = ctypes.c_int
+    lib.oracle_ktip.argtypes = [i32, i32, i64, p, p, i32, p, i64, p]
+    lib.oracle_ktip.restype = ctypes.c_int
     return lib
 
 
@@ -144,3 +159,55 @@ def support_levels(g, side: int, theta: np.ndarray, query: np.ndarray, lib=None)
     if rc != 0:
         raise ValueError("oracle_support_levels: invalid argument")
     return out
+
+
+def canonical_edges(g, lib=None):
+    """(cu int32[m'], cv int32[m']): duplicates merged, sorted by (u, v)."""
+    lib = lib or _load()
+    eu, ev = _edges(g)
+    cu = np.zeros(max(g.m, 1), np.int32)
+    cv = np.zeros(max(g.m, 1), np.int32)
+    mu = np.zeros(1, np.int64)
+    if lib.oracle_canonical_edges(g.n_u, g.n_v, g.m, _ptr(eu), _ptr(ev), _ptr(cu), _ptr(cv), _ptr(mu)) != 0:
+        raise ValueError("oracle_canonical_edges: invalid graph")
+    k = int(mu[0])
+    return cu[:k].copy(), cv[:k].copy()
+
+
+def edge_count(g, lib=None) -> np.ndarray:
+    """Butterflies containing each canonical edge: int64[m']."""
+    lib = lib or _load()
+    eu, ev = _edges(g)
+    k = canonical_edges(g, lib)[0].shape[0]
+    out = np.zeros(max(k, 1), np.int64)
+    if lib.oracle_edge_count(g.n_u, g.n_v, g.m, _ptr(eu), _ptr(ev), _ptr(out)) != 0:
+        raise ValueError("oracle_edge_count: invalid graph")
+    return out[:k]
+
+
+def wing(g, lib=None):
+    """Returns (psi int64[m'], peel order int64[m'], pairs examined)."""
+    lib = lib or _load()
+    eu, ev = _edges(g)
+    k = canonical_edges(g, lib)[0].shape[0]
+    psi = np.zeros(max(k, 1), np.int64)
+    order = np.zeros(max(k, 1), np.int64)
+    w = np.zeros(1, np.int64)
+    if lib.oracle_wing(g.n_u, g.n_v, g.m, _ptr(eu), _ptr(ev), _ptr(psi), _ptr(order), _ptr(w)) != 0:
+        raise ValueError("oracle_wing: invalid graph")
+    return psi[:k], order[:k], int(w[0])
+
+
+def ktip(g, side: int, theta: np.ndarray, k: int, lib=None) -> np.ndarray:
+    """k-tips of one side: int32 label per vertex (smallest id of its k-tip,
+    -1 when theta < k)."""
+    lib = lib or _load()
+    eu, ev = _edges(g)
+    n = g.n_u if side == 0 else g.n_v
+    theta = np.ascontiguousarray(theta, dtype=np.int64)
+    if theta.shape != (n,):
+        raise ValueError("ktip: one theta per vertex of the side")
+    out = np.zeros(max(n, 1), np.int32)
+    if lib.oracle_ktip(g.n_u, g.n_v, g.m, _ptr(eu), _ptr(ev), side, _ptr(theta), int(k), _ptr(out)) != 0:
+        raise ValueError("oracle_ktip: invalid argument")
+    return out[:n]

@@ -77,3 +77,98 @@ def tip_numbers(g, side: int = 0) -> np.ndarray:
     for x in range(n):
         theta[x] = fmin[member[:, x] == 1].max()
     return theta
+
+
+# ---------------------------------------------------------------------------
+# Edges and k-tips
+# ---------------------------------------------------------------------------
+
+def canonical(g):
+    """Distinct edges sorted by (u, v), as two int arrays."""
+    key = np.unique(g.eu.astype(np.int64) * max(g.n_v, 1) + g.ev.astype(np.int64))
+    return (key // max(g.n_v, 1)).astype(np.int64), (key % max(g.n_v, 1)).astype(np.int64)
+
+
+def _butterfly_list(g):
+    """Every butterfly as the four canonical edge ids it consists of."""
+    cu, cv = canonical(g)
+    eid = {(int(u), int(v)): i for i, (u, v) in enumerate(zip(cu, cv))}
+    out = []
+    for u1, u2 in itertools.combinations(range(g.n_u), 2):
+        for v1, v2 in itertools.combinations(range(g.n_v), 2):
+            es = [eid.get((u1, v1)), eid.get((u1, v2)), eid.get((u2, v1)), eid.get((u2, v2))]
+            if all(e is not None for e in es):
+                out.append(es)
+    return out, cu.shape[0]
+
+
+def edge_butterflies(g) -> np.ndarray:
+    """Butterflies containing each canonical edge, by 4-tuple enumeration."""
+    bf, m = _butterfly_list(g)
+    cnt = np.zeros(m, np.int64)
+    for es in bf:
+        for e in es:
+            cnt[e] += 1
+    return cnt
+
+
+def wing_numbers(g) -> np.ndarray:
+    """psi_e = max over edge sets S containing e of min over f in S of the
+    butterflies of f inside S (the k-wing analogue of Def. 1), enumerating
+    every edge subset (at most 16 edges)."""
+    bf, m = _butterfly_list(g)
+    if m > 16:
+        raise ValueError("brute force needs at most 16 edges")
+    psi = np.zeros(m, np.int64)
+    if m == 0:
+        return psi
+    masks = np.arange(1, 1 << m, dtype=np.int64)
+    member = ((masks[:, None] >> np.arange(m)[None, :]) & 1).astype(np.int64)
+    f = np.zeros((masks.shape[0], m), np.int64)
+    for es in bf:
+        inside = member[:, es].all(axis=1).astype(np.int64)
+        for e in es:
+            f[:, e] += inside
+    big = np.iinfo(np.int64).max
+    fmin = np.where(member == 1, f, big).min(axis=1)
+    for e in range(m):
+        psi[e] = fmin[member[:, e] == 1].max()
+    return psi
+
+
+def ktips(g, side: int, k: int) -> np.ndarray:
+    """Def. 1 read literally: the maximal vertex sets S of the side in which
+    every member takes part in at least k butterflies of the subgraph on S
+    and the whole other side, and every two members are joined by a chain of
+    members that pairwise share a butterfly; enumerates every subset (at most
+    12 vertices).  Returns each vertex's set labelled by its smallest member,
+    -1 outside every such set."""
+    a = dense(g)
+    if side == 1:
+        a = a.T.copy()
+    n = a.shape[0]
+    if n > 12:
+        raise ValueError("brute force needs at most 12 vertices on the side")
+    b = _pair_butterflies(a)
+    valid = []
+    for mask in range(1, 1 << n):
+        s = [x for x in range(n) if mask >> x & 1]
+        if min(sum(b[x, w] for w in s) for x in s) < k:
+            continue
+        seen, todo = {s[0]}, [s[0]]
+        while todo:
+            x = todo.pop()
+            for w in s:
+                if w not in seen and b[x, w] > 0:
+                    seen.add(w)
+                    todo.append(w)
+        if len(seen) == len(s):
+            valid.append(mask)
+    maximal = [s for s in valid if not any(t != s and (s & t) == s for t in valid)]
+    comp = np.full(n, -1, np.int64)
+    for s in maximal:
+        members = [x for x in range(n) if s >> x & 1]
+        for x in members:
+            assert comp[x] == -1, "maximal k-tips overlap"
+            comp[x] = members[0]
+    return comp
