@@ -220,6 +220,35 @@ tip_status tip_decompose_async(const int32_t* d_eu, const int32_t* d_ev, int32_t
 tip_status tip_decompose_noalloc(const int32_t* d_eu, const int32_t* d_ev, int32_t n_u, int32_t n_v, int64_t m,
                                  int32_t side, int64_t* d_theta, void* stream, const tip_opts* opt, tip_stats* st);
 
+/* Butterflies containing each edge: bfly_e[i] for input edge i (duplicates of
+ * one edge get the same value), and the total number of butterflies (every
+ * butterfly has four edges).  The edge analogue of the per-vertex counts of
+ * Section 2.1: for e = (u, v) it is the sum over u' != u adjacent to v of
+ * |N_u intersect N_u'| - 1.  bfly_e [m] or total may be NULL (not both when
+ * m > 0). */
+tip_status tip_count_edge_butterflies(const tip_edges* g, int64_t* bfly_e, int64_t* total);
+
+/* Wing numbers (edge peeling, the extension of the method to edges named in
+ * the Conclusion): psi[i] for input edge i is the largest k such that the edge
+ * lies in a k-wing, a subgraph in which every edge is in at least k
+ * butterflies.  Computed by level-synchronous bottom-up edge peeling: each
+ * round removes every live edge whose support is at most the current level,
+ * and a butterfly with several edges removed in the same round is taken out
+ * of the surviving edges' supports once, by its removed edge of smallest id.
+ * opt must be NULL or all zero.  st (NULL ok): wedges_count = wedges walked
+ * by the per-edge count, wedges_cd = (x', y'') pairs walked by peeling,
+ * pair_updates = support decrements, rounds = peeling rounds, fd_levels =
+ * distinct levels, m_unique; other fields 0. */
+tip_status tip_wing_decompose(const tip_edges* g, int64_t* psi, const tip_opts* opt, tip_stats* st);
+
+/* k-tips (Def. 1) of `side`: comp[x] = the smallest vertex id of the k-tip
+ * holding x, or -1 when theta[x] < k.  theta [n_side] holds the side's tip
+ * numbers (from tip_decompose); the k-tips are the butterfly-connected
+ * components of {x : theta[x] >= k}, two vertices being connected when they
+ * share at least two neighbours.  k may be any value (k <= 0 takes every
+ * vertex; a vertex in no butterfly is then a k-tip of its own). */
+tip_status tip_ktips(const tip_edges* g, int32_t side, const int64_t* theta, int64_t k, int32_t* comp);
+
 /* Message of the last failed call on this thread ("" if none).  Valid until
  * the next tip_* call on this thread. */
 const char* tip_last_error(void);

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtip.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["util.hip", "ingest.hip", "count.hip", "peel.hip", "fd.hip", "tip_api.hip"]
+SOURCES = ["util.hip", "ingest.hip", "count.hip", "peel.hip", "fd.hip", "wing.hip", "tip_api.hip"]
 ARCH = os.environ.get("TIP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -4,6 +4,7 @@
 // sequences launches and reads a small control block between CD rounds.
 #include <cmath>
 #include <cstdlib>
+#include <algorithm>
 #include <atomic>
 #include <cstring>
 #include <memory>
@@ -14,6 +15,7 @@
 #include "../../include/tip.h"
 #include "tip_ingest.h"
 #include "tip_kernels.h"
+#include "wing.h"
 
 // Scratch of tip_decompose_noalloc: one copy per device, held until the
 // process ends.  Host code never uses this name as an address (on the host it
@@ -934,6 +936,98 @@ tip_status tip_decompose_noalloc(const int32_t* d_eu, const int32_t* d_ev, int32
         out.theta = d_theta;
         return run(w, a_is_u ? d_eu : d_ev, a_is_u ? d_ev : d_eu, n_a, n_b, m, a_is_u, P, flags, tune_of(opt), true,
                    out, st, s);
+    });
+}
+
+// Host-pointer calls on the edge-peeling path: ingest, then wing_run or
+// ktip_run, results copied back in input order.
+struct EdgeCall {
+    StreamHolder sh;
+    WingWork w;
+    DeviceBuffer buf;
+    int32_t* d_eu = nullptr;
+    int32_t* d_ev = nullptr;
+    int64_t* d_scalar = nullptr;
+    int32_t* d_comp = nullptr;
+
+    EdgeCall(const tip_edges* g, bool ktip, int32_t side) {
+        const int64_t m = g->m;
+        const int32_t n_a = ktip && side == TIP_SIDE_V ? g->n_v : g->n_u;
+        const int32_t n_b = ktip && side == TIP_SIDE_V ? g->n_u : g->n_v;
+        const int slots = wing_slots();
+        Arena sizer;
+        wing_plan(sizer, n_a, n_b, m, slots, ktip, w);
+        const size_t extra = sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(m, 1) +
+                             sizeof(int32_t) * (size_t)std::max(n_a, 1) + 4096;
+        buf.alloc(sizer.off + extra);
+        Arena ar{static_cast<char*>(buf.p), sizer.off + extra, 0};
+        wing_plan(ar, n_a, n_b, m, slots, ktip, w);
+        d_eu = ar.take<int32_t>(std::max<int64_t>(m, 1));
+        d_ev = ar.take<int32_t>(std::max<int64_t>(m, 1));
+        d_scalar = ar.take<int64_t>(1);
+        d_comp = ar.take<int32_t>(std::max(n_a, 1));
+        if (m > 0) {
+            TIP_HIP_TRY(hipMemcpyAsync(d_eu, g->eu, sizeof(int32_t) * m, hipMemcpyHostToDevice, sh.s));
+            TIP_HIP_TRY(hipMemcpyAsync(d_ev, g->ev, sizeof(int32_t) * m, hipMemcpyHostToDevice, sh.s));
+        }
+    }
+};
+
+tip_status tip_count_edge_butterflies(const tip_edges* g, int64_t* bfly_e, int64_t* total) {
+    return guard([&]() -> tip_status {
+        check_edges(g);
+        if (g->m > 0 && !bfly_e && !total) throw InvalidArg("bfly_e and total are both NULL");
+        EdgeCall c(g, false, TIP_SIDE_U);
+        const hipStream_t s = c.sh.s;
+        const int64_t m = g->m;
+        const tip_status rc = wing_run(c.w, c.d_eu, c.d_ev, g->n_u, g->n_v, m, false, c.w.out, nullptr, s);
+        if (rc != TIP_OK) return rc;
+        int64_t sum = 0;
+        if (total && c.w.g.m > 0) {
+            k_sum_i64<<<1, 1024, 0, s>>>(c.w.supp, (int32_t)c.w.g.m, c.d_scalar);
+            TIP_HIP_TRY(hipGetLastError());
+            TIP_HIP_TRY(hipMemcpyAsync(&sum, c.d_scalar, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        }
+        if (m > 0 && bfly_e)
+            TIP_HIP_TRY(hipMemcpyAsync(bfly_e, c.w.out, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s));
+        TIP_HIP_TRY(hipStreamSynchronize(s));
+        if (total) *total = sum / 4;  // every butterfly has four edges
+        return TIP_OK;
+    });
+}
+
+tip_status tip_wing_decompose(const tip_edges* g, int64_t* psi, const tip_opts* opt, tip_stats* st) {
+    return guard([&]() -> tip_status {
+        check_edges(g);
+        if (g->m > 0 && !psi) throw InvalidArg("psi is NULL");
+        if (opt && (opt->P != 0 || opt->flags != 0 || std::any_of(opt->tune, opt->tune + 8, [](int32_t t) { return t != 0; })))
+            throw InvalidArg("tip_wing_decompose takes no options yet: opt must be NULL or all zero");
+        EdgeCall c(g, false, TIP_SIDE_U);
+        const hipStream_t s = c.sh.s;
+        const int64_t m = g->m;
+        const tip_status rc = wing_run(c.w, c.d_eu, c.d_ev, g->n_u, g->n_v, m, true, c.w.out, st, s);
+        if (rc != TIP_OK) return rc;
+        if (m > 0) TIP_HIP_TRY(hipMemcpyAsync(psi, c.w.out, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s));
+        TIP_HIP_TRY(hipStreamSynchronize(s));
+        return TIP_OK;
+    });
+}
+
+tip_status tip_ktips(const tip_edges* g, int32_t side, const int64_t* theta, int64_t k, int32_t* comp) {
+    return guard([&]() -> tip_status {
+        check_edges(g);
+        if (side != TIP_SIDE_U && side != TIP_SIDE_V) throw InvalidArg("side must be 0 (U) or 1 (V)");
+        const int32_t n_side = side == TIP_SIDE_U ? g->n_u : g->n_v;
+        if (n_side > 0 && (!theta || !comp)) throw InvalidArg("theta or comp is NULL");
+        for (int32_t x = 0; x < n_side; ++x)
+            if (theta[x] < 0) throw InvalidArg("tip numbers are never negative");
+        EdgeCall c(g, true, side);
+        const hipStream_t s = c.sh.s;
+        const tip_status rc = ktip_run(c.w, c.d_eu, c.d_ev, g->n_u, g->n_v, g->m, side, theta, k, c.d_comp, s);
+        if (rc != TIP_OK) return rc;
+        if (n_side > 0) TIP_HIP_TRY(hipMemcpyAsync(comp, c.d_comp, sizeof(int32_t) * n_side, hipMemcpyDeviceToHost, s));
+        TIP_HIP_TRY(hipStreamSynchronize(s));
+        return TIP_OK;
     });
 }
 

@@ -30,8 +30,8 @@ STATUS_NAMES = {0: "TIP_OK", -1: "TIP_EINVAL", -2: "TIP_ENOMEM", -3: "TIP_EDEVIC
 
 # Every symbol declared in include/tip.h.
 EXPORTS = ["tip_count_butterflies", "tip_decompose", "tip_decompose_ex", "tip_decompose_batch",
-           "tip_workspace_size", "tip_decompose_async", "tip_decompose_noalloc", "tip_last_error",
-           "tip_device_count"]
+           "tip_workspace_size", "tip_decompose_async", "tip_decompose_noalloc", "tip_count_edge_butterflies",
+           "tip_wing_decompose", "tip_ktips", "tip_last_error", "tip_device_count"]
 
 
 class TipError(RuntimeError):
@@ -103,7 +103,10 @@ def load(path: str | None = None) -> ctypes.CDLL:
                                             ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
         lib.tip_decompose_noalloc.argtypes = [vp, vp, i32, i32, i64, i32, vp, vp, ctypes.POINTER(Opts),
                                               ctypes.POINTER(Stats)]
-        for name in EXPORTS[:7]:
+        lib.tip_count_edge_butterflies.argtypes = [ctypes.POINTER(Edges), vp, vp]
+        lib.tip_wing_decompose.argtypes = [ctypes.POINTER(Edges), vp, ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
+        lib.tip_ktips.argtypes = [ctypes.POINTER(Edges), i32, vp, i64, vp]
+        for name in EXPORTS[:10]:
             getattr(lib, name).restype = ctypes.c_int32
         lib.tip_last_error.argtypes = []
         lib.tip_last_error.restype = ctypes.c_char_p
@@ -283,3 +286,37 @@ def decompose_noalloc(d_eu, d_ev, n_u: int, n_v: int, side: int, d_theta, stream
         ctypes.c_void_p(d_theta.data_ptr()), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(o),
         ctypes.byref(st)))
     return st.to_dict()
+
+
+def count_edge_butterflies(g):
+    """Butterflies containing each input edge: (int64[m], total)."""
+    lib = load()
+    e, keep = _edges(g)
+    out = np.zeros(max(g.m, 1), np.int64)
+    tot = np.zeros(1, np.int64)
+    _check(lib, lib.tip_count_edge_butterflies(ctypes.byref(e), _ptr(out), _ptr(tot)))
+    return out[:g.m], int(tot[0])
+
+
+def wing_decompose(g, with_stats: bool = False):
+    """Wing number of each input edge: int64[m] (and the stats)."""
+    lib = load()
+    e, keep = _edges(g)
+    out = np.zeros(max(g.m, 1), np.int64)
+    st = Stats()
+    _check(lib, lib.tip_wing_decompose(ctypes.byref(e), _ptr(out), None, ctypes.byref(st)))
+    return (out[:g.m], st.to_dict()) if with_stats else out[:g.m]
+
+
+def ktips(g, side: int, theta, k: int):
+    """k-tips of one side: int32 label per vertex (smallest id of its k-tip,
+    -1 when theta < k)."""
+    lib = load()
+    e, keep = _edges(g)
+    n = g.n_u if side == SIDE_U else g.n_v
+    theta = np.ascontiguousarray(theta, dtype=np.int64)
+    if theta.shape != (n,):
+        raise ValueError("one tip number per vertex of the side")
+    comp = np.zeros(max(n, 1), np.int32)
+    _check(lib, lib.tip_ktips(ctypes.byref(e), int(side), _ptr(theta), int(k), _ptr(comp)))
+    return comp[:n]

@@ -54,7 +54,8 @@ def _build(tmp_path, name, edit):
     cpp = tmp_path / f"{name}.cpp"
     so = tmp_path / f"lib{name}.so"
     cpp.write_text(src)
-    subprocess.check_call(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", str(cpp), "-o", str(so)])
+    wing = os.path.join(os.path.dirname(SRC), "wing_oracle.cpp")
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", str(cpp), wing, "-o", str(so)])
     return oracle._load(str(so))
 
 
