@@ -131,6 +131,8 @@ struct FdLds {
     int32_t spill_n;
     int32_t flag;
     int32_t wave_head;   // next per-wave update of the level
+    int32_t lcnt[4];     // list lengths of a level's partition: kept, per-wave, heavy
+    unsigned long long hw;  // induced wedges of a level's heavy vertices
     int64_t hx_off[kFdHeavyPre];  // row offset and degree of a level's heavy vertices
     int32_t hx_deg[kFdHeavyPre];
 };
@@ -239,13 +241,29 @@ static_assert(sizeof(FdLds::Shared) >= (size_t)kFdWaveKeys * (kFdThreads / kWave
 // Decrements of the subset's dead vertices are applied too: their support is
 // never read again (each level reads the live list only), and skipping the
 // liveness load shortens every update's chain of memory round trips.
+//
+// With `cx` set (a step that peels few vertices), every decrement returns the
+// old support, and a vertex whose support crosses from above the level to
+// at or below it is appended to cx: exactly the live vertices the next step
+// at the same level must peel (a support crosses once; vertices already at
+// or below the level, live or dead, never cross).
 struct FdHbmState {
     int64_t* sup;
     int32_t* alive;
     const int32_t* vert;
+    int32_t* cx = nullptr;    // crossing list, or nullptr
+    int32_t* cxn = nullptr;   // its length (LDS)
+    int64_t level = 0;
     __device__ inline bool live(int32_t) const { return true; }
     __device__ inline int32_t vtx(int32_t x) const { return vert[x]; }
-    __device__ inline void dec(int32_t w, int64_t d) const { atomic_add_i64(&sup[w], -d); }
+    __device__ inline void dec(int32_t w, int64_t d) const {
+        if (!cx) {
+            atomic_add_i64(&sup[w], -d);
+            return;
+        }
+        const int64_t old = atomic_add_i64_ret(&sup[w], -d);
+        if (old > level && old - d <= level) cx[atomicAdd(cxn, 1)] = w;
+    }
 };
 
 struct FdLdsState {
@@ -501,6 +519,38 @@ __device__ inline void fd_heavy_level(const DevGraph& g, const FdBuffers& fb, Fd
     }
 }
 
+// Heavy updates taken one at a time from a help-board slot until its
+// published heavy list is exhausted; the whole workgroup does each (its LDS
+// bitmap and repeat table, its own spill area).  Finished entries are
+// counted in hdone after their decrements are visible device-wide.  All
+// threads call.
+template <class St>
+__device__ inline void fd_heavy_take(const DevGraph& g, const FdBuffers& fb, FdLds& L, const Spill& sp,
+                                     const int32_t* ph, int32_t n_i, FdHelpSlot* hs, const St& st,
+                                     unsigned long long& wedges, unsigned long long& pairs,
+                                     unsigned long long& spills) {
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long wv = atomicAdd(&hs->hword, 1ull);
+            const uint32_t q = (uint32_t)wv, n = (uint32_t)(wv >> 32);
+            L.flag = q < n ? (int32_t)q : -1;
+        }
+        __syncthreads();
+        const int32_t q = L.flag;
+        if (q < 0) break;
+        __threadfence();
+        const int32_t x = ph[q];
+        const int32_t ux = st.vtx(x);
+        const int64_t e0 = g.a_off[ux], d = g.a_off[ux + 1] - e0;
+        fd_update_heavy(g, fb, L, sp, x, e0, d, n_i, st, wedges, pairs, spills);
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(&hs->hdone, 1);
+    }
+    __syncthreads();
+}
+
 // Per-wave updates taken from a help-board slot until its published list is
 // exhausted: one atomic on the slot word hands out `chunk` entries;
 // finished entries are counted in `done` after their decrements are visible
@@ -544,6 +594,19 @@ __device__ inline bool fd_heavy(const DevGraph& g, const FdBuffers& fb, int64_t 
     return w > kFdWaveMax;
 }
 
+// Position in an LDS-counted list for the lanes of the calling wave with
+// pred; one LDS atomic per wave.  Every lane of the wave must call.
+__device__ inline int32_t fd_wave_slot(bool pred, int32_t* counter) {
+    const uint64_t m = __ballot(pred);
+    if (m == 0) return 0;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (int32_t)__popcll(m));
+    base = __shfl(base, leader, kWave);
+    return base + (int32_t)__popcll(m & lanemask_lt());
+}
+
 // Level loop of a subset whose state lives in HBM.
 __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const int64_t* __restrict__ init,
                                    int64_t P0, int32_t n_i, FdLds& L, unsigned long long* tab, const Spill& sp,
@@ -551,17 +614,17 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
                                    unsigned long long& wedges, unsigned long long& pairs,
                                    unsigned long long& levels, unsigned long long& spills) {
     constexpr int NT = kFdThreads;
-    constexpr int NW = NT / kWave;
     const int tid = threadIdx.x, wid = tid / kWave;
     int32_t* lc = fb.lst[0] + P0;
     int32_t* ln = fb.lst[1] + P0;
     int32_t* pl = fb.lst[2] + P0;
     int32_t* ph = fb.lst[3] + P0;
+    int32_t* cx = fb.lst[4] + P0;
     int64_t* sup = fb.supp_fd + P0;
     const int64_t* fw = fb.fd_w + P0;
     int32_t* alive = fb.alive + P0;
     const int32_t* vert = fb.fd_vert + P0;
-    const FdHbmState st{sup, alive, vert};
+    FdHbmState st{sup, alive, vert};
     const bool wave_dense = n_i <= kFdWaveKeys;
     uint32_t* wcnt = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(&L.u) + (size_t)wid * kFdWaveKeys);
     for (int32_t j = tid; j < n_i; j += NT) {
@@ -570,53 +633,119 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
         alive[j] = kFdAlive | (fd_heavy(g, fb, P0, n_i, j) ? kFdHeavy : 0);
     }
     __syncthreads();
+    // lc: the live list (it may still hold vertices peeled by later steps of
+    // a level; the next full pass drops them)
     int32_t n_live = n_i;
+    int32_t n_cx = -1;  // >= 0: the next step peels the crossing list cx instead
     int64_t level = 0;
-    while (n_live > 0) {
-        int64_t mn = INT64_MAX;
-        for (int32_t j = tid; j < n_live; j += NT) {
-            const int64_t sv = sup[lc[j]];
-            mn = sv < mn ? sv : mn;
+    // Full passes over the live list stride through it with kFdPassUnroll
+    // entries per thread loaded before any is used, so that many of the
+    // list's dependent loads (entry, then support) are in flight together;
+    // partitions append through one LDS atomic per wave and list.
+    constexpr int U = kFdPassUnroll;
+    for (;;) {
+        if (tid < 4) L.lcnt[tid] = 0;
+        if (tid == 0) {
+            L.wave_head = 0;
+            L.hw = 0;
         }
-        mn = fd_min<NT>(L, mn);
-        level = mn > level ? mn : level;
-        // peel every live vertex at or below the level; per-wave and heavy
-        // ones go to separate lists, vertices without support left need no
-        // update at all.  Each thread takes a contiguous run of the live
-        // list; one block scan of packed counts gives every offset.
-        const int32_t per = (n_live + NT - 1) / NT;
-        const int32_t j0 = min(n_live, tid * per), j1 = min(n_live, j0 + per);
-        int64_t cnt = 0;
-        for (int32_t j = j0; j < j1; ++j) {
-            const int32_t x = lc[j];
-            const int64_t sx = sup[x];
-            if (sx > level) cnt += 1ll << (2 * kFdPack);
-            else if (sx > 0) cnt += (alive[x] & kFdHeavy) ? (1ll << kFdPack) : 1ll;
-        }
-        int64_t tot;
-        int64_t off = fd_scan_i64<NT>(L, cnt, tot);
-        const int64_t pm = (1ll << kFdPack) - 1;
-        int32_t ol = (int32_t)(off & pm), oh = (int32_t)((off >> kFdPack) & pm), ok = (int32_t)(off >> (2 * kFdPack));
-        if (tid == 0) L.wave_head = 0;
-        const int32_t n_light = (int32_t)(tot & pm), n_heavy = (int32_t)((tot >> kFdPack) & pm);
-        const int32_t n_keep = (int32_t)(tot >> (2 * kFdPack));
-        for (int32_t j = j0; j < j1; ++j) {
-            const int32_t x = lc[j];
-            const int64_t sx = sup[x];
-            if (sx > level) {
-                ln[ok++] = x;
-            } else {
+        if (n_cx < 0) {
+            if (n_live == 0) break;
+            int64_t mn = INT64_MAX;
+            for (int32_t b0 = 0; b0 < n_live; b0 += NT * U) {
+                int32_t xs[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t j = b0 + u * NT + tid;
+                    xs[u] = j < n_live ? lc[j] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (xs[u] < 0) continue;
+                    const int64_t sv = sup[xs[u]];
+                    if ((alive[xs[u]] & kFdAlive) && sv < mn) mn = sv;
+                }
+            }
+            mn = fd_min<NT>(L, mn);
+            if (mn == INT64_MAX) break;  // every entry left was peeled
+            level = mn > level ? mn : level;
+            // peel every live vertex at or below the level; per-wave and
+            // heavy ones go to separate lists, vertices without support left
+            // need no update at all
+            for (int32_t b0 = 0; b0 < n_live; b0 += NT * U) {
+                int32_t xs[U], fl[U];
+                int64_t ss[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t j = b0 + u * NT + tid;
+                    xs[u] = j < n_live ? lc[j] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    ss[u] = xs[u] >= 0 ? sup[xs[u]] : 0;
+                    fl[u] = xs[u] >= 0 ? alive[xs[u]] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t x = xs[u];
+                    const bool is_live = x >= 0 && (fl[u] & kFdAlive);
+                    const bool keep = is_live && ss[u] > level;
+                    const bool peel = is_live && !keep;
+                    const bool heavy = peel && ss[u] > 0 && (fl[u] & kFdHeavy);
+                    const bool light = peel && ss[u] > 0 && !(fl[u] & kFdHeavy);
+                    const int32_t pk = fd_wave_slot(keep, &L.lcnt[0]);
+                    const int32_t pw = fd_wave_slot(light, &L.lcnt[1]);
+                    const int32_t pq = fd_wave_slot(heavy, &L.lcnt[2]);
+                    if (keep) ln[pk] = x;
+                    if (light) pl[pw] = x;
+                    if (heavy) {
+                        ph[pq] = x;
+                        atomicAdd(&L.hw, (unsigned long long)fw[x]);
+                    }
+                    if (peel) {
+                        alive[x] = fl[u] & ~kFdAlive;
+                        fb.theta[vert[x]] = level;
+                    }
+                }
+            }
+            __syncthreads();
+            int32_t* tmp = lc;
+            lc = ln;
+            ln = tmp;
+            n_live = L.lcnt[0];
+        } else {
+            // the vertices the last step dropped to the level: all live
+            __syncthreads();
+            for (int32_t j = tid; j < n_cx; j += NT) {
+                const int32_t x = cx[j];
+                const int64_t sx = sup[x];
                 const int32_t f = alive[x];
                 alive[x] = f & ~kFdAlive;
                 fb.theta[vert[x]] = level;
                 if (sx > 0) {
-                    if (f & kFdHeavy) ph[oh++] = x;
-                    else pl[ol++] = x;
+                    if (f & kFdHeavy) {
+                        ph[atomicAdd(&L.lcnt[2], 1)] = x;
+                        atomicAdd(&L.hw, (unsigned long long)fw[x]);
+                    } else {
+                        pl[atomicAdd(&L.lcnt[1], 1)] = x;
+                    }
                 }
             }
+            __syncthreads();
         }
+        const int32_t n_light = L.lcnt[1], n_heavy = L.lcnt[2];
         levels += tid == 0;
-        if (hs && n_light >= help_level_min) {
+        const bool publish = hs && n_light >= help_level_min;
+        // heavy updates are shared only when there are several and enough
+        // wedges to outweigh the board's fences
+        const bool publish_heavy = hs && n_heavy >= kFdHelpHeavyMin && L.hw >= (unsigned long long)kFdHelpHeavyWedges;
+        // a small step (not published, so no helper decrements) tracks the
+        // vertices it drops to the level
+        const bool track = !publish && !publish_heavy && n_light + n_heavy <= kFdCascadeMax;
+        st.cx = track ? cx : nullptr;
+        st.cxn = &L.lcnt[3];
+        st.level = level;
+        if (publish) {
             // publish the level's per-wave updates on the help board, take
             // entries like the helpers do, then wait for every taken entry
             // (levels with fewer updates are not worth the fences)
@@ -644,11 +773,28 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
             }
         }
         __syncthreads();
-        fd_heavy_level(g, fb, L, sp, ph, n_heavy, n_i, st, wedges, pairs, spills);
-        int32_t* tmp = lc;
-        lc = ln;
-        ln = tmp;
-        n_live = n_keep;
+        if (publish_heavy) {
+            // the heavy updates go on the help board too: every workgroup
+            // helping this subset takes whole heavy vertices
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) {
+                atomicExch(&hs->hdone, 0);
+                __threadfence();
+                atomicExch(&hs->hword, (unsigned long long)n_heavy << 32);
+            }
+            fd_heavy_take(g, fb, L, sp, ph, n_i, hs, st, wedges, pairs, spills);
+            if (tid == 0)
+                while (__hip_atomic_load(&hs->hdone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n_heavy)
+                    __builtin_amdgcn_s_sleep(2);
+            __syncthreads();
+            __threadfence();
+        } else {
+            fd_heavy_level(g, fb, L, sp, ph, n_heavy, n_i, st, wedges, pairs, spills);
+        }
+        __syncthreads();
+        n_cx = track && L.lcnt[3] > 0 ? L.lcnt[3] : -1;
+        __syncthreads();
     }
 }
 
@@ -802,6 +948,8 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
                         h.P0 = P0;
                         h.word = 0;
                         h.done = 0;
+                        h.hword = 0;
+                        h.hdone = 0;
                         __threadfence();
                         atomicExch(&h.state, 1);
                     }
@@ -839,6 +987,11 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
                 FdHelpSlot* hs = &board->slot[k];
                 if (__hip_atomic_load(&hs->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 1) continue;
                 pick = -2;
+                const unsigned long long hv = __hip_atomic_load(&hs->hword, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((uint32_t)hv < (uint32_t)(hv >> 32)) {
+                    pick = kFdHelpSlots + k;  // heavy entries to take
+                    break;
+                }
                 const unsigned long long wv = __hip_atomic_load(&hs->word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if ((uint32_t)wv < (uint32_t)(wv >> 32)) pick = k;
             }
@@ -848,7 +1001,24 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
         const int32_t k = L.flag;
         __syncthreads();
         if (k == -1) break;
-        if (k >= 0) {
+        if (k >= kFdHelpSlots) {
+            __threadfence();
+            FdHelpSlot* hs = &board->slot[k - kFdHelpSlots];
+            const FdJob& J = hs->job >= 0 ? jobs.list[hs->job] : jobs.one;
+            const FdBuffers& fb = J.fb;
+            const int64_t P0 = hs->P0;
+            const FdHbmState st{fb.supp_fd + P0, fb.alive + P0, fb.fd_vert + P0};
+            unsigned long long wedges = 0, pairs = 0, spills = 0;
+            fd_heavy_take(J.g, fb, L, sp, fb.lst[3] + P0, hs->n_i, hs, st, wedges, pairs, spills);
+            wedges = (unsigned long long)wave_sum_i64((int64_t)wedges);
+            pairs = (unsigned long long)wave_sum_i64((int64_t)pairs);
+            spills = (unsigned long long)wave_sum_i64((int64_t)spills);
+            if (lane == 0) {
+                if (wedges) atomicAdd(&J.ctl->wedges_fd, wedges);
+                if (pairs) atomicAdd(&J.ctl->pair_updates, pairs);
+                if (spills) atomicAdd(&J.ctl->spills, spills);
+            }
+        } else if (k >= 0) {
             __threadfence();
             FdHelpSlot* hs = &board->slot[k];
             const FdJob& J = hs->job >= 0 ? jobs.list[hs->job] : jobs.one;

@@ -112,7 +112,7 @@ void plan(Arena& ar, int32_t n_a, int32_t n_b, int64_t m, int32_t P, int slots, 
     w.fb.supp_fd = ar.take<int64_t>(na);
     w.fb.fd_w = ar.take<int64_t>(na);
     w.fb.alive = ar.take<int32_t>(na);
-    for (int i = 0; i < 4; ++i) w.fb.lst[i] = ar.take<int32_t>(na);
+    for (int i = 0; i < 5; ++i) w.fb.lst[i] = ar.take<int32_t>(na);
     w.fb.theta = ar.take<int64_t>(na);
     w.fb.board = ar.take<FdBoard>(1);
     w.ctl = ar.take<Ctl>(1);

@@ -93,6 +93,10 @@ constexpr int64_t kFdWaveDenseMax = 1024;  // ... for peeled vertices with at mo
 constexpr int kFdHelpMin = 4096;          // subsets from this size let idle workgroups take their per-wave updates
 constexpr int kFdHelpChunk = 16;          // per-wave updates taken at once from a help-board slot
 constexpr int kFdHelpLevelMin = 256;      // levels with fewer per-wave updates are not published
+constexpr int kFdPassUnroll = 8;          // live-list entries per thread in flight in a level's passes
+constexpr int kFdHelpHeavyMin = 2;        // levels with this many heavy updates of a large subset publish them,
+constexpr int64_t kFdHelpHeavyWedges = 1 << 18;  // ... when they hold at least this many induced wedges
+constexpr int kFdCascadeMax = 64;         // a step peeling at most this many vertices tracks the ones it drops to the level
 
 constexpr int32_t kLive = -1;              // subset id of a vertex not yet assigned
 

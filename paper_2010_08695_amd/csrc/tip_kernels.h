@@ -120,6 +120,8 @@ struct CompactScratch {
 struct FdHelpSlot {
     unsigned long long word;  // (published entries << 32) | next entry to take
     int32_t done;             // entries of the published level finished
+    int32_t hdone;            // heavy entries of the published level finished
+    unsigned long long hword; // heavy updates: (published << 32) | next to take
     int32_t state;            // 0 unused, 1 open, 2 closed
     int32_t job;              // index in the job list, -1 for the single job
     int32_t n_i;              // subset size
@@ -146,7 +148,7 @@ struct FdBuffers {
     int64_t* supp_fd;    // [n_a] by subset position
     int64_t* fd_w;       // [n_a] wedges of each vertex inside its subset's subgraph, by position
     int32_t* alive;      // [n_a] by subset position
-    int32_t* lst[4];     // [n_a] live / next-live / light-peel / heavy-peel lists by subset position
+    int32_t* lst[5];     // [n_a] live / next-live / light-peel / heavy-peel / crossing lists by subset position
     int64_t* theta;      // [n_a] by rank
     FdBoard* board;      // task queue and help board of the launch
 };
