@@ -9,6 +9,7 @@ minutes-long oracle.
     python tests/golden/make_golden.py plain-small cl-1m cl-10m
     python tests/golden/make_golden.py batch-64 [--procs 6]
     python tests/golden/make_golden.py cl-100m-skew     # V side only
+    python tests/golden/make_golden.py cl-1m-wing       # per-edge counts and wing numbers of cl-1m
 
 ``batch-64`` holds one record per graph of the 64-graph batch workload (U
 side), computed in parallel, one oracle per process.  ``cl-100m-skew``
@@ -101,6 +102,27 @@ def make(name: str, sides=(0, 1), g=None) -> dict:
     return rec
 
 
+def make_wing(name: str) -> dict:
+    """Per-edge butterfly counts and wing numbers of a workload's edges, in
+    canonical order (duplicates merged, sorted by (u, v))."""
+    g = graphgen.config_graph(name)
+    rec = {"config": f"{name}-wing", "graph_sha256": graphgen.graph_sha256(g), "n_u": g.n_u, "n_v": g.n_v,
+           "m": g.m, "source": "oracle/wing_oracle.cpp", "host": host(), "order": "canonical (u, v)"}
+    t0 = time.time()
+    c = oracle.edge_count(g)
+    rec["edge_count"] = {"sha256": digest(c), "sum": int(c.sum()), "max": int(c.max()) if c.size else 0,
+                         "sample": sample(c, seed=5), "seconds": round(time.time() - t0, 2)}
+    print(name, "edge counts", rec["edge_count"]["seconds"], "s", flush=True)
+    t0 = time.time()
+    psi, _order, pairs = oracle.wing(g)
+    vals = np.unique(psi)
+    rec["wing"] = {"sha256": digest(psi), "max": int(psi.max()) if psi.size else 0, "sum": int(psi.sum()),
+                   "distinct": int(vals.shape[0]), "pairs": pairs, "sample": sample(psi, seed=6),
+                   "seconds": round(time.time() - t0, 2)}
+    print(name, "wing", rec["wing"]["seconds"], "s", flush=True)
+    return rec
+
+
 def _batch_one(p: dict) -> dict:
     g = graphgen.batch_graph(p)
     rec = make(g.name, sides=(0,), g=g)
@@ -129,6 +151,8 @@ def main(argv):
     for name in args.names:
         if name.startswith("batch-"):
             rec = make_batch(int(name.split("-")[1]), args.procs)
+        elif name.endswith("-wing"):
+            rec = make_wing(name[:-len("-wing")])
         elif name == "cl-100m-skew":
             rec = make(name, sides=(1,))
         else:
