@@ -157,9 +157,9 @@ def log(msg: str) -> None:
 
 def batch_record(P: int, count: int = 64, steps: int = 1) -> dict:
     """64 Chung-Lu graphs (m log-uniform in [1e4, 2e6], |U|:|V| in [1, 8],
-    exponents in [2.0, 2.8], U side): the batched form against the plain form
-    (one full decomposition after another), same API call, each once after a
-    warm-up; both checked against the oracle's stored per-graph digests."""
+    exponents in [2.0, 2.8], U side): the batched forms against the plain
+    form (one full decomposition after another), same API call, each once
+    after a warm-up; checked against the oracle's stored per-graph digests."""
     import numpy as np
 
     from paper_2010_08695_amd import autotune, graphgen, tip
@@ -168,32 +168,38 @@ def batch_record(P: int, count: int = 64, steps: int = 1) -> dict:
     sides = [0] * len(graphs)
     tunes = autotune.batch_tunes(graphs, sides)
     res = {}
-    for name, flags in (("batched", 0), ("plain", tip.TIP_FLAG_BATCH_PLAIN)):
-        tip.decompose_batch(graphs, sides, P=P, flags=flags, tunes=tunes)  # warm-up
+    # union: the batch as one disjoint-union decomposition (the default
+    # batched form); streams: graphs on concurrent streams with their stored
+    # tunings and one fine-grained launch; plain: one after another
+    forms = (("union", 0, None), ("streams", tip.TIP_FLAG_BATCH_STREAMS, tunes),
+             ("plain", tip.TIP_FLAG_BATCH_PLAIN, None))
+    for name, flags, tn in forms:
+        tip.decompose_batch(graphs, sides, P=P, flags=flags, tunes=tn)  # warm-up
         best, out, sts = None, None, None
         for _ in range(max(1, steps)):
             t0 = time.perf_counter()
-            out, sts = tip.decompose_batch(graphs, sides, P=P, with_stats=True, flags=flags, tunes=tunes)
+            out, sts = tip.decompose_batch(graphs, sides, P=P, with_stats=True, flags=flags, tunes=tn)
             dt = time.perf_counter() - t0
             best = dt if best is None or dt < best else best
         res[name] = (best, out, sts)
         log(f"batch {name}: {best:.3f} s")
-    same = all(np.array_equal(a, b) for a, b in zip(res["batched"][1], res["plain"][1]))
+    same = all(np.array_equal(a, b) and np.array_equal(a, c)
+               for a, b, c in zip(res["union"][1], res["streams"][1], res["plain"][1]))
     gold = load_golden(f"batch-{count}")
     golden_match = None
     if gold is not None and P == 150:
         golden_match = all(gr["graph_sha256"] == graphgen.graph_sha256(g) and
                            digest(th) == gr["theta_u"]["sha256"]
-                           for gr, g, th in zip(gold["graphs"], graphs, res["batched"][1]))
-    sts = res["batched"][2]
+                           for gr, g, th in zip(gold["graphs"], graphs, res["union"][1]))
+    sts = res["union"][2]
     wedges = sum(s["wedges_count"] + s["wedges_cd"] + s["wedges_fd"] for s in sts)
     return {"workload": f"batch-{len(graphs)}: Chung-Lu graphs, m log-uniform in [1e4, 2e6], "
                         f"sum m = {sum(g.m for g in graphs)}, side U, P={P}",
-            "wedges_per_s": wedges / res["batched"][0], "wedges": wedges,
-            "batched_s": res["batched"][0], "plain_s": res["plain"][0],
-            "speedup_vs_plain": res["plain"][0] / res["batched"][0],
+            "wedges_per_s": wedges / res["union"][0], "wedges": wedges,
+            "batched_s": res["union"][0], "streams_s": res["streams"][0], "plain_s": res["plain"][0],
+            "speedup_vs_plain": res["plain"][0] / res["union"][0],
             "same_results": same, "oracle_digests_match": golden_match,
-            "tuned_graphs": sum(1 for t in tunes if t is not None),
+            "streams_tuned_graphs": sum(1 for t in tunes if t is not None),
             "note": "host edge lists in, host tip numbers out (H2D/D2H and allocation included in both forms)"}
 
 

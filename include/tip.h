@@ -85,6 +85,13 @@ typedef struct {
  * Every opt[k].flags must be equal and carry this bit. */
 #define TIP_FLAG_OPTS_PER_GRAPH 16
 
+/* TIP_FLAG_BATCH_STREAMS: tip_decompose_batch runs the graphs' counting and
+ * coarse-grained steps concurrently on several host threads and streams,
+ * then one fine-grained launch over all graphs' subsets (the batched form
+ * used with TIP_FLAG_OPTS_PER_GRAPH, or when the batch's disjoint union
+ * would exceed 2^31 - 1 ids or edges); same results. */
+#define TIP_FLAG_BATCH_STREAMS 32
+
 /* Options.  Zero-initialised means defaults. */
 typedef struct {
     int32_t P;       /* number of tip-number ranges of the coarse-grained step
@@ -170,14 +177,19 @@ tip_status tip_decompose_ex(const tip_edges* g, int32_t side, int64_t* theta, co
                             int32_t* n_subsets);
 
 /* Decomposes n independent graphs: graph k's side sides[k] into thetas[k].
- * st may be NULL or point to n entries.  Batched form (default): the
- * graphs' counting and coarse-grained steps run concurrently on several
- * streams, then the fine-grained subsets of ALL graphs are peeled in one
- * persistent launch that takes (graph, subset) tasks from one queue ordered
- * by induced wedges (the workload-aware schedule of the Parallelization
- * Strategy section, applied across graphs).  Device memory for all graphs is
- * held until the call returns.  TIP_FLAG_BATCH_PLAIN runs the graphs one
- * after another instead.  Results are identical either way. */
+ * Batched form (default): the graphs, each with its decomposed side first,
+ * are laid side by side as one disjoint union (no butterfly joins two of
+ * them, so each part keeps its own tip numbers) and the union is decomposed
+ * once: one ingest, one count, one coarse-grained round loop whose rounds
+ * take every graph's activeSet, and one fine-grained launch over every
+ * graph's subsets.  st may be NULL or point to n entries; in this form
+ * st[0] receives the totals of the whole batch and the other entries are
+ * zero.  With TIP_FLAG_OPTS_PER_GRAPH, TIP_FLAG_BATCH_STREAMS, or a union
+ * beyond 2^31 - 1 ids or edges, the graphs run concurrently on host threads
+ * and streams instead, with one fine-grained launch over all graphs'
+ * subsets ordered by induced wedges, and st[k] holds graph k's figures.
+ * TIP_FLAG_BATCH_PLAIN runs one full decomposition after another.  Results
+ * are identical in every form. */
 tip_status tip_decompose_batch(int32_t n, const tip_edges* gs, const int32_t* sides, int64_t* const* thetas,
                                const tip_opts* opt, tip_stats* st);
 

@@ -492,8 +492,8 @@ void check_edges(const tip_edges* g) {
     }
 }
 
-constexpr int32_t kKnownFlags =
-    TIP_FLAG_TIME_KERNELS | TIP_FLAG_NO_GRAPH | TIP_FLAG_BATCH_PLAIN | TIP_FLAG_NO_COMPACT | TIP_FLAG_OPTS_PER_GRAPH;
+constexpr int32_t kKnownFlags = TIP_FLAG_TIME_KERNELS | TIP_FLAG_NO_GRAPH | TIP_FLAG_BATCH_PLAIN | TIP_FLAG_NO_COMPACT |
+                                TIP_FLAG_OPTS_PER_GRAPH | TIP_FLAG_BATCH_STREAMS;
 
 int32_t check_opts(const tip_opts* opt, bool batch = false) {
     if (!opt) return kDefaultP;
@@ -768,6 +768,89 @@ tip_status decompose_batched(int32_t n, const tip_edges* gs, const int32_t* side
     return TIP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batch as one graph: the graphs (each with its decomposed side as side A)
+// are laid side by side as one disjoint union -- graph k's A ids shifted by
+// the A vertices of the graphs before it, its B ids likewise -- and the
+// union is decomposed once.  No butterfly joins two graphs, so every
+// vertex's count, its f over any set and its tip number are those of its own
+// graph (tip numbers of a disjoint union are those of the parts); one
+// ingest, one count, one coarse-grained round loop over the whole batch's
+// activeSets (one device control block) and one fine-grained launch over
+// every graph's subsets.
+// ---------------------------------------------------------------------------
+
+__global__ void k_add_offset(int32_t* a, int64_t n, int32_t off) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] += off;
+}
+
+// false (nothing done) when the union exceeds the id or edge limits
+bool decompose_union(int32_t n, const tip_edges* gs, const int32_t* sides, int64_t* const* thetas, int32_t P,
+                     int32_t flags, const Tune& tune, tip_stats* st, tip_status& rc) {
+    int64_t na = 0, nb = 0, m = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const bool u = sides[k] == TIP_SIDE_U;
+        na += u ? gs[k].n_u : gs[k].n_v;
+        nb += u ? gs[k].n_v : gs[k].n_u;
+        m += gs[k].m;
+    }
+    if (na > INT32_MAX || nb > INT32_MAX || m > INT32_MAX) return false;
+    const int32_t n_a = (int32_t)na, n_b = (int32_t)nb;
+    StreamHolder sh;
+    const hipStream_t s = sh.s;
+    Work w;
+    const int slots = resident_workgroups();
+    Arena sizer;
+    plan(sizer, n_a, n_b, m, P, slots, w);
+    const size_t extra = sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(m, 1) +
+                         sizeof(int64_t) * (size_t)std::max<int32_t>(n_a, 1) + 4096;
+    DeviceBuffer buf;
+    buf.alloc(sizer.off + extra);
+    Arena ar{static_cast<char*>(buf.p), sizer.off + extra, 0};
+    plan(ar, n_a, n_b, m, P, slots, w);
+    int32_t* d_a = ar.take<int32_t>(std::max<int64_t>(m, 1));
+    int32_t* d_b = ar.take<int32_t>(std::max<int64_t>(m, 1));
+    int64_t* d_theta = ar.take<int64_t>(std::max<int32_t>(n_a, 1));
+    TIP_HIP_TRY(hipMemsetAsync(w.spill.dense, 0, sizeof(int32_t) * w.spill.stride * w.spill.slots, s));
+    std::vector<int32_t> off_a(n + 1, 0);
+    int64_t moff = 0;
+    int32_t ob = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const tip_edges& g = gs[k];
+        const bool u = sides[k] == TIP_SIDE_U;
+        const int32_t ka = u ? g.n_u : g.n_v, kb = u ? g.n_v : g.n_u;
+        if (g.m > 0) {
+            TIP_HIP_TRY(hipMemcpyAsync(d_a + moff, u ? g.eu : g.ev, sizeof(int32_t) * g.m, hipMemcpyHostToDevice, s));
+            TIP_HIP_TRY(hipMemcpyAsync(d_b + moff, u ? g.ev : g.eu, sizeof(int32_t) * g.m, hipMemcpyHostToDevice, s));
+            const unsigned grid = (unsigned)std::min<int64_t>(4096, (g.m + 255) / 256);
+            if (off_a[k]) k_add_offset<<<grid, 256, 0, s>>>(d_a + moff, g.m, off_a[k]);
+            if (ob) k_add_offset<<<grid, 256, 0, s>>>(d_b + moff, g.m, ob);
+            TIP_HIP_TRY(hipGetLastError());
+        }
+        moff += g.m;
+        off_a[k + 1] = off_a[k] + ka;
+        ob += kb;
+    }
+    RunOut out;
+    out.theta = d_theta;
+    tip_stats tot;
+    rc = run(w, d_a, d_b, n_a, n_b, m, true, P, flags, tune, true, out, st ? &tot : nullptr, s);
+    if (rc != TIP_OK) return true;
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t ka = off_a[k + 1] - off_a[k];
+        if (ka > 0)
+            TIP_HIP_TRY(hipMemcpyAsync(thetas[k], d_theta + off_a[k], sizeof(int64_t) * ka, hipMemcpyDeviceToHost, s));
+    }
+    TIP_HIP_TRY(hipStreamSynchronize(s));
+    if (st) {
+        // one decomposition: its totals go to graph 0, the other entries are 0
+        for (int32_t k = 0; k < n; ++k) std::memset(&st[k], 0, sizeof(tip_stats));
+        if (n > 0) st[0] = tot;
+    }
+    return true;
+}
+
 // Device address of `scratch` on the current device, looked up once per
 // device (with that device current) and kept.
 constexpr int kMaxDevices = 64;
@@ -893,7 +976,11 @@ tip_status tip_decompose_batch(int32_t n, const tip_edges* gs, const int32_t* si
             const int32_t n_side = sides[k] == TIP_SIDE_U ? gs[k].n_u : gs[k].n_v;
             if (n_side > 0 && !thetas[k]) throw InvalidArg("theta is NULL");
         }
-        const int32_t run_flags = flags & ~TIP_FLAG_OPTS_PER_GRAPH;
+        const int32_t run_flags = flags & ~(TIP_FLAG_OPTS_PER_GRAPH | TIP_FLAG_BATCH_STREAMS);
+        if (!(flags & (TIP_FLAG_BATCH_PLAIN | TIP_FLAG_BATCH_STREAMS)) && !per_graph && n > 0) {
+            tip_status rc = TIP_OK;
+            if (decompose_union(n, gs, sides, thetas, Ps[0], run_flags, tunes[0], st, rc)) return rc;
+        }
         if (!(flags & TIP_FLAG_BATCH_PLAIN)) return decompose_batched(n, gs, sides, thetas, Ps, run_flags, tunes, st);
         // the plain form: one full decomposition after another
         for (int32_t k = 0; k < n; ++k) {

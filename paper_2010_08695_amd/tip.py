@@ -24,6 +24,7 @@ TIP_FLAG_NO_GRAPH = 2
 TIP_FLAG_BATCH_PLAIN = 4
 TIP_FLAG_NO_COMPACT = 8
 TIP_FLAG_OPTS_PER_GRAPH = 16
+TIP_FLAG_BATCH_STREAMS = 32
 SIDE_U, SIDE_V = 0, 1
 STATUS_NAMES = {0: "TIP_OK", -1: "TIP_EINVAL", -2: "TIP_ENOMEM", -3: "TIP_EDEVICE",
                 -4: "TIP_EOVERFLOW", -5: "TIP_EBUSY"}

@@ -91,7 +91,7 @@ def test_decompose_rejects_bad_arguments(lib):
     o.P = 70000
     _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
     o = tip.Opts()
-    o.flags = 16                                  # no such flag
+    o.flags = 64                                  # no such flag
     _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
     o = tip.Opts()
     o.tune[1] = -1

@@ -232,20 +232,27 @@ def test_batch_matches_single(gpu_lib):
 
 
 def test_batch_forms_agree(gpu_lib):
-    """The batched form (concurrent graphs, one fine-grained launch over all
-    graphs' subsets) and the plain one-after-another form give the oracle's
-    tip numbers and the same per-graph work."""
+    """The batched forms (the batch as one disjoint union; the graphs on
+    concurrent streams with one fine-grained launch over all graphs' subsets)
+    and the plain one-after-another form give the oracle's tip numbers; the
+    streams form reports the same per-graph work as the plain one, and the
+    union's totals (in entry 0) cover every graph's count wedges."""
     params = gg.batch_params(12, seed_base=3000, m_lo=2e3, m_hi=4e4)
     gs = [gg.batch_graph(p) for p in params]
     sides = [k % 2 for k in range(len(gs))]
-    tb, sb = tip.decompose_batch(gs, sides, with_stats=True)
+    tu, su = tip.decompose_batch(gs, sides, with_stats=True)
+    ts, ss = tip.decompose_batch(gs, sides, with_stats=True, flags=tip.TIP_FLAG_BATCH_STREAMS)
     tp, sp = tip.decompose_batch(gs, sides, with_stats=True, flags=tip.TIP_FLAG_BATCH_PLAIN)
-    for g, s, a, b, x, y in zip(gs, sides, tb, tp, sb, sp):
+    for g, s, a, b, c in zip(gs, sides, tu, ts, tp):
         th = oracle.bup(g, s)[0]
         np.testing.assert_array_equal(a, th)
         np.testing.assert_array_equal(b, th)
+        np.testing.assert_array_equal(c, th)
+    for x, y in zip(ss, sp):
         for k in ("wedges_count", "wedges_cd", "wedges_fd", "pair_updates", "subsets", "fd_levels"):
             assert x[k] == y[k], k
+    assert su[0]["m_unique"] == sum(y["m_unique"] for y in sp)
+    assert all(x["m_unique"] == 0 for x in su[1:])
 
 
 def test_batch_with_empty_and_tiny_graphs(gpu_lib):
