@@ -173,6 +173,8 @@ int oracle_bup(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu, const int
     std::vector<char> gone(n, 0);
     std::vector<int32_t> co(n, 0);
     std::vector<int32_t> met;  // vertices with co > 0 for the vertex leaving
+    std::vector<int32_t> rest(n);  // every vertex still in the graph, and some that left
+    for (int32_t x = 0; x < n; ++x) rest[x] = x;
     int64_t walked = 0;
     int32_t left_graph = 0;
 
@@ -213,13 +215,18 @@ int oracle_bup(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu, const int
 
             // Bound the queue's memory: once stale entries dominate, file
             // every remaining vertex above the level afresh (those at the
-            // level are already in the bag).
+            // level are already in the bag).  `rest` drops the vertices that
+            // left, so this costs time in proportion to what remains.
             const int64_t remaining = static_cast<int64_t>(n) - left_graph;
             if (filed > 4 * remaining + 4096) {
                 queue.clear();
                 filed = 0;
-                for (int32_t z = 0; z < n; ++z)
-                    if (!gone[z] && supp[z] > level) {
+                size_t k = 0;
+                for (int32_t z : rest)
+                    if (!gone[z]) rest[k++] = z;
+                rest.resize(k);
+                for (int32_t z : rest)
+                    if (supp[z] > level) {
                         queue[supp[z]].push_back(z);
                         ++filed;
                     }

@@ -132,6 +132,8 @@ int oracle_wing(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu, const in
     int64_t filed = ne;
     std::vector<char> gone(ne, 0);
     std::vector<int64_t> tag(n_v, -1);  // tag[v'] = id of the remaining edge (u, v') of the edge leaving
+    std::vector<int64_t> rest(ne);         // every edge still in the graph, and some that left
+    for (int64_t e = 0; e < ne; ++e) rest[e] = e;
     int64_t examined = 0, left_graph = 0;
 
     while (!queue.empty()) {
@@ -180,8 +182,12 @@ int oracle_wing(int32_t n_u, int32_t n_v, int64_t m, const int32_t* eu, const in
             if (filed > 4 * remaining + 4096) {
                 queue.clear();
                 filed = 0;
-                for (int64_t f = 0; f < ne; ++f)
-                    if (!gone[f] && supp[f] > level) {
+                size_t k = 0;
+                for (int64_t f : rest)
+                    if (!gone[f]) rest[k++] = f;
+                rest.resize(k);
+                for (int64_t f : rest)
+                    if (supp[f] > level) {
                         queue[supp[f]].push_back(f);
                         ++filed;
                     }
