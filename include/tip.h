@@ -128,7 +128,15 @@ typedef struct {
                         updates of a level worth publishing (0 = 256),
                         tune[6] smallest subset that opens a slot (0 =
                         4096); the results do not change;
-                        tune[0..6] >= 0; tune[7] reserved, must be 0 */
+                        tune[7]: HUC in the fine-grained step (Section 4.1,
+                        last paragraph): a step of a subset kept in HBM
+                        whose peeled vertices' induced wedges exceed
+                        tune[7] percent of the live vertices' re-counts
+                        the live supports instead (support at the range
+                        start minus the butterflies shared with the
+                        subset's peeled vertices); 0 = never (the
+                        default); the results do not change;
+                        tune[0..7] >= 0 */
 } tip_opts;
 
 /* Work and time accounting of one decomposition (NULL = not wanted). */
@@ -153,6 +161,7 @@ typedef struct {
     double peel_ms;        /* summed launch time (TIP_FLAG_TIME_KERNELS), else 0 */
     double t_ingest_ms, t_count_ms, t_cd_ms, t_fd_ms, t_total_ms; /* device time per phase */
     int64_t huc_rounds;    /* coarse-grained rounds that re-counted instead of peeling (tune[3]) */
+    int64_t fd_huc_steps;  /* fine-grained steps that re-counted instead of peeling (tune[7]) */
 } tip_stats;
 
 /* Per-vertex butterfly counts of both sides (Alg. 1, Section 2.1) and the

@@ -133,6 +133,8 @@ struct FdLds {
     int32_t wave_head;   // next per-wave update of the level
     int32_t lcnt[4];     // list lengths of a level's partition: kept, per-wave, heavy
     unsigned long long hw;  // induced wedges of a level's heavy vertices
+    unsigned long long pw_all, pw_upd;  // induced wedges of a step's peeled vertices (all; with support left)
+    unsigned long long racc[kFdThreads / kWave];  // HUC re-count sums, per wave
     int64_t hx_off[kFdHeavyPre];  // row offset and degree of a level's heavy vertices
     int32_t hx_deg[kFdHeavyPre];
 };
@@ -264,6 +266,22 @@ struct FdHbmState {
         const int64_t old = atomic_add_i64_ret(&sup[w], -d);
         if (old > level && old - d <= level) cx[atomicAdd(cxn, 1)] = w;
     }
+};
+
+// HUC inside a subset (Section 4.1, last paragraph).  The support of a live
+// vertex u of subset i is its support at the range start (which counts the
+// butterflies with every vertex of this and later subsets) minus those it
+// shares with the vertices of U_i peeled so far; a re-count walks u's wedges
+// inside G_i and sums C(c(u, w), 2) over the peeled w.  As the "state" of
+// the update routines: the keys they apply to are the peeled ones, and
+// "decrementing" adds to the wave's (or workgroup's) accumulator.
+struct FdRecountState {
+    const int32_t* alive;
+    const int32_t* vert;
+    unsigned long long* acc;
+    __device__ inline bool live(int32_t w) const { return (alive[w] & kFdAlive) == 0; }
+    __device__ inline int32_t vtx(int32_t x) const { return vert[x]; }
+    __device__ inline void dec(int32_t, int64_t d) const { atomicAdd(acc, (unsigned long long)d); }
 };
 
 struct FdLdsState {
@@ -607,14 +625,88 @@ __device__ inline int32_t fd_wave_slot(bool pred, int32_t* counter) {
     return base + (int32_t)__popcll(m & lanemask_lt());
 }
 
+template <int NT>
+__device__ inline int64_t fd_block_sum(FdLds& L, int64_t x) {
+    x = wave_sum_i64(x);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) L.red[wid] = x;
+    __syncthreads();
+    int64_t s = 0;
+#pragma unroll
+    for (int w = 0; w < NT / kWave; ++w) s += L.red[w];
+    __syncthreads();
+    return s;
+}
+
+// HUC re-count of every live vertex of a subset kept in HBM: support = its
+// support at the range start minus the butterflies shared with the peeled
+// vertices of the subset.  Light vertices one per wave, heavy ones with the
+// whole workgroup; rl and rh (the step's peel lists, unused by a re-count
+// step) hold the two work lists.  All threads call, after a barrier.
+__device__ inline void fd_recount(const DevGraph& g, const FdBuffers& fb, FdLds& L, const Spill& sp,
+                                  const int32_t* lc, int32_t n_live, int32_t* rl, int32_t* rh,
+                                  const int32_t* alive, const int32_t* vert, int64_t* sup, const int64_t* fw,
+                                  const int64_t* __restrict__ init, int32_t n_i, bool wave_dense,
+                                  unsigned long long* tab, uint32_t* wcnt, unsigned long long& wedges,
+                                  unsigned long long& pairs, unsigned long long& spills) {
+    constexpr int NT = kFdThreads;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    if (tid < 4) L.lcnt[tid] = 0;
+    if (tid < NT / kWave) L.racc[tid] = 0;
+    if (tid == 0) L.wave_head = 0;
+    __syncthreads();
+    // the live vertices (the list may still hold some that were peeled)
+    for (int32_t b0 = 0; b0 < n_live; b0 += NT) {
+        const int32_t j = b0 + tid;
+        const int32_t x = j < n_live ? lc[j] : -1;
+        const int32_t f = x >= 0 ? alive[x] : 0;
+        const bool lv = (f & kFdAlive) != 0;
+        const bool hv = lv && (f & kFdHeavy) != 0;
+        const int32_t pw = fd_wave_slot(lv && !hv, &L.lcnt[1]);
+        const int32_t pq = fd_wave_slot(hv, &L.lcnt[2]);
+        if (lv && !hv) rl[pw] = x;
+        if (hv) rh[pq] = x;
+    }
+    __syncthreads();
+    const int32_t n_rl = L.lcnt[1], n_rh = L.lcnt[2];
+    const FdRecountState rs{alive, vert, &L.racc[wid]};
+    for (int32_t q = fd_next_wave_item(L); q < n_rl; q = fd_next_wave_item(L)) {
+        const int32_t x = rl[q];
+        if (wave_dense) fd_update_wave_dense(g, fb, L, wcnt, x, n_i, rs, wedges, pairs);
+        else fd_update_light(g, fb, L, tab, x, min<uint32_t>(kFdWaveSlots, wave_slots(fw[x])), rs, wedges, pairs);
+        if (lane == 0) {
+            sup[x] = init[vert[x]] - (int64_t)L.racc[wid];
+            L.racc[wid] = 0;
+        }
+        wave_sync();
+    }
+    __syncthreads();
+    const FdRecountState rw{alive, vert, &L.racc[0]};
+    for (int32_t q = 0; q < n_rh; ++q) {
+        const int32_t x = rh[q];
+        const int32_t ux = vert[x];
+        const int64_t e0 = g.a_off[ux], d = g.a_off[ux + 1] - e0;
+        // ends with a barrier, so every thread's share is in racc[0]
+        fd_update_heavy(g, fb, L, sp, x, e0, d, n_i, rw, wedges, pairs, spills);
+        if (tid == 0) {
+            sup[x] = init[vert[x]] - (int64_t)L.racc[0];
+            L.racc[0] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+
 // Level loop of a subset whose state lives in HBM.
 __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const int64_t* __restrict__ init,
                                    int64_t P0, int32_t n_i, FdLds& L, unsigned long long* tab, const Spill& sp,
-                                   FdHelpSlot* hs, int32_t help_chunk, int32_t help_level_min,
+                                   FdHelpSlot* hs, int32_t help_chunk, int32_t help_level_min, int32_t huc_pct,
                                    unsigned long long& wedges, unsigned long long& pairs,
-                                   unsigned long long& levels, unsigned long long& spills) {
+                                   unsigned long long& levels, unsigned long long& spills,
+                                   unsigned long long& huc_steps) {
     constexpr int NT = kFdThreads;
-    const int tid = threadIdx.x, wid = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     int32_t* lc = fb.lst[0] + P0;
     int32_t* ln = fb.lst[1] + P0;
     int32_t* pl = fb.lst[2] + P0;
@@ -627,11 +719,15 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
     FdHbmState st{sup, alive, vert};
     const bool wave_dense = n_i <= kFdWaveKeys;
     uint32_t* wcnt = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(&L.u) + (size_t)wid * kFdWaveKeys);
+    int64_t wsum = 0;
     for (int32_t j = tid; j < n_i; j += NT) {
         lc[j] = j;
         sup[j] = init[vert[j]];
         alive[j] = kFdAlive | (fd_heavy(g, fb, P0, n_i, j) ? kFdHeavy : 0);
+        wsum += fw[j];
     }
+    // induced wedges of the live vertices: the cost of a HUC re-count
+    int64_t w_live = huc_pct > 0 ? fd_block_sum<NT>(L, wsum) : 0;
     __syncthreads();
     // lc: the live list (it may still hold vertices peeled by later steps of
     // a level; the next full pass drops them)
@@ -648,6 +744,8 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
         if (tid == 0) {
             L.wave_head = 0;
             L.hw = 0;
+            L.pw_all = 0;
+            L.pw_upd = 0;
         }
         if (n_cx < 0) {
             if (n_live == 0) break;
@@ -705,6 +803,11 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
                     if (peel) {
                         alive[x] = fl[u] & ~kFdAlive;
                         fb.theta[vert[x]] = level;
+                        if (huc_pct > 0) {
+                            const unsigned long long wx = (unsigned long long)fw[x];
+                            atomicAdd(&L.pw_all, wx);
+                            if (ss[u] > 0) atomicAdd(&L.pw_upd, wx);
+                        }
                     }
                 }
             }
@@ -722,6 +825,11 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
                 const int32_t f = alive[x];
                 alive[x] = f & ~kFdAlive;
                 fb.theta[vert[x]] = level;
+                if (huc_pct > 0) {
+                    const unsigned long long wx = (unsigned long long)fw[x];
+                    atomicAdd(&L.pw_all, wx);
+                    if (sx > 0) atomicAdd(&L.pw_upd, wx);
+                }
                 if (sx > 0) {
                     if (f & kFdHeavy) {
                         ph[atomicAdd(&L.lcnt[2], 1)] = x;
@@ -735,6 +843,21 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
         }
         const int32_t n_light = L.lcnt[1], n_heavy = L.lcnt[2];
         levels += tid == 0;
+        if (huc_pct > 0) {
+            // HUC: re-count the live supports instead of applying this
+            // step's updates when those walk more wedges than huc_pct % of a
+            // re-count of the vertices left
+            w_live -= (int64_t)L.pw_all;
+            const int64_t peel_w = (int64_t)L.pw_upd;
+            if (peel_w > 0 && w_live > 0 && peel_w * 100 > (int64_t)huc_pct * w_live) {
+                __syncthreads();
+                fd_recount(g, fb, L, sp, lc, n_live, pl, ph, alive, vert, sup, fw, init, n_i, wave_dense, tab, wcnt,
+                           wedges, pairs, spills);
+                huc_steps += tid == 0;
+                n_cx = -1;
+                continue;
+            }
+        }
         const bool publish = hs && n_light >= help_level_min;
         // heavy updates are shared only when there are several and enough
         // wedges to outweigh the board's fences
@@ -931,7 +1054,7 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
         const int64_t P0 = fb.sub_off[sub];
         const int32_t n_i = (int32_t)(fb.sub_off[sub + 1] - P0);
         if (n_i == 0) continue;
-        unsigned long long wedges = 0, pairs = 0, levels = 0, spills = 0;
+        unsigned long long wedges = 0, pairs = 0, levels = 0, spills = 0, huc_steps = 0;
         if (n_i <= kFdLdsVerts) {
             fd_peel_lds(J.g, fb, J.init, P0, n_i, L, S, tab, sp, wedges, pairs, levels, spills);
         } else {
@@ -958,19 +1081,21 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
                 if (L.flag < kFdHelpSlots) hs = &board->slot[L.flag];
                 __syncthreads();
             }
-            fd_peel_hbm(J.g, fb, J.init, P0, n_i, L, tab, sp, hs, J.help_chunk, J.help_level_min, wedges, pairs,
-                        levels, spills);
+            fd_peel_hbm(J.g, fb, J.init, P0, n_i, L, tab, sp, hs, J.help_chunk, J.help_level_min, J.huc_pct, wedges,
+                        pairs, levels, spills, huc_steps);
             if (hs && tid == 0) atomicExch(&hs->state, 2);
         }
         wedges = (unsigned long long)wave_sum_i64((int64_t)wedges);
         pairs = (unsigned long long)wave_sum_i64((int64_t)pairs);
         levels = (unsigned long long)wave_sum_i64((int64_t)levels);
         spills = (unsigned long long)wave_sum_i64((int64_t)spills);
+        huc_steps = (unsigned long long)wave_sum_i64((int64_t)huc_steps);
         if (lane == 0) {
             if (wedges) atomicAdd(&J.ctl->wedges_fd, wedges);
             if (pairs) atomicAdd(&J.ctl->pair_updates, pairs);
             if (levels) atomicAdd(&J.ctl->fd_levels, levels);
             if (spills) atomicAdd(&J.ctl->spills, spills);
+            if (huc_steps) atomicAdd(&J.ctl->fd_huc_steps, huc_steps);
         }
     }
     // No task left: help the large subsets still open until no slot is
@@ -1092,7 +1217,8 @@ void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl
     k_fd_reset_board<<<1, 256, 0, s>>>(fb.board);
     TIP_HIP_TRY(hipGetLastError());
     FdJobs jobs{};
-    jobs.one = FdJob{g, fb, pb.init, ctl, tune.fd_help_min, tune.fd_help_chunk, tune.fd_help_level_min};
+    jobs.one = FdJob{g, fb, pb.init, ctl, tune.fd_help_min, tune.fd_help_chunk, tune.fd_help_level_min,
+                     tune.fd_huc_pct};
     // every resident workgroup: those without a task of their own help
     // with the large subsets
     const int grid = std::max(1, big_grid);

@@ -430,6 +430,7 @@ void run_back(Work& w, int32_t n_a, int32_t n_b, bool decompose, RunOut& out, Ru
         st->pair_updates = (int64_t)(cf.pair_updates + spread_sum(cf, kScPairs));
         st->rounds = (int64_t)cf.rounds_done;
         st->huc_rounds = (int64_t)cf.huc_rounds;
+        st->fd_huc_steps = (int64_t)cf.fd_huc_steps;
         st->subsets = S;
         st->fd_levels = (int64_t)cf.fd_levels;
         st->spills = (int64_t)(cf.spills + spread_sum(cf, kScSpills));
@@ -501,10 +502,9 @@ int32_t check_opts(const tip_opts* opt, bool batch = false) {
     if (opt->flags & ~kKnownFlags) throw InvalidArg("unknown flag bits");
     if (!batch && (opt->flags & TIP_FLAG_OPTS_PER_GRAPH))
         throw InvalidArg("TIP_FLAG_OPTS_PER_GRAPH is for tip_decompose_batch only");
-    for (int i = 0; i < 7; ++i)
-        if (opt->tune[i] < 0) throw InvalidArg("tune[0..6] must be >= 0");
+    for (int i = 0; i < 8; ++i)
+        if (opt->tune[i] < 0) throw InvalidArg("tune[0..7] must be >= 0");
     if (opt->tune[4] > (1 << 20)) throw InvalidArg("tune[4] must be at most 2^20");
-    if (opt->tune[7] != 0) throw InvalidArg("tune[7] is reserved and must be 0");
     return opt->P == 0 ? kDefaultP : opt->P;
 }
 
@@ -517,6 +517,7 @@ Tune tune_of(const tip_opts* opt) {
     if (opt && opt->tune[4] > 0) t.fd_help_chunk = opt->tune[4];
     if (opt && opt->tune[5] > 0) t.fd_help_level_min = opt->tune[5];
     if (opt && opt->tune[6] > 0) t.fd_help_min = opt->tune[6];
+    if (opt) t.fd_huc_pct = opt->tune[7];
     if (opt && (opt->flags & TIP_FLAG_NO_COMPACT)) t.compact_permille = 0;
     return t;
 }
@@ -725,7 +726,7 @@ tip_status decompose_batched(int32_t n, const tip_edges* gs, const int32_t* side
         TIP_HIP_TRY(hipStreamSynchronize(s));
         const int64_t j = (int64_t)jobs.size();
         jobs.push_back(FdJob{b.w.g, b.w.fb, b.w.pb.init, b.w.ctl, b.tune.fd_help_min, b.tune.fd_help_chunk,
-                             b.tune.fd_help_level_min});
+                             b.tune.fd_help_level_min, b.tune.fd_huc_pct});
         for (int32_t i = 0; i < b.rs.S; ++i) tasks.emplace_back(tw[i], (j << 32) | i);
         stride = std::max(stride, b.w.spill.stride);
     }

@@ -61,6 +61,7 @@ struct Ctl {
     long long huc_pct;            // re-count when peel work > huc_pct % of re-count work; 0 = never
     unsigned long long huc_w_prev;  // range wedge proxy at the previous decision
     unsigned long long huc_rounds;  // rounds that re-counted
+    unsigned long long fd_huc_steps;  // fine-grained steps that re-counted
 };
 
 __device__ inline void spread_add(Ctl* ctl, int c, unsigned long long v) {
@@ -163,6 +164,7 @@ struct Tune {
     int32_t fd_help_chunk = kFdHelpChunk;
     int32_t fd_help_level_min = kFdHelpLevelMin;
     int32_t fd_help_min = kFdHelpMin;
+    int32_t fd_huc_pct = 0;  // tip_opts.tune[7]
 };
 
 // counting
@@ -209,6 +211,7 @@ struct FdJob {
     int32_t help_min;        // subsets of at least this many vertices open a help-board slot
     int32_t help_chunk;      // per-wave updates taken at once from a slot
     int32_t help_level_min;  // levels with fewer per-wave updates are not published
+    int32_t huc_pct;         // HUC in subsets kept in HBM (0 = never)
 };
 
 // The jobs of one launch: a device array, or (list == nullptr) one job

@@ -58,7 +58,7 @@ class Stats(ctypes.Structure):
                  "peel_launches", "peel_wedges", "peel_edges", "peel_pairs")] + \
                [(n, ctypes.c_double) for n in
                 ("peel_ms", "t_ingest_ms", "t_count_ms", "t_cd_ms", "t_fd_ms", "t_total_ms")] + \
-               [("huc_rounds", ctypes.c_int64)]
+               [("huc_rounds", ctypes.c_int64), ("fd_huc_steps", ctypes.c_int64)]
 
     def to_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -410,3 +410,28 @@ def test_batch_with_per_graph_tunings(gpu_lib):
         out = tip.decompose_batch(gs, [0] * len(gs), flags=flags, tunes=tunes)
         for g, th in zip(gs, out):
             np.testing.assert_array_equal(th, oracle.bup(g, 0)[0])
+
+
+def test_fd_huc_recount_changes_nothing(gpu_lib):
+    """HUC in the fine-grained step (Section 4.1, last paragraph): with a
+    threshold of 1%, nearly every step of a subset kept in HBM re-counts its
+    live supports (support at the range start minus the butterflies shared
+    with the subset's peeled vertices) instead of applying its updates.  The
+    subsets, initial supports, bounds and tip numbers are those of peeling;
+    on cl-1m both sides keep the oracle's digests."""
+    g = gg.chung_lu(20000, 3000, 150000, 2.2, 2.0, seed=47)
+    th = oracle.bup(g, 0)[0]
+    for P in (1, 3):
+        ref = tip.decompose_ex(g, 0, P=P)
+        got = tip.decompose_ex(g, 0, P=P, tune=[0, 0, 0, 0, 0, 0, 0, 1])
+        assert got["stats"]["fd_huc_steps"] > 0 and ref["stats"]["fd_huc_steps"] == 0
+        np.testing.assert_array_equal(got["theta"], th)
+        np.testing.assert_array_equal(got["subset"], ref["subset"])
+        np.testing.assert_array_equal(got["init"], ref["init"])
+        np.testing.assert_array_equal(got["bounds"], ref["bounds"])
+    rec = _golden("cl-1m")
+    c1 = gg.config_graph("cl-1m")
+    for side, key in ((0, "theta_u"), (1, "theta_v")):
+        out, st = tip.decompose(c1, side, P=4, tune=[0, 0, 0, 0, 0, 0, 0, 1], with_stats=True)
+        assert st["fd_huc_steps"] > 0
+        assert digest(out) == rec[key]["sha256"], side
