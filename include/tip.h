@@ -92,6 +92,20 @@ typedef struct {
  * would exceed 2^31 - 1 ids or edges); same results. */
 #define TIP_FLAG_BATCH_STREAMS 32
 
+/* TIP_FLAG_FD_DGM: Dynamic Graph Maintenance (Section 4.2) in the
+ * fine-grained step too: a subset kept in HBM removes its peeled vertices
+ * from the neighbour runs of its induced subgraph G_i each time the updates
+ * since the last compaction walked as many wedges as G_i has edges (the
+ * section's trigger).  Not combined with tune[7] (a HUC re-count there
+ * needs the peeled vertices).  Same results, fewer wedges traversed. */
+#define TIP_FLAG_FD_DGM 64
+
+/* TIP_FLAG_DGM_PAPER: the coarse-grained step compacts its lists at a range
+ * start once the wedges traversed since the last compaction reach the
+ * entries left (Section 4.2's trigger), instead of tune[2]'s share of
+ * entries held by peeled vertices.  Same results. */
+#define TIP_FLAG_DGM_PAPER 128
+
 /* Options.  Zero-initialised means defaults. */
 typedef struct {
     int32_t P;       /* number of tip-number ranges of the coarse-grained step
@@ -162,6 +176,7 @@ typedef struct {
     double t_ingest_ms, t_count_ms, t_cd_ms, t_fd_ms, t_total_ms; /* device time per phase */
     int64_t huc_rounds;    /* coarse-grained rounds that re-counted instead of peeling (tune[3]) */
     int64_t fd_huc_steps;  /* fine-grained steps that re-counted instead of peeling (tune[7]) */
+    int64_t compactions;   /* list compactions: coarse-grained (low 32 bits) + fine-grained << 32 */
 } tip_stats;
 
 /* Per-vertex butterfly counts of both sides (Alg. 1, Section 2.1) and the

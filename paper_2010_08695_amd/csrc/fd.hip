@@ -91,6 +91,47 @@ __global__ void k_fd_slices(DevGraph g, const int32_t* __restrict__ state, const
     }
 }
 
+// Runs of the partitioned CSC (one per (row, subset) key), for compaction
+// in the fine-grained step (Section 4.2): every run's start position and
+// subset, its length at the start, and the run count of every subset.
+__device__ inline bool fd_run_start(const uint64_t* __restrict__ pkeys, int64_t q) {
+    return q == 0 || pkeys[q] != pkeys[q - 1];
+}
+
+__global__ void k_fd_run_flags(const uint64_t* __restrict__ pkeys, int64_t m, int64_t* flag) {
+    GRID_STRIDE(q, m) flag[q] = fd_run_start(pkeys, q) ? 1 : 0;
+}
+
+// pos: exclusive scan of the flags.  Runs in position order go to
+// rkey/rval [0, R) (key: subset, value: start), the rest of rkey is the
+// sentinel S so that a sort by subset leaves them last.
+__global__ void k_fd_run_compact(const uint64_t* __restrict__ pkeys, int64_t m, int32_t S,
+                                 const int64_t* __restrict__ pos, uint64_t* rkey, int32_t* rval, int64_t* sub_rcnt) {
+    GRID_STRIDE(q, m) {
+        rkey[q] = (uint64_t)S;
+        if (fd_run_start(pkeys, q)) {
+            const int32_t sub = (int32_t)(pkeys[q] % (uint64_t)S);
+            const int64_t j = pos[q];
+            rval[j] = (int32_t)q;
+            atomic_add_i64(&sub_rcnt[sub], 1);
+        }
+    }
+}
+
+// Length of every run (next start - start) and the keys of the runs, once
+// every run's start is in place.
+__global__ void k_fd_run_len(const uint64_t* __restrict__ pkeys, int64_t m, int32_t S,
+                             const int64_t* __restrict__ pos, const int32_t* __restrict__ rval, uint64_t* rkey,
+                             int32_t* rlen_at) {
+    const int64_t R = m > 0 ? pos[m - 1] + (fd_run_start(pkeys, m - 1) ? 1 : 0) : 0;
+    GRID_STRIDE(j, R) {
+        const int32_t q = rval[j];
+        const int64_t next = j + 1 < R ? rval[j + 1] : m;
+        rlen_at[q] = (int32_t)(next - q);
+        rkey[j] = pkeys[q] % (uint64_t)S;
+    }
+}
+
 // Workload-aware schedule: subsets in decreasing order of induced wedges
 // (ties by subset id).
 __global__ void k_fd_order(const int64_t* __restrict__ task_w, int32_t S, int32_t* order) {
@@ -698,13 +739,55 @@ __device__ inline void fd_recount(const DevGraph& g, const FdBuffers& fb, FdLds&
 }
 
 
+// DGM (Section 4.2) for a subset kept in HBM: every run of G_i keeps only
+// its live members, in order (each wave compacts whole runs in place with
+// ballots; every write lands at or before the entries still to be read),
+// then the edges of the live vertices take their runs' new lengths.  All
+// threads call.
+__device__ inline void fd_compact_runs(const DevGraph& g, const FdBuffers& fb, FdLds& L, int32_t sub, int64_t P0,
+                                       const int32_t* lc, int32_t n_live, const int32_t* alive,
+                                       const int32_t* vert) {
+    constexpr int NW = kFdThreads / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    __syncthreads();
+    const int64_t r0 = fb.sub_roff[sub], r1 = fb.sub_roff[sub + 1];
+    for (int64_t r = r0 + wid; r < r1; r += NW) {
+        const int32_t q = fb.run_q[r];
+        const int32_t len = fb.rlen_at[q];
+        int32_t out = 0;
+        for (int32_t i0 = 0; i0 < len; i0 += kWave) {
+            const int32_t i = i0 + lane;
+            int32_t w = 0;
+            bool keep = false;
+            if (i < len) {
+                w = fb.pcsc[q + i];
+                keep = (alive[w] & kFdAlive) != 0;
+            }
+            const uint64_t km = __ballot(keep);
+            wave_sync();  // every lane has read its entry before any is written
+            if (keep) fb.pcsc[q + out + (int32_t)__popcll(km & lanemask_lt())] = w;
+            out += (int32_t)__popcll(km);
+            wave_sync();
+        }
+        if (lane == 0) fb.rlen_at[q] = out;
+    }
+    __syncthreads();
+    for (int32_t j = wid; j < n_live; j += NW) {
+        const int32_t x = lc[j];
+        if (!(alive[x] & kFdAlive)) continue;
+        const int32_t ux = vert[x];
+        for (int64_t e = g.a_off[ux] + lane; e < g.a_off[ux + 1]; e += kWave) fb.fd_len[e] = fb.rlen_at[fb.fd_beg[e]];
+    }
+    __syncthreads();
+}
+
 // Level loop of a subset whose state lives in HBM.
 __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const int64_t* __restrict__ init,
                                    int64_t P0, int32_t n_i, FdLds& L, unsigned long long* tab, const Spill& sp,
                                    FdHelpSlot* hs, int32_t help_chunk, int32_t help_level_min, int32_t huc_pct,
-                                   unsigned long long& wedges, unsigned long long& pairs,
+                                   int32_t sub, int32_t dgm, unsigned long long& wedges, unsigned long long& pairs,
                                    unsigned long long& levels, unsigned long long& spills,
-                                   unsigned long long& huc_steps) {
+                                   unsigned long long& huc_steps, unsigned long long& compactions) {
     constexpr int NT = kFdThreads;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     int32_t* lc = fb.lst[0] + P0;
@@ -719,15 +802,22 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
     FdHbmState st{sup, alive, vert};
     const bool wave_dense = n_i <= kFdWaveKeys;
     uint32_t* wcnt = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(&L.u) + (size_t)wid * kFdWaveKeys);
-    int64_t wsum = 0;
+    int64_t wsum = 0, esum = 0;
     for (int32_t j = tid; j < n_i; j += NT) {
         lc[j] = j;
-        sup[j] = init[vert[j]];
+        const int32_t v = vert[j];
+        sup[j] = init[v];
         alive[j] = kFdAlive | (fd_heavy(g, fb, P0, n_i, j) ? kFdHeavy : 0);
         wsum += fw[j];
+        if (dgm) esum += g.a_off[v + 1] - g.a_off[v];
     }
     // induced wedges of the live vertices: the cost of a HUC re-count
     int64_t w_live = huc_pct > 0 ? fd_block_sum<NT>(L, wsum) : 0;
+    // DGM (Section 4.2): the runs of G_i are compacted each time the
+    // updates since the last compaction walked as many wedges as G_i has
+    // edges (the induced wedges of the peeled vertices stand for the walk)
+    const int64_t m_i = dgm ? fd_block_sum<NT>(L, esum) : 0;
+    int64_t walked = 0;
     __syncthreads();
     // lc: the live list (it may still hold vertices peeled by later steps of
     // a level; the next full pass drops them)
@@ -803,7 +893,7 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
                     if (peel) {
                         alive[x] = fl[u] & ~kFdAlive;
                         fb.theta[vert[x]] = level;
-                        if (huc_pct > 0) {
+                        if (huc_pct > 0 || dgm) {
                             const unsigned long long wx = (unsigned long long)fw[x];
                             atomicAdd(&L.pw_all, wx);
                             if (ss[u] > 0) atomicAdd(&L.pw_upd, wx);
@@ -825,7 +915,7 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
                 const int32_t f = alive[x];
                 alive[x] = f & ~kFdAlive;
                 fb.theta[vert[x]] = level;
-                if (huc_pct > 0) {
+                if (huc_pct > 0 || dgm) {
                     const unsigned long long wx = (unsigned long long)fw[x];
                     atomicAdd(&L.pw_all, wx);
                     if (sx > 0) atomicAdd(&L.pw_upd, wx);
@@ -917,6 +1007,14 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
         }
         __syncthreads();
         n_cx = track && L.lcnt[3] > 0 ? L.lcnt[3] : -1;
+        if (dgm) {
+            walked += (int64_t)L.pw_upd;
+            if (walked >= m_i) {
+                fd_compact_runs(g, fb, L, sub, P0, lc, n_live, alive, vert);
+                walked = 0;
+                compactions += tid == 0;
+            }
+        }
         __syncthreads();
     }
 }
@@ -1054,7 +1152,7 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
         const int64_t P0 = fb.sub_off[sub];
         const int32_t n_i = (int32_t)(fb.sub_off[sub + 1] - P0);
         if (n_i == 0) continue;
-        unsigned long long wedges = 0, pairs = 0, levels = 0, spills = 0, huc_steps = 0;
+        unsigned long long wedges = 0, pairs = 0, levels = 0, spills = 0, huc_steps = 0, compactions = 0;
         if (n_i <= kFdLdsVerts) {
             fd_peel_lds(J.g, fb, J.init, P0, n_i, L, S, tab, sp, wedges, pairs, levels, spills);
         } else {
@@ -1081,8 +1179,8 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
                 if (L.flag < kFdHelpSlots) hs = &board->slot[L.flag];
                 __syncthreads();
             }
-            fd_peel_hbm(J.g, fb, J.init, P0, n_i, L, tab, sp, hs, J.help_chunk, J.help_level_min, J.huc_pct, wedges,
-                        pairs, levels, spills, huc_steps);
+            fd_peel_hbm(J.g, fb, J.init, P0, n_i, L, tab, sp, hs, J.help_chunk, J.help_level_min, J.huc_pct, sub,
+                        J.dgm, wedges, pairs, levels, spills, huc_steps, compactions);
             if (hs && tid == 0) atomicExch(&hs->state, 2);
         }
         wedges = (unsigned long long)wave_sum_i64((int64_t)wedges);
@@ -1090,12 +1188,14 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
         levels = (unsigned long long)wave_sum_i64((int64_t)levels);
         spills = (unsigned long long)wave_sum_i64((int64_t)spills);
         huc_steps = (unsigned long long)wave_sum_i64((int64_t)huc_steps);
+        compactions = (unsigned long long)wave_sum_i64((int64_t)compactions);
         if (lane == 0) {
             if (wedges) atomicAdd(&J.ctl->wedges_fd, wedges);
             if (pairs) atomicAdd(&J.ctl->pair_updates, pairs);
             if (levels) atomicAdd(&J.ctl->fd_levels, levels);
             if (spills) atomicAdd(&J.ctl->spills, spills);
             if (huc_steps) atomicAdd(&J.ctl->fd_huc_steps, huc_steps);
+            if (compactions) atomicAdd(&J.ctl->fd_compactions, compactions);
         }
     }
     // No task left: help the large subsets still open until no slot is
@@ -1182,7 +1282,7 @@ int fd_occupancy() {
 
 void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, uint64_t* tmp_keys,
                      int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp, uint64_t* keys_scratch,
-                     int32_t* vals_scratch, hipStream_t s) {
+                     int32_t* vals_scratch, hipStream_t s, bool runs) {
     const int32_t n_a = g.n_a;
     fill_i64(fb.task_w, 0, S, s);
     if (n_a <= 0) return;
@@ -1204,6 +1304,21 @@ void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t 
         k_fd_slices<<<grid1(g.m, 2048), kT, lds_tw ? sizeof(unsigned long long) * (size_t)S : 0, s>>>(
             g, pb.state, fb.pkeys, S, fb.fd_pos, fb.fd_beg, fb.fd_len, fb.task_w, fb.fd_w, lds_tw);
         TIP_HIP_TRY(hipGetLastError());
+        if (runs) {
+            // the sort's buffers are free again: keys_scratch holds the flags
+            // and their scan, tmp_keys the run keys
+            int64_t* pos = reinterpret_cast<int64_t*>(keys_scratch);
+            fill_i64(fb.sub_rcnt, 0, (int64_t)S + 2, s);
+            k_fd_run_flags<<<grid1(g.m), kT, 0, s>>>(fb.pkeys, g.m, pos);
+            TIP_HIP_TRY(hipGetLastError());
+            scan_exclusive_i64(pos, pos, g.m, scan_tmp, s);
+            k_fd_run_compact<<<grid1(g.m), kT, 0, s>>>(fb.pkeys, g.m, S, pos, tmp_keys, fb.run_q, fb.sub_rcnt);
+            TIP_HIP_TRY(hipGetLastError());
+            k_fd_run_len<<<grid1(g.m), kT, 0, s>>>(fb.pkeys, g.m, S, pos, fb.run_q, tmp_keys, fb.rlen_at);
+            TIP_HIP_TRY(hipGetLastError());
+            radix_sort_pairs(tmp_keys, fb.run_q, keys_scratch, tmp_vals, g.m, bits_for((uint64_t)S), hist, scan_tmp, s);
+            scan_exclusive_i64(fb.sub_rcnt, fb.sub_roff, (int64_t)S + 2, scan_tmp, s);
+        }
     }
     k_fd_order<<<1, 1024, 0, s>>>(fb.task_w, S, fb.order);
     TIP_HIP_TRY(hipGetLastError());
@@ -1213,12 +1328,13 @@ void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl
                const SpillArena& spill, int big_grid, uint64_t* tmp_keys, int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp,
                uint64_t* keys_scratch, int32_t* vals_scratch, hipStream_t s) {
     if (g.n_a <= 0) return;
-    launch_fd_setup(g, pb, fb, S, tmp_keys, tmp_vals, hist, scan_tmp, keys_scratch, vals_scratch, s);
+    launch_fd_setup(g, pb, fb, S, tmp_keys, tmp_vals, hist, scan_tmp, keys_scratch, vals_scratch, s,
+                    tune.fd_dgm && tune.fd_huc_pct == 0);
     k_fd_reset_board<<<1, 256, 0, s>>>(fb.board);
     TIP_HIP_TRY(hipGetLastError());
     FdJobs jobs{};
     jobs.one = FdJob{g, fb, pb.init, ctl, tune.fd_help_min, tune.fd_help_chunk, tune.fd_help_level_min,
-                     tune.fd_huc_pct};
+                     tune.fd_huc_pct, tune.fd_dgm && tune.fd_huc_pct == 0 ? 1 : 0};
     // every resident workgroup: those without a task of their own help
     // with the large subsets
     const int grid = std::max(1, big_grid);

@@ -113,6 +113,10 @@ void plan(Arena& ar, int32_t n_a, int32_t n_b, int64_t m, int32_t P, int slots, 
     w.fb.fd_w = ar.take<int64_t>(na);
     w.fb.alive = ar.take<int32_t>(na);
     for (int i = 0; i < 5; ++i) w.fb.lst[i] = ar.take<int32_t>(na);
+    w.fb.run_q = ar.take<int32_t>(mm);
+    w.fb.rlen_at = ar.take<int32_t>(mm);
+    w.fb.sub_roff = ar.take<int64_t>(S + 2);
+    w.fb.sub_rcnt = ar.take<int64_t>(S + 2);
     w.fb.theta = ar.take<int64_t>(na);
     w.fb.board = ar.take<FdBoard>(1);
     w.ctl = ar.take<Ctl>(1);
@@ -248,6 +252,8 @@ struct RunState {
     int64_t peel_launches = 0;
     int32_t S = 0;
     std::vector<int64_t> bounds;
+    unsigned long long cd_walked_at = 0;  // coarse-grained wedges walked at the last compaction
+    int64_t cd_compactions = 0;
 };
 
 // fd_inline = false stops after the set-up of FD (Alg. 4): the caller then
@@ -317,9 +323,18 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
             // DGM: drop the vertices of finished ranges from the CD lists once
             // they hold enough of the remaining entries
             const unsigned long long dead = spread_sum(c0, kScDeadEdges);
-            if (tune.compact_permille > 0 && dead > 0 &&
-                (double)dead * 1000.0 >= (double)c0.cd_m * (double)tune.compact_permille)
+            const unsigned long long walked = spread_sum(c0, kScWedgesCd);
+            bool compact = false;
+            if (tune.dgm_paper)  // Section 4.2: after as many wedges as entries left
+                compact = tune.compact_permille > 0 && dead > 0 && walked - rs.cd_walked_at >= (unsigned long long)c0.cd_m;
+            else
+                compact = tune.compact_permille > 0 && dead > 0 &&
+                          (double)dead * 1000.0 >= (double)c0.cd_m * (double)tune.compact_permille;
+            if (compact) {
                 launch_compact(g, pb, cscr, c0.cd_m, tune, w.ctl, s);
+                rs.cd_walked_at = walked;
+                ++rs.cd_compactions;
+            }
             uint64_t max_supp = 0;
             for (int i = 0; i < kSpread; ++i) max_supp = std::max<uint64_t>(max_supp, c0.spread_max[i]);
             const long long w_rem = (long long)spread_sum(c0, kScWRem);
@@ -393,8 +408,8 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
                           w.ib.scan_tmp, w.ib.keys, w.ib.vals, s);
             ev.rec(4, s);
         } else {
-            launch_fd_setup(g, pb, w.fb, S, w.ib.keys2, w.ib.vals2, w.ib.hist, w.ib.scan_tmp, w.ib.keys, w.ib.vals,
-                            s);
+            launch_fd_setup(g, pb, w.fb, S, w.ib.keys2, w.ib.vals2, w.ib.hist, w.ib.scan_tmp, w.ib.keys, w.ib.vals, s,
+                            tune.fd_dgm && tune.fd_huc_pct == 0);
         }
     }
     return TIP_OK;
@@ -431,6 +446,7 @@ void run_back(Work& w, int32_t n_a, int32_t n_b, bool decompose, RunOut& out, Ru
         st->rounds = (int64_t)cf.rounds_done;
         st->huc_rounds = (int64_t)cf.huc_rounds;
         st->fd_huc_steps = (int64_t)cf.fd_huc_steps;
+        st->compactions = rs.cd_compactions + (int64_t)(cf.fd_compactions << 32);
         st->subsets = S;
         st->fd_levels = (int64_t)cf.fd_levels;
         st->spills = (int64_t)(cf.spills + spread_sum(cf, kScSpills));
@@ -494,7 +510,8 @@ void check_edges(const tip_edges* g) {
 }
 
 constexpr int32_t kKnownFlags = TIP_FLAG_TIME_KERNELS | TIP_FLAG_NO_GRAPH | TIP_FLAG_BATCH_PLAIN | TIP_FLAG_NO_COMPACT |
-                                TIP_FLAG_OPTS_PER_GRAPH | TIP_FLAG_BATCH_STREAMS;
+                                TIP_FLAG_OPTS_PER_GRAPH | TIP_FLAG_BATCH_STREAMS | TIP_FLAG_FD_DGM |
+                                TIP_FLAG_DGM_PAPER;
 
 int32_t check_opts(const tip_opts* opt, bool batch = false) {
     if (!opt) return kDefaultP;
@@ -519,6 +536,8 @@ Tune tune_of(const tip_opts* opt) {
     if (opt && opt->tune[6] > 0) t.fd_help_min = opt->tune[6];
     if (opt) t.fd_huc_pct = opt->tune[7];
     if (opt && (opt->flags & TIP_FLAG_NO_COMPACT)) t.compact_permille = 0;
+    if (opt) t.fd_dgm = (opt->flags & TIP_FLAG_FD_DGM) != 0;
+    if (opt) t.dgm_paper = (opt->flags & TIP_FLAG_DGM_PAPER) != 0;
     return t;
 }
 
@@ -726,7 +745,8 @@ tip_status decompose_batched(int32_t n, const tip_edges* gs, const int32_t* side
         TIP_HIP_TRY(hipStreamSynchronize(s));
         const int64_t j = (int64_t)jobs.size();
         jobs.push_back(FdJob{b.w.g, b.w.fb, b.w.pb.init, b.w.ctl, b.tune.fd_help_min, b.tune.fd_help_chunk,
-                             b.tune.fd_help_level_min, b.tune.fd_huc_pct});
+                             b.tune.fd_help_level_min, b.tune.fd_huc_pct,
+                             b.tune.fd_dgm && b.tune.fd_huc_pct == 0 ? 1 : 0});
         for (int32_t i = 0; i < b.rs.S; ++i) tasks.emplace_back(tw[i], (j << 32) | i);
         stride = std::max(stride, b.w.spill.stride);
     }

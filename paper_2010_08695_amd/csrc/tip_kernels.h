@@ -62,6 +62,7 @@ struct Ctl {
     unsigned long long huc_w_prev;  // range wedge proxy at the previous decision
     unsigned long long huc_rounds;  // rounds that re-counted
     unsigned long long fd_huc_steps;  // fine-grained steps that re-counted
+    unsigned long long cd_compactions, fd_compactions;
 };
 
 __device__ inline void spread_add(Ctl* ctl, int c, unsigned long long v) {
@@ -150,6 +151,11 @@ struct FdBuffers {
     int64_t* fd_w;       // [n_a] wedges of each vertex inside its subset's subgraph, by position
     int32_t* alive;      // [n_a] by subset position
     int32_t* lst[5];     // [n_a] live / next-live / light-peel / heavy-peel / crossing lists by subset position
+    // runs of the partitioned CSC grouped by subset (built with TIP_FLAG_FD_DGM)
+    int32_t* run_q;      // [m] start position of each run, runs of subset s at [sub_roff[s], sub_roff[s + 1])
+    int32_t* rlen_at;    // [m] current length of the run starting at a position
+    int64_t* sub_roff;   // [S + 2]
+    int64_t* sub_rcnt;   // [S + 2]
     int64_t* theta;      // [n_a] by rank
     FdBoard* board;      // task queue and help board of the launch
 };
@@ -165,6 +171,8 @@ struct Tune {
     int32_t fd_help_level_min = kFdHelpLevelMin;
     int32_t fd_help_min = kFdHelpMin;
     int32_t fd_huc_pct = 0;  // tip_opts.tune[7]
+    bool fd_dgm = false;     // TIP_FLAG_FD_DGM
+    bool dgm_paper = false;  // TIP_FLAG_DGM_PAPER
 };
 
 // counting
@@ -212,6 +220,7 @@ struct FdJob {
     int32_t help_chunk;      // per-wave updates taken at once from a slot
     int32_t help_level_min;  // levels with fewer per-wave updates are not published
     int32_t huc_pct;         // HUC in subsets kept in HBM (0 = never)
+    int32_t dgm;             // compaction of the runs of subsets kept in HBM
 };
 
 // The jobs of one launch: a device array, or (list == nullptr) one job
@@ -226,7 +235,7 @@ struct FdJobs {
 // not including, the peeling launch); fb.task_w holds the induced wedges.
 void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, uint64_t* tmp_keys,
                      int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp, uint64_t* keys_scratch,
-                     int32_t* vals_scratch, hipStream_t s);
+                     int32_t* vals_scratch, hipStream_t s, bool runs);
 // Persistent peeling of the subsets of many graphs in one launch: tasks[t] =
 // job << 32 | subset, in the order they are to be taken; *head is the queue
 // head (reset here).

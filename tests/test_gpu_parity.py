@@ -435,3 +435,51 @@ def test_fd_huc_recount_changes_nothing(gpu_lib):
         out, st = tip.decompose(c1, side, P=4, tune=[0, 0, 0, 0, 0, 0, 0, 1], with_stats=True)
         assert st["fd_huc_steps"] > 0
         assert digest(out) == rec[key]["sha256"], side
+
+
+def test_fd_dgm_changes_nothing_but_work(gpu_lib):
+    """DGM in the fine-grained step (Section 4.2, TIP_FLAG_FD_DGM): a subset
+    kept in HBM drops its peeled vertices from G_i's neighbour runs each time
+    its updates walked as many wedges as G_i has edges.  Subsets, initial
+    supports, bounds and tip numbers are unchanged, and the fine-grained step
+    walks no more wedges; cl-1m keeps the oracle's digests on both sides."""
+    g = gg.chung_lu(20000, 3000, 150000, 2.2, 2.0, seed=47)
+    th = oracle.bup(g, 0)[0]
+    for P in (1, 3):
+        ref = tip.decompose_ex(g, 0, P=P)
+        got = tip.decompose_ex(g, 0, P=P, flags=tip.TIP_FLAG_FD_DGM)
+        assert got["stats"]["compactions"] >> 32 > 0 and ref["stats"]["compactions"] >> 32 == 0
+        assert got["stats"]["wedges_fd"] < ref["stats"]["wedges_fd"]
+        np.testing.assert_array_equal(got["theta"], th)
+        np.testing.assert_array_equal(got["subset"], ref["subset"])
+        np.testing.assert_array_equal(got["init"], ref["init"])
+        np.testing.assert_array_equal(got["bounds"], ref["bounds"])
+    rec = _golden("cl-1m")
+    c1 = gg.config_graph("cl-1m")
+    for side, key in ((0, "theta_u"), (1, "theta_v")):
+        out, st = tip.decompose(c1, side, P=4, flags=tip.TIP_FLAG_FD_DGM, with_stats=True)
+        assert st["compactions"] >> 32 > 0
+        assert digest(out) == rec[key]["sha256"], side
+    # with HUC forced in the same subsets, compaction stays off (a re-count
+    # needs the peeled vertices) and results stay exact
+    got = tip.decompose_ex(g, 0, P=1, flags=tip.TIP_FLAG_FD_DGM, tune=[0, 0, 0, 0, 0, 0, 0, 1])
+    assert got["stats"]["compactions"] >> 32 == 0 and got["stats"]["fd_huc_steps"] > 0
+    np.testing.assert_array_equal(got["theta"], th)
+
+
+def test_cd_dgm_paper_trigger_changes_nothing(gpu_lib):
+    """Section 4.2's own trigger for the coarse-grained lists
+    (TIP_FLAG_DGM_PAPER: compact once the wedges walked since the last
+    compaction reach the entries left): same subsets, supports, bounds and
+    tip numbers as with the default trigger and with no compaction."""
+    g = gg.chung_lu(6000, 1200, 60000, 2.2, 2.0, seed=43)
+    th = oracle.bup(g, 0)[0]
+    ref = tip.decompose_ex(g, 0, flags=tip.TIP_FLAG_NO_COMPACT)
+    got = tip.decompose_ex(g, 0, flags=tip.TIP_FLAG_DGM_PAPER)
+    assert got["stats"]["compactions"] & 0xffffffff > 0
+    assert got["stats"]["wedges_cd"] <= ref["stats"]["wedges_cd"]
+    np.testing.assert_array_equal(got["theta"], th)
+    for k in ("subset", "init", "bounds"):
+        np.testing.assert_array_equal(got[k], ref[k])
+    rec = _golden("cl-1m")
+    assert digest(tip.decompose(gg.config_graph("cl-1m"), 0, flags=tip.TIP_FLAG_DGM_PAPER)) == rec["theta_u"]["sha256"]
