@@ -265,7 +265,7 @@ tip_status tip_decompose_noalloc(const int32_t* d_eu, const int32_t* d_ev, int32
 tip_status tip_count_edge_butterflies(const tip_edges* g, int64_t* bfly_e, int64_t* total);
 
 /* Wing numbers (edge peeling, the extension of the method to edges named in
- * the Conclusion): psi[i] for input edge i is the largest k such that the edge
+ * the Extensions section): psi[i] for input edge i is the largest k such that the edge
  * lies in a k-wing, a subgraph in which every edge is in at least k
  * butterflies.  Computed by level-synchronous bottom-up edge peeling: each
  * round removes every live edge whose support is at most the current level,

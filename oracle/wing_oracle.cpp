@@ -12,7 +12,7 @@
 //     v' != v of u and u', so the count is the sum over u' in N_v, u' != u,
 //     of (|N_u intersect N_u'| - 1);
 //   * wing numbers by sequential bottom-up edge peeling (the edge-peeling
-//     extension named in the Conclusion: the k-wing is the edge analogue of
+//     extension named in the Extensions section: the k-wing is the edge analogue of
 //     the k-tip, every edge in at least k butterflies of the subgraph): edges
 //     leave in order of least support, each with the support it has when it
 //     leaves (never less than any earlier wing number); every butterfly it

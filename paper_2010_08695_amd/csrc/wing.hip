@@ -3,7 +3,7 @@
 // Wing numbers are the edge analogue of tip numbers: the k-wing is the
 // largest subgraph in which every edge lies in at least k butterflies, and
 // an edge's wing number is the largest k whose k-wing holds it.  The paper's
-// Conclusion names parallel edge peeling as the extension of its method and
+// Extensions section names parallel edge peeling as the extension of its method and
 // its one difficulty: several edges of one butterfly can be peeled in the
 // same round, and the butterfly must then be taken out of the survivors'
 // supports exactly once.  Here every peeling round takes ALL live edges of
