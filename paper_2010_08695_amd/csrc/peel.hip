@@ -763,13 +763,21 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
     // with at most NT neighbours, their list offsets and the tile bounds of
     // every pass of the item (at most kDensePasses + 1) are loaded once and
     // stay in registers; bnd[0] and bnd[1] bound the current pass
+    //
+    // With at most kWave neighbours (every vertex of the 2- and 4-bit
+    // counters, most of the 8-bit ones) every wave loads all of them, lane l
+    // neighbour l, and finds each traversal unit's run with a ballot over its
+    // own lanes: a pass then needs no staging in LDS and no barrier before
+    // its traversal.
     const bool one = d <= NT;
+    const bool narrow = d <= kWave;
     int64_t bo1 = 0;
     int32_t bnd[kDensePasses + 1];
 #pragma unroll
     for (int k = 0; k <= kDensePasses; ++k) bnd[k] = 0;
-    if (one && tid < d) {
-        const int32_t v1 = g.a_adj[e0 + tid];
+    const int nb_idx = narrow ? lane : tid;  // the neighbour this thread holds
+    if (one && nb_idx < d) {
+        const int32_t v1 = g.a_adj[e0 + nb_idx];
         bo1 = g.b_off[v1];
         const int32_t* row = tb + (int64_t)v1 * (ntt + 1);
 #pragma unroll
@@ -779,7 +787,55 @@ __device__ inline void dense_item(const DevGraph& g, const int32_t* __restrict__
     for (int32_t p0 = t_begin; p0 < t_end; p0 += gpass) {
         const int32_t p1 = min(t_end, p0 + gpass);
         const int32_t klo = p0 * tk;
-        for (int64_t g0 = 0; g0 < d; g0 += NT) {
+        if (narrow) {
+            constexpr int NW = NT / kWave;
+            constexpr int R = kUnitsInFlight;
+            const int wid = tid / kWave;
+            int64_t s0 = 0;
+            int32_t len = 0;
+            if (lane < d) {
+                s0 = bo1 + bnd[0];
+                len = bnd[1] - bnd[0];
+            }
+            const int32_t units = (len + kUnit - 1) / kUnit;
+            const int32_t incl = wave_incl_scan_i32(units);
+            const int32_t nu = __shfl(incl, kWave - 1, kWave);
+            const int32_t pre = incl - units;  // lanes past d: nu
+            unsigned long long wl = 0;
+            for (int32_t k0 = wid; k0 < nu; k0 += R * NW) {
+                int32_t x[2 * R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int32_t k = k0 + r * NW;
+                    int32_t n = 0;
+                    const int32_t* pp = g.b_adj;
+                    if (k < nu) {
+                        // the unit's run: the last lane whose first unit is <= k
+                        const uint64_t le = __ballot(pre <= k);
+                        const int j = kWave - 1 - __clzll((long long)le);
+                        const int64_t sj = __shfl(s0, j, kWave);
+                        const int32_t lj = __shfl(len, j, kWave), pj = __shfl(pre, j, kWave);
+                        const int32_t off = (k - pj) * kUnit;
+                        n = min(kUnit, lj - off);
+                        pp = g.b_adj + sj + off;
+                    }
+                    x[2 * r] = lane < n ? pp[lane] : -1;
+                    x[2 * r + 1] = lane + kWave < n ? pp[lane + kWave] : -1;
+                }
+#pragma unroll
+                for (int r = 0; r < 2 * R; ++r) {
+                    const int32_t w = x[r];
+                    if (w >= 0 && w != u) {
+                        ++wl;
+                        const uint32_t k = (uint32_t)(w - klo);
+                        atomicAdd(&cnt[k / PER_WORD], 1u << ((k % PER_WORD) * BITS));
+                    }
+                }
+            }
+            pc.wedges += wl;
+            __syncthreads();
+        }
+        for (int64_t g0 = 0; !narrow && g0 < d; g0 += NT) {
             const int gs = (int)min<int64_t>(NT, d - g0);
             int64_t s0 = 0;
             int32_t len = 0;
