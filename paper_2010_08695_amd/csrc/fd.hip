@@ -1153,6 +1153,7 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
         const int32_t n_i = (int32_t)(fb.sub_off[sub + 1] - P0);
         if (n_i == 0) continue;
         unsigned long long wedges = 0, pairs = 0, levels = 0, spills = 0, huc_steps = 0, compactions = 0;
+        const unsigned long long t_start = jobs.trace ? wall_clock64() : 0ull;
         if (n_i <= kFdLdsVerts) {
             fd_peel_lds(J.g, fb, J.init, P0, n_i, L, S, tab, sp, wedges, pairs, levels, spills);
         } else {
@@ -1182,6 +1183,13 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
             fd_peel_hbm(J.g, fb, J.init, P0, n_i, L, tab, sp, hs, J.help_chunk, J.help_level_min, J.huc_pct, sub,
                         J.dgm, wedges, pairs, levels, spills, huc_steps, compactions);
             if (hs && tid == 0) atomicExch(&hs->state, 2);
+        }
+        if (jobs.trace && tid == 0 && t < jobs.trace_max) {
+            unsigned long long* e = jobs.trace + 4 * (int64_t)t;
+            e[0] = (unsigned long long)n_i;
+            e[1] = levels;  // thread 0 counts every level
+            e[2] = t_start;
+            e[3] = wall_clock64();
         }
         wedges = (unsigned long long)wave_sum_i64((int64_t)wedges);
         pairs = (unsigned long long)wave_sum_i64((int64_t)pairs);
@@ -1326,7 +1334,7 @@ void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t 
 
 void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl, const Tune& tune,
                const SpillArena& spill, int big_grid, uint64_t* tmp_keys, int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp,
-               uint64_t* keys_scratch, int32_t* vals_scratch, hipStream_t s) {
+               uint64_t* keys_scratch, int32_t* vals_scratch, hipStream_t s, bool trace) {
     if (g.n_a <= 0) return;
     launch_fd_setup(g, pb, fb, S, tmp_keys, tmp_vals, hist, scan_tmp, keys_scratch, vals_scratch, s,
                     tune.fd_dgm && tune.fd_huc_pct == 0);
@@ -1335,6 +1343,10 @@ void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl
     FdJobs jobs{};
     jobs.one = FdJob{g, fb, pb.init, ctl, tune.fd_help_min, tune.fd_help_chunk, tune.fd_help_level_min,
                      tune.fd_huc_pct, tune.fd_dgm && tune.fd_huc_pct == 0 ? 1 : 0};
+    if (trace) {
+        jobs.trace = fb.task_trace;
+        jobs.trace_max = kFdTraceTasks;
+    }
     // every resident workgroup: those without a task of their own help
     // with the large subsets
     const int grid = std::max(1, big_grid);

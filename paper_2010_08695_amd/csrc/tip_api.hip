@@ -119,6 +119,7 @@ void plan(Arena& ar, int32_t n_a, int32_t n_b, int64_t m, int32_t P, int slots, 
     w.fb.sub_rcnt = ar.take<int64_t>(S + 2);
     w.fb.theta = ar.take<int64_t>(na);
     w.fb.board = ar.take<FdBoard>(1);
+    w.fb.task_trace = ar.take<unsigned long long>(4 * kFdTraceTasks);
     w.ctl = ar.take<Ctl>(1);
     w.total = ar.take<int64_t>(2);
     const int64_t keys = std::max<int64_t>(std::max(na, nb), 1);
@@ -403,10 +404,33 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
         ev.rec(3, s);
         // Fine-grained decomposition (Alg. 4).
         if (fd_inline) {
+            // diagnostic: with kernel timing on, TIP_TRACE_FD=1 prints every
+            // fine-grained task's size, levels and start and end times
+            static const bool trace_fd = [] {
+                const char* e = std::getenv("TIP_TRACE_FD");
+                return e && e[0] == '1';
+            }();
+            const bool tr = trace_fd && time_kernels && S > 0;
             if (S > 0)
                 launch_fd(g, pb, w.fb, S, w.ctl, tune, w.spill, big_grid, w.ib.keys2, w.ib.vals2, w.ib.hist,
-                          w.ib.scan_tmp, w.ib.keys, w.ib.vals, s);
+                          w.ib.scan_tmp, w.ib.keys, w.ib.vals, s, tr);
             ev.rec(4, s);
+            if (tr) {
+                const int32_t n = std::min<int32_t>(S, kFdTraceTasks);
+                std::vector<unsigned long long> h(4 * (size_t)n);
+                TIP_HIP_TRY(hipMemcpyAsync(h.data(), w.fb.task_trace, h.size() * sizeof(unsigned long long),
+                                           hipMemcpyDeviceToHost, s));
+                TIP_HIP_TRY(hipStreamSynchronize(s));
+                unsigned long long t0 = ~0ull;
+                for (int32_t t = 0; t < n; ++t)
+                    if (h[4 * t] > 0) t0 = std::min(t0, h[4 * t + 2]);
+                // the wall clock counts at 100 MHz
+                for (int32_t t = 0; t < n; ++t)
+                    if (h[4 * t] > 0)
+                        std::fprintf(stderr, "tip-fd-task task=%d n=%llu levels=%llu start_us=%.1f end_us=%.1f\n", t,
+                                     h[4 * t], h[4 * t + 1], (double)(h[4 * t + 2] - t0) / 100.0,
+                                     (double)(h[4 * t + 3] - t0) / 100.0);
+            }
         } else {
             launch_fd_setup(g, pb, w.fb, S, w.ib.keys2, w.ib.vals2, w.ib.hist, w.ib.scan_tmp, w.ib.keys, w.ib.vals, s,
                             tune.fd_dgm && tune.fd_huc_pct == 0);

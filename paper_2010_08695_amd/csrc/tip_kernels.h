@@ -158,6 +158,7 @@ struct FdBuffers {
     int64_t* sub_rcnt;   // [S + 2]
     int64_t* theta;      // [n_a] by rank
     FdBoard* board;      // task queue and help board of the launch
+    unsigned long long* task_trace;  // [4 * kFdTraceTasks] per-task timing (diagnostic)
 };
 
 // Update-kernel selection thresholds (tip_opts.tune[0], tune[1]).
@@ -228,6 +229,10 @@ struct FdJob {
 struct FdJobs {
     const FdJob* list;
     FdJob one;
+    // diagnostic: per task t < trace_max, (subset size, levels, start, end)
+    // in wall-clock ticks; null when not asked for
+    unsigned long long* trace;
+    int32_t trace_max;
 };
 
 // FD
@@ -244,7 +249,7 @@ void launch_fd_batch(const FdJob* d_jobs, const int64_t* d_tasks, int32_t n_task
 void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl, const Tune& tune,
                const SpillArena& spill,
                int big_grid, uint64_t* tmp_keys, int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp,
-               uint64_t* keys_scratch, int32_t* vals_scratch, hipStream_t s);
+               uint64_t* keys_scratch, int32_t* vals_scratch, hipStream_t s, bool trace = false);
 // output
 void launch_scatter_i64(const int64_t* by_rank, const int32_t* orig, int32_t n, int64_t* out, hipStream_t s);
 

@@ -180,6 +180,118 @@ def cmd_lds(args) -> int:
     return 0
 
 
+WAVE_COUNTERS = ["SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU",
+                 "SQ_ACTIVE_INST_LDS", "SQ_WAVES", "SQ_BUSY_CYCLES"]
+
+
+def cmd_waves(args) -> int:
+    """Where the waves of the top kernels spend their resident cycles, from
+    one counter run: waiting on memory or a barrier (SQ_WAIT_ANY), ready but
+    not issued (SQ_WAIT_INST_ANY), issuing (SQ_ACTIVE_INST_ANY, of which VALU
+    and LDS)."""
+    v = {c: counter_per_dispatch(args.dir, c) for c in WAVE_COUNTERS}
+    lines = [f"# wave states per kernel ({args.workload})", f"command: {args.cmd}", "",
+             "shares of the waves' resident cycles (SQ_WAVE_CYCLES): waiting for memory, LDS or a barrier",
+             "(SQ_WAIT_ANY), ready but not selected to issue (SQ_WAIT_INST_ANY), issuing any instruction",
+             "(SQ_ACTIVE_INST_ANY), of which VALU and LDS instructions", "",
+             f"{'kernel':<18}{'disp':>6}{'waves':>10}{'wait mem/bar':>14}{'wait issue':>12}{'issuing':>9}"
+             f"{'VALU':>7}{'LDS':>7}"]
+    for k in args.kernels.split(","):
+        tot = {c: sum(v[c].get(k, [])) for c in WAVE_COUNTERS}
+        n = len(v["SQ_WAVE_CYCLES"].get(k, []))
+        wc = tot["SQ_WAVE_CYCLES"]
+        if n == 0 or wc <= 0:
+            continue
+        lines.append(f"{k:<18}{n:>6}{tot['SQ_WAVES']:>10.3g}{tot['SQ_WAIT_ANY'] / wc:>14.3f}"
+                     f"{tot['SQ_WAIT_INST_ANY'] / wc:>12.3f}{tot['SQ_ACTIVE_INST_ANY'] / wc:>9.3f}"
+                     f"{tot['SQ_ACTIVE_INST_VALU'] / wc:>7.3f}{tot['SQ_ACTIVE_INST_LDS'] / wc:>7.3f}")
+    text = "\n".join(lines) + "\n"
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text)
+    return 0
+
+
+def cmd_launch(args) -> int:
+    """rocprofv3's average launch time of one kernel next to the figure the
+    bench line reports for it (HIP events on the launch stream)."""
+    st = {r["name"]: r for r in kernel_stats(args.dir)}.get(args.kernel)
+    if st is None:
+        raise SystemExit(f"kernel {args.kernel} not in {args.dir}")
+    bench = None
+    with open(args.bench_log) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("{") and '"roofline"' in line:
+                bench = json.loads(line)
+    if bench is None:
+        raise SystemExit(f"no bench line in {args.bench_log}")
+    rf = bench["roofline"]
+    mean_us = round(rf["mean_launch_ms"] * 1e3, 1) if rf.get("mean_launch_ms") else None
+    lines = [f"# {args.kernel} on {args.workload}: rocprofv3 average launch time vs the bench's HIP-event figure",
+             f"command: {args.cmd}", "",
+             f"rocprofv3: {args.kernel} {st['calls']} dispatches, total {st['total_ns'] / 1e6:.2f} ms, average "
+             f"{st['avg_ns'] / 1e3:.1f} us (min {st['min_ns'] / 1e3:.1f}, max {st['max_ns'] / 1e3:.1f})",
+             f"bench.py (HIP events on the launch stream, same run): mean {mean_us} us per launch" if mean_us
+             else "bench.py: no per-launch time in its line",
+             f"bench roofline: achieved {rf['achieved']:.1f} {rf['unit']} of {rf['peak']} -> frac {rf['frac']:.4f}"]
+    if rf.get("alg_bytes_per_launch"):
+        ab = rf["alg_bytes_per_launch"]
+        ach = ab / (st["avg_ns"] / 1e9) / 1e9
+        lines.append(f"algorithmic bytes per launch {ab / 1e6:.1f} MB / rocprofv3 average {st['avg_ns'] / 1e3:.1f} us "
+                     f"-> {ach:.1f} GB/s = {ach / 8000.0:.1%} of 8 TB/s")
+        tf = os.path.join(ROOT, "profiles", f"{args.kernel}.{args.workload}.traffic.txt")
+        if os.path.exists(tf):
+            with open(tf) as f:
+                tr = json.loads(f.readline())
+            lines.append(f"HBM traffic ({os.path.basename(tf)}): {tr['bytes_per_launch'] / 1e6:.1f} MB per launch, "
+                         f"{tr['bytes_per_launch'] / ab:.2f}x the algorithmic bytes")
+    text = "\n".join(lines) + "\n"
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text)
+    return 0
+
+
+def cmd_fdtrace(args) -> int:
+    """Critical path of one fine-grained launch from the tip-fd-task lines a
+    TIP_TRACE_FD=1 run prints (kernel timing on): the tasks that end last,
+    with their levels and time per level."""
+    import re
+    pat = re.compile(r"tip-fd-task task=(\d+) n=(\d+) levels=(\d+) start_us=([\d.]+) end_us=([\d.]+)")
+    runs, cur = [], []
+    with open(args.log) as f:
+        for line in f:
+            m = pat.search(line)
+            if m:
+                t = int(m.group(1))
+                if t == 0 and cur:
+                    runs.append(cur)
+                    cur = []
+                cur.append((t, int(m.group(2)), int(m.group(3)), float(m.group(4)), float(m.group(5))))
+    if cur:
+        runs.append(cur)
+    if not runs:
+        raise SystemExit(f"no tip-fd-task lines in {args.log}")
+    tasks = runs[-1]
+    span = max(e for *_, e in tasks)
+    lines = [f"# fine-grained launch ({args.workload}): per-task times and the critical path", f"command: {args.cmd}", "",
+             f"{len(tasks)} tasks (subsets); launch span {span / 1e3:.2f} ms (first task start to last task end)",
+             f"levels: {sum(t[2] for t in tasks)} in all, at most {max(t[2] for t in tasks)} in one subset", "",
+             "tasks ending last (subset size, levels, start, end, time per level):"]
+    for t, n, lv, s0, e in sorted(tasks, key=lambda x: -x[4])[: args.top]:
+        lines.append(f"  task {t:4d}  n_i {n:7d}  levels {lv:5d}  start {s0 / 1e3:7.3f} ms  end {e / 1e3:7.3f} ms  "
+                     f"{(e - s0) / max(lv, 1):7.1f} us/level")
+    text = "\n".join(lines) + "\n"
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -210,6 +322,28 @@ def main(argv=None) -> int:
     p.add_argument("--cmd", default="")
     p.add_argument("--out", default="")
     p.set_defaults(fn=cmd_lds)
+    p = sub.add_parser("waves")
+    p.add_argument("dir")
+    p.add_argument("--kernels", default="k_peel_dense,k_fd_peel,k_count_big,k_frontier_scan,k_peel_bitmap")
+    p.add_argument("--workload", default="cl-10m")
+    p.add_argument("--cmd", default="")
+    p.add_argument("--out", default="")
+    p.set_defaults(fn=cmd_waves)
+    p = sub.add_parser("launch")
+    p.add_argument("dir")
+    p.add_argument("--bench-log", required=True)
+    p.add_argument("--kernel", default="k_peel_dense")
+    p.add_argument("--workload", default="cl-10m")
+    p.add_argument("--cmd", default="")
+    p.add_argument("--out", default="")
+    p.set_defaults(fn=cmd_launch)
+    p = sub.add_parser("fdtrace")
+    p.add_argument("log")
+    p.add_argument("--workload", default="cl-10m")
+    p.add_argument("--top", type=int, default=12)
+    p.add_argument("--cmd", default="")
+    p.add_argument("--out", default="")
+    p.set_defaults(fn=cmd_fdtrace)
     args = ap.parse_args(argv)
     return args.fn(args)
 
