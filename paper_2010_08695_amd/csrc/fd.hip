@@ -7,13 +7,28 @@ namespace {
 // Fine-grained decomposition (Alg. 4)
 // ===========================================================================
 
-__global__ void k_fd_vertex_keys(const int32_t* __restrict__ state, int32_t n_a, uint64_t* keys, int32_t* vals,
-                                 int64_t* sub_cnt) {
+// Sort keys of the vertices by subset and the subsets' sizes.  With lds_hist
+// the sizes are counted in LDS per workgroup (S bins) and added to HBM once
+// per workgroup and subset: a million atomics on a few hundred addresses
+// would queue up at those addresses.
+__global__ void k_fd_vertex_keys(const int32_t* __restrict__ state, int32_t n_a, int32_t S, uint64_t* keys,
+                                 int32_t* vals, int64_t* sub_cnt, int lds_hist) {
+    extern __shared__ int32_t hist_s[];  // [S] when lds_hist
+    if (lds_hist) {
+        for (int32_t i = threadIdx.x; i < S; i += blockDim.x) hist_s[i] = 0;
+        __syncthreads();
+    }
     GRID_STRIDE(u, (int64_t)n_a) {
         const int32_t s = state[u];
         keys[u] = (uint64_t)s;
         vals[u] = (int32_t)u;
-        atomic_add_i64(&sub_cnt[s], 1);
+        if (lds_hist) atomicAdd(&hist_s[s], 1);
+        else atomic_add_i64(&sub_cnt[s], 1);
+    }
+    if (lds_hist) {
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < S; i += blockDim.x)
+            if (hist_s[i]) atomic_add_i64(&sub_cnt[i], hist_s[i]);
     }
 }
 
@@ -1296,7 +1311,13 @@ void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t 
     if (n_a <= 0) return;
     // vertices grouped by subset, ascending rank inside each subset
     fill_i64(fb.sub_cnt, 0, (int64_t)S + 1, s);
-    k_fd_vertex_keys<<<grid1(n_a), kT, 0, s>>>(pb.state, n_a, keys_scratch, fb.fd_vert, fb.sub_cnt);
+    {
+        // a few vertices per thread, so that each workgroup's LDS counts
+        // carry many of them
+        const int lds_hist = S <= kFdHistMax ? 1 : 0;
+        k_fd_vertex_keys<<<grid1(n_a, 256), kT, lds_hist ? sizeof(int32_t) * (size_t)S : 0, s>>>(
+            pb.state, n_a, S, keys_scratch, fb.fd_vert, fb.sub_cnt, lds_hist);
+    }
     TIP_HIP_TRY(hipGetLastError());
     radix_sort_pairs(keys_scratch, fb.fd_vert, tmp_keys, tmp_vals, n_a, bits_for((uint64_t)S), hist, scan_tmp, s);
     scan_exclusive_i64(fb.sub_cnt, fb.sub_off, (int64_t)S + 1, scan_tmp, s);

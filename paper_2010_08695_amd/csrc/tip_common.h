@@ -87,6 +87,7 @@ constexpr int kFdBits = 1 << 19;           // keys per bitmap tile for heavy pee
 constexpr int kFdRep = 2048;               // repeat slots of that path
 constexpr int kFdWaveSlots = 512;          // per-wave hash slots for light peeled vertices
 constexpr int64_t kFdWaveMax = 224;        // light: at most this many wedges inside the subset
+constexpr int kFdHistMax = 16384;          // subsets counted in LDS per workgroup at the fine-grained set-up
 constexpr int kFdTraceTasks = 4096;        // fine-grained tasks a diagnostic trace records
 constexpr int kFdLdsVerts = 2560;         // subsets up to this size keep their peeling state in LDS
 constexpr int kFdWaveKeys = 10240;        // subsets up to this size: per-wave 8-bit counters per vertex
