@@ -36,34 +36,60 @@ __global__ void k_fd_positions(const int32_t* __restrict__ fd_vert, int32_t n_a,
     GRID_STRIDE(p, (int64_t)n_a) fd_pos[fd_vert[p]] = (int32_t)p;
 }
 
-// Partitioned CSC: key (row, subset of the entry), value = entry's index
-// inside its subset.  The stable sort keeps each (row, subset) run ascending.
-__global__ void k_fd_csc_keys(DevGraph g, const int32_t* __restrict__ state, const int32_t* __restrict__ fd_pos,
-                              const int64_t* __restrict__ sub_off, int32_t S, uint64_t* keys, int32_t* vals) {
+// Partitioned CSC: key (row, subset of the entry), value = the entry's CSC
+// position (replaced after the sort by the entry's index inside its subset).
+// The stable sort keeps each (row, subset) run ascending.
+__global__ void k_fd_csc_keys(DevGraph g, const int32_t* __restrict__ state, int32_t S, uint64_t* keys,
+                              int32_t* vals) {
     GRID_STRIDE(q, g.m) {
+        keys[q] = (uint64_t)g.b_row[q] * (uint64_t)S + (uint64_t)state[g.b_adj[q]];
+        vals[q] = (int32_t)q;
+    }
+}
+
+// Entry q of the sorted partitioned CSC starts a (row, subset) run.
+__device__ inline bool fd_run_start(const uint64_t* __restrict__ pkeys, int64_t q) {
+    return q == 0 || pkeys[q] != pkeys[q - 1];
+}
+
+// The run of every sorted entry of the partitioned CSC: pos = exclusive scan
+// of the run-start flags, so entry i lies in run pos[i] + start(i) - 1;
+// run_lo[r] = the first entry of run r.
+__global__ void k_fd_run_lo(const uint64_t* __restrict__ pkeys, int64_t m, const int64_t* __restrict__ pos,
+                            int64_t* run_lo) {
+    GRID_STRIDE(i, m) if (fd_run_start(pkeys, i)) run_lo[pos[i]] = i;
+}
+
+// Every sorted entry i of the partitioned CSC is an edge (w, v) with w in
+// subset s: the CSR edge (w, v) gets the run [lo, hi) of N_v inside s (the
+// edges of the induced subgraph G_i seen from v, Alg. 4), and the entry's
+// value becomes w's index inside s.
+__global__ void k_fd_run_scatter(DevGraph g, const int32_t* __restrict__ state, const uint64_t* __restrict__ pkeys,
+                                 const int64_t* __restrict__ pos, const int64_t* __restrict__ run_lo,
+                                 const int32_t* __restrict__ fd_pos, const int64_t* __restrict__ sub_off,
+                                 int32_t* pcsc, int64_t* fd_beg, int32_t* fd_len) {
+    const int64_t m = g.m;
+    const int64_t n_runs = pos[m - 1] + (fd_run_start(pkeys, m - 1) ? 1 : 0);
+    GRID_STRIDE(i, m) {
+        const int64_t r = pos[i] + (fd_run_start(pkeys, i) ? 1 : 0) - 1;
+        const int64_t lo = run_lo[r];
+        const int64_t hi = r + 1 < n_runs ? run_lo[r + 1] : m;
+        const int32_t q = pcsc[i];  // the entry's CSC position
         const int32_t w = g.b_adj[q];
         const int32_t s = state[w];
-        keys[q] = (uint64_t)g.b_row[q] * (uint64_t)S + (uint64_t)s;
-        vals[q] = (int32_t)(fd_pos[w] - sub_off[s]);
+        const int64_t p = g.a_off[w] + g.b_rev[q];
+        fd_beg[p] = lo;
+        fd_len[p] = (int32_t)(hi - lo);
+        pcsc[i] = (int32_t)(fd_pos[w] - sub_off[s]);
     }
 }
 
-__device__ inline int64_t lower_bound_u64(const uint64_t* __restrict__ a, int64_t lo, int64_t hi, uint64_t key) {
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (a[mid] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// For every CSR edge (u, v): the run of N_v inside u's own subset, i.e. the
-// edges of the induced subgraph G_i seen from v (Alg. 4 induced subgraph),
-// and the induced wedges per subset (task_w) and per vertex (fd_w).  Subset
-// sums gather in LDS when there are few subsets (lds_tw); per-vertex sums are
-// segmented wave sums over the CSR rows.  Wave-uniform grid-stride loop.
-__global__ void k_fd_slices(DevGraph g, const int32_t* __restrict__ state, const uint64_t* __restrict__ pkeys,
-                            int32_t S, const int32_t* __restrict__ fd_pos, int64_t* fd_beg, int32_t* fd_len,
+// For every CSR edge (u, v) with its run in u's subset: the induced wedges
+// per subset (task_w) and per vertex (fd_w).  Subset sums gather in LDS when
+// there are few subsets (lds_tw); per-vertex sums are segmented wave sums
+// over the CSR rows.  Wave-uniform grid-stride loop.
+__global__ void k_fd_slices(DevGraph g, const int32_t* __restrict__ state, int32_t S,
+                            const int32_t* __restrict__ fd_pos, const int32_t* __restrict__ fd_len,
                             int64_t* task_w, int64_t* fd_w, int lds_tw) {
     extern __shared__ unsigned long long tw[];  // [S] when lds_tw
     const int lane = threadIdx.x & (kWave - 1);
@@ -77,14 +103,9 @@ __global__ void k_fd_slices(DevGraph g, const int32_t* __restrict__ state, const
         int64_t x = 0;
         if (p < g.m) {
             u = g.a_row[p];
-            const int32_t v = g.a_adj[p];
             const int32_t s = state[u];
-            const uint64_t k0 = (uint64_t)v * (uint64_t)S + (uint64_t)s;
-            const int64_t lo = lower_bound_u64(pkeys, g.b_off[v], g.b_off[v + 1], k0);
-            const int64_t hi = lower_bound_u64(pkeys, lo, g.b_off[v + 1], k0 + 1);
-            fd_beg[p] = lo;
-            fd_len[p] = (int32_t)(hi - lo);
-            x = hi - lo > 1 ? hi - lo - 1 : 0;
+            const int32_t len = fd_len[p];
+            x = len > 1 ? len - 1 : 0;
             if (x) {
                 if (lds_tw) atomicAdd(&tw[s], (unsigned long long)x);
                 else atomic_add_i64(&task_w[s], x);
@@ -106,13 +127,10 @@ __global__ void k_fd_slices(DevGraph g, const int32_t* __restrict__ state, const
     }
 }
 
-// Runs of the partitioned CSC (one per (row, subset) key), for compaction
-// in the fine-grained step (Section 4.2): every run's start position and
+// Runs of the partitioned CSC (one per (row, subset) key): their start
+// flags (which also give every CSR edge its run, above) and, for compaction
+// in the fine-grained step (Section 4.2), every run's start position and
 // subset, its length at the start, and the run count of every subset.
-__device__ inline bool fd_run_start(const uint64_t* __restrict__ pkeys, int64_t q) {
-    return q == 0 || pkeys[q] != pkeys[q - 1];
-}
-
 __global__ void k_fd_run_flags(const uint64_t* __restrict__ pkeys, int64_t m, int64_t* flag) {
     GRID_STRIDE(q, m) flag[q] = fd_run_start(pkeys, q) ? 1 : 0;
 }
@@ -1325,13 +1343,28 @@ void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t 
     TIP_HIP_TRY(hipGetLastError());
     fill_i64(fb.fd_w, 0, n_a, s);
     if (g.m > 0) {
-        k_fd_csc_keys<<<grid1(g.m), kT, 0, s>>>(g, pb.state, fb.fd_pos, fb.sub_off, S, fb.pkeys, fb.pcsc);
+        k_fd_csc_keys<<<grid1(g.m), kT, 0, s>>>(g, pb.state, S, fb.pkeys, fb.pcsc);
         TIP_HIP_TRY(hipGetLastError());
         radix_sort_pairs(fb.pkeys, fb.pcsc, tmp_keys, tmp_vals, g.m,
                          bits_for((uint64_t)g.n_b * (uint64_t)S), hist, scan_tmp, s);
+        {
+            // runs of the sorted entries (the sort's buffers are free again:
+            // keys_scratch holds the flags and their scan, tmp_keys the runs'
+            // first entries), then each CSR edge's run and each entry's index
+            int64_t* pos = reinterpret_cast<int64_t*>(keys_scratch);
+            int64_t* run_lo = reinterpret_cast<int64_t*>(tmp_keys);
+            k_fd_run_flags<<<grid1(g.m), kT, 0, s>>>(fb.pkeys, g.m, pos);
+            TIP_HIP_TRY(hipGetLastError());
+            scan_exclusive_i64(pos, pos, g.m, scan_tmp, s);
+            k_fd_run_lo<<<grid1(g.m), kT, 0, s>>>(fb.pkeys, g.m, pos, run_lo);
+            TIP_HIP_TRY(hipGetLastError());
+            k_fd_run_scatter<<<grid1(g.m), kT, 0, s>>>(g, pb.state, fb.pkeys, pos, run_lo, fb.fd_pos, fb.sub_off,
+                                                       fb.pcsc, fb.fd_beg, fb.fd_len);
+            TIP_HIP_TRY(hipGetLastError());
+        }
         const int lds_tw = S <= 4096 ? 1 : 0;
         k_fd_slices<<<grid1(g.m, 2048), kT, lds_tw ? sizeof(unsigned long long) * (size_t)S : 0, s>>>(
-            g, pb.state, fb.pkeys, S, fb.fd_pos, fb.fd_beg, fb.fd_len, fb.task_w, fb.fd_w, lds_tw);
+            g, pb.state, S, fb.fd_pos, fb.fd_len, fb.task_w, fb.fd_w, lds_tw);
         TIP_HIP_TRY(hipGetLastError());
         if (runs) {
             // the sort's buffers are free again: keys_scratch holds the flags
