@@ -92,17 +92,69 @@ __global__ void k_count_work(DevGraph g, int64_t* work) {
     }
 }
 
-__global__ void k_count_bins(const int64_t* __restrict__ work, int64_t n, int32_t* small, int32_t* big, Ctl* ctl) {
+// Start vertices by work item kind.  Almost every vertex is appended to one
+// of the two lists, so the list counters are reserved once per workgroup
+// for its whole contiguous chunk (counted in a first pass): per-wave appends
+// would queue tens of thousands of atomics on the two counters.
+constexpr int kBinsThreads = 256;
+
+__global__ void __launch_bounds__(kBinsThreads)
+k_count_bins(const int64_t* __restrict__ work, int64_t n, int32_t* small, int32_t* big, Ctl* ctl) {
+    constexpr int NW = kBinsThreads / kWave;
+    __shared__ int32_t wcnt[2][NW];
+    __shared__ int32_t base_l[2];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t c0 = (int64_t)blockIdx.x * chunk, c1 = min(n, c0 + chunk);
+    int32_t ns = 0, nb = 0;
     unsigned long long tot = 0;
-    UNIFORM_STRIDE(base, n) {
-        const int64_t i = base + threadIdx.x;
-        const int64_t w = i < n ? work[i] : 0;
+    for (int64_t i = c0 + tid; i < c1; i += kBinsThreads) {
+        const int64_t w = work[i];
         tot += (unsigned long long)w;
-        wave_append(w > 0 && w <= kSmallMaxWedges, (int32_t)i, small, &ctl->n_items[0]);
-        wave_append(w > kSmallMaxWedges, (int32_t)i, big, &ctl->n_items[1]);
+        ns += (w > 0 && w <= kSmallMaxWedges) ? 1 : 0;
+        nb += w > kSmallMaxWedges ? 1 : 0;
     }
     tot = (unsigned long long)wave_sum_i64((int64_t)tot);
-    if ((threadIdx.x & (kWave - 1)) == 0 && tot) atomicAdd(&ctl->wedges_count, tot);
+    if (lane == 0 && tot) atomicAdd(&ctl->wedges_count, tot);
+    ns = (int32_t)wave_sum_i64(ns);
+    nb = (int32_t)wave_sum_i64(nb);
+    if (lane == 0) {
+        wcnt[0][wid] = ns;
+        wcnt[1][wid] = nb;
+    }
+    __syncthreads();
+    if (tid < 2) {
+        int32_t t = 0;
+        for (int w = 0; w < NW; ++w) t += wcnt[tid][w];
+        base_l[tid] = t ? atomicAdd(&ctl->n_items[tid], t) : 0;
+    }
+    __syncthreads();
+    // second pass: positions in chunk order, one running offset per wave
+    // (waves take consecutive 64-entry slices in turn)
+    int32_t off_s = base_l[0], off_b = base_l[1];
+    for (int64_t b0 = c0; b0 < c1; b0 += kBinsThreads) {
+        const int64_t i = b0 + tid;
+        const int64_t w = i < c1 ? work[i] : 0;
+        const bool is_s = w > 0 && w <= kSmallMaxWedges, is_b = w > kSmallMaxWedges;
+        const uint64_t ms = __ballot(is_s), mb = __ballot(is_b);
+        if (lane == 0) {
+            wcnt[0][wid] = (int32_t)__popcll(ms);
+            wcnt[1][wid] = (int32_t)__popcll(mb);
+        }
+        __syncthreads();
+        int32_t ps = off_s, pb = off_b;
+        for (int w2 = 0; w2 < wid; ++w2) {
+            ps += wcnt[0][w2];
+            pb += wcnt[1][w2];
+        }
+        if (is_s) small[ps + (int32_t)__popcll(ms & lanemask_lt())] = (int32_t)i;
+        if (is_b) big[pb + (int32_t)__popcll(mb & lanemask_lt())] = (int32_t)i;
+        for (int w2 = 0; w2 < NW; ++w2) {
+            off_s += wcnt[0][w2];
+            off_b += wcnt[1][w2];
+        }
+        __syncthreads();  // wcnt is rewritten by the next slice
+    }
 }
 
 __global__ void __launch_bounds__(kSmallThreads)
@@ -349,7 +401,8 @@ void launch_count(const DevGraph& g, CountBuffers& cb, Ctl* ctl, const SpillAren
     if (g.m == 0) return;
     k_count_work<<<grid1(g.m), kT, 0, s>>>(g, cb.work);
     TIP_HIP_TRY(hipGetLastError());
-    k_count_bins<<<grid1(n_tot, 4096), kT, 0, s>>>(cb.work, n_tot, cb.items_small, cb.items_big, ctl);
+    k_count_bins<<<(unsigned)std::min<int64_t>(256, std::max<int64_t>(1, (n_tot + kBinsThreads - 1) / kBinsThreads)),
+                   kBinsThreads, 0, s>>>(cb.work, n_tot, cb.items_small, cb.items_big, ctl);
     TIP_HIP_TRY(hipGetLastError());
     k_count_small<<<2048, kSmallThreads, 0, s>>>(g, cb.items_small, ctl, cb.work, cb.bfly_a, cb.bfly_b, nullptr);
     TIP_HIP_TRY(hipGetLastError());

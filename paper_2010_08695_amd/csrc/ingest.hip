@@ -57,12 +57,29 @@ __global__ void k_unique_compact(const uint64_t* __restrict__ keys, const int64_
     }
 }
 
+// ea is sorted, so side A's degrees are counted per run of equal ids inside
+// each wave (one atomic per run piece); side B's ids are in no order.  The
+// loop's trip count is uniform across each wave.
 __global__ void k_degrees(const int32_t* __restrict__ ea, const int32_t* __restrict__ eb, const int64_t* m_p,
                           int32_t* deg_a, int32_t* deg_b) {
     const int64_t m = *m_p;
-    GRID_STRIDE(i, m) {
-        atomicAdd(&deg_a[ea[i]], 1);
-        atomicAdd(&deg_b[eb[i]], 1);
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        int32_t a = -1, x = 0;
+        if (i < m) {
+            a = ea[i];
+            x = 1;
+            atomicAdd(&deg_b[eb[i]], 1);
+        }
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t y = __shfl_up(x, d, 64);
+            const int32_t ay = __shfl_up(a, d, 64);
+            if (lane >= d && ay == a) x += y;
+        }
+        const int32_t an = __shfl_down(a, 1, 64);
+        if (a >= 0 && (lane == 63 || an != a)) atomicAdd(&deg_a[a], x);
     }
 }
 
