@@ -1215,12 +1215,18 @@ __global__ void k_set_key_hi(Ctl* ctl, int32_t v) { ctl->key_hi = v; }
 
 // Largest live rank + 1: every key the update can still touch is below it.
 __global__ void k_key_hi(const int32_t* __restrict__ state, int32_t n_a, Ctl* ctl) {
+    __shared__ int32_t bhi;
+    if (threadIdx.x == 0) bhi = 0;
+    __syncthreads();
     int32_t hi = 0;
     GRID_STRIDE(u, (int64_t)n_a)
         if (state[u] == kLive) hi = (int32_t)u + 1;
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) hi = max(hi, __shfl_xor(hi, d, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0 && hi) atomicMax(&ctl->key_hi, hi);
+    // one atomic per workgroup on the single address
+    if ((threadIdx.x & (kWave - 1)) == 0 && hi) atomicMax(&bhi, hi);
+    __syncthreads();
+    if (threadIdx.x == 0 && bhi) atomicMax(&ctl->key_hi, bhi);
 }
 
 __global__ void k_set_cd_m(Ctl* ctl, long long m, int32_t n_a) {
@@ -1311,7 +1317,7 @@ void launch_compact(const DevGraph& g, PeelBuffers& pb, const CompactScratch& cs
         TIP_HIP_TRY(hipGetLastError());
         k_set_key_hi<<<1, 1, 0, s>>>(ctl, 0);
         TIP_HIP_TRY(hipGetLastError());
-        k_key_hi<<<grid1(g.n_a, 2048), kT, 0, s>>>(pb.state, g.n_a, ctl);
+        k_key_hi<<<grid1(g.n_a, 512), kT, 0, s>>>(pb.state, g.n_a, ctl);
         TIP_HIP_TRY(hipGetLastError());
         k_peel_bins<<<grid1(g.n_a), kT, 0, s>>>(g.a_off, pb.wlive, g.n_a, tune.dense_div, tune.bitmap_max,
                                                 item_keys(pb), ctl, pb.bin);
@@ -1383,7 +1389,7 @@ void launch_round(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena
     // below then return at once); uses the original lists and their cuts
     if (cb) launch_recount(g, *cb, pb.state, ctl, spill, big_grid, s);
     if (has(kBinWave)) {
-        k_peel_wave<<<2048, kSmallThreads, 0, s>>>(gc, fs, pb.wlive, ap, ctl);
+        k_peel_wave<<<1024, kSmallThreads, 0, s>>>(gc, fs, pb.wlive, ap, ctl);
         TIP_HIP_TRY(hipGetLastError());
     }
     if (has(kBinBitmap)) {
@@ -1401,7 +1407,7 @@ void launch_round(const DevGraph& g, PeelBuffers& pb, Ctl* ctl, const SpillArena
         launch_dense(gc, pb, fs, ap, ctl, s);
         if (ev_big) TIP_HIP_TRY(hipEventRecord(ev_big[1], s));
     }
-    k_frontier_scan<<<grid1(g.n_a, 4096), kT, 0, s>>>(fs, pb.live[0], pb.live[1], pb.supp, pb.state, pb.wprox,
+    k_frontier_scan<<<grid1(g.n_a, 1024), kT, 0, s>>>(fs, pb.live[0], pb.live[1], pb.supp, pb.state, pb.wprox,
                                                        pb.bin, g.a_off, 1, ctl);
     TIP_HIP_TRY(hipGetLastError());
     k_ctl_swap_front<<<1, 1, 0, s>>>(ctl);
