@@ -1342,7 +1342,7 @@ void launch_select(PeelBuffers& pb, int cur_live, int32_t n_live, uint64_t max_s
     const int passes = (bits + 7) / 8;
     for (int p = passes - 1; p >= 0; --p) {
         const int shift = 8 * p;
-        k_select_hist<<<grid1(n_live, 2048), kT, 0, s>>>(pb.live[cur_live], n_live, pb.supp, pb.wprox, shift, ctl,
+        k_select_hist<<<grid1(n_live, 256), kT, 0, s>>>(pb.live[cur_live], n_live, pb.supp, pb.wprox, shift, ctl,
                                                           pb.sel_hist);
         TIP_HIP_TRY(hipGetLastError());
         k_select_pick<<<1, 256, 0, s>>>(shift, ctl, pb.sel_hist);
