@@ -263,7 +263,7 @@ __device__ inline void block_append(bool pred, int32_t val, int b, int32_t* cons
 }
 
 inline unsigned scan_grid(int64_t n) {
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, (n + kScanThreads - 1) / kScanThreads));
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(512, (n + kScanThreads - 1) / kScanThreads));
 }
 
 // Compacts the live list, snapshots the supports of the live vertices
@@ -1355,7 +1355,7 @@ void launch_range_begin(const DevGraph& g, PeelBuffers& pb, int cur_live, int32_
     k_set_range<<<1, 1, 0, s>>>(ctl, (long long)hi, (long long)max_supp, label, cur_live, n_live);
     TIP_HIP_TRY(hipGetLastError());
     if (n_live <= 0) return;
-    k_frontier_scan<<<grid1(n_live, 4096), kT, 0, s>>>(front_set(pb), pb.live[0], pb.live[1], pb.supp, pb.state,
+    k_frontier_scan<<<grid1(n_live, 1024), kT, 0, s>>>(front_set(pb), pb.live[0], pb.live[1], pb.supp, pb.state,
                                                         pb.wprox, pb.bin, g.a_off, 0, ctl);
     TIP_HIP_TRY(hipGetLastError());
     if (huc) {
