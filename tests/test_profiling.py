@@ -102,3 +102,58 @@ def test_lds_ratios_and_bandwidth(tmp_path, capsys):
     assert float(row[3]) == pytest.approx(0.2) and float(row[4]) == pytest.approx(0.05)
     assert float(row[5]) == pytest.approx(640.0) and float(row[7]) == pytest.approx(8.0)
     assert P.LDS_PEAK_TBS == pytest.approx(78.6432)
+
+
+def test_wave_state_shares(tmp_path, capsys):
+    d = _counters(tmp_path / "w", [
+        (1, "k_peel_dense", "SQ_WAVE_CYCLES", 1000.0), (1, "k_peel_dense", "SQ_WAIT_ANY", 550.0),
+        (1, "k_peel_dense", "SQ_WAIT_INST_ANY", 150.0), (1, "k_peel_dense", "SQ_ACTIVE_INST_ANY", 300.0),
+        (1, "k_peel_dense", "SQ_ACTIVE_INST_VALU", 160.0), (1, "k_peel_dense", "SQ_ACTIVE_INST_LDS", 30.0),
+        (1, "k_peel_dense", "SQ_WAVES", 16.0), (1, "k_peel_dense", "SQ_BUSY_CYCLES", 10.0),
+        (2, "k_peel_dense", "SQ_WAVE_CYCLES", 1000.0), (2, "k_peel_dense", "SQ_WAIT_ANY", 650.0),
+        (2, "k_peel_dense", "SQ_WAIT_INST_ANY", 50.0), (2, "k_peel_dense", "SQ_ACTIVE_INST_ANY", 300.0),
+        (2, "k_peel_dense", "SQ_ACTIVE_INST_VALU", 140.0), (2, "k_peel_dense", "SQ_ACTIVE_INST_LDS", 30.0),
+        (2, "k_peel_dense", "SQ_WAVES", 16.0), (2, "k_peel_dense", "SQ_BUSY_CYCLES", 10.0)])
+
+    class A:
+        dir, kernels, workload, cmd, out = d, "k_peel_dense,k_absent", "wl", "c", ""
+    assert P.cmd_waves(A) == 0
+    row = [l for l in capsys.readouterr().out.splitlines() if l.startswith("k_peel_dense")][0].split()
+    # summed over both dispatches: 1200 / 2000 waiting, 200 / 2000 ready, 600 / 2000 issuing
+    assert int(row[1]) == 2
+    assert [float(x) for x in row[3:]] == pytest.approx([0.6, 0.1, 0.3, 0.15, 0.03])
+
+
+def test_launch_summary_pairs_rocprof_with_the_bench_line(tmp_path, capsys):
+    t = _stats(tmp_path / "t", [("k_peel_dense", 4, 800e3)])   # 200 us per launch
+    log = tmp_path / "bench.log"
+    line = {"metric": "m", "roofline": {"achieved": 1000.0, "peak": 8000.0, "unit": "GB/s", "frac": 0.125,
+                                        "mean_launch_ms": 0.25, "alg_bytes_per_launch": 250e6}}
+    log.write_text("[bench] noise\n" + json.dumps(line) + "\n")
+
+    class A:
+        dir, bench_log, kernel, workload, cmd, out = t, str(log), "k_peel_dense", "wl", "c", ""
+    assert P.cmd_launch(A) == 0
+    out = capsys.readouterr().out
+    assert "average 200.0 us" in out and "mean 250.0 us per launch" in out
+    # 250 MB over rocprofv3's 200 us: 1250 GB/s
+    assert "1250.0 GB/s" in out and "15.6% of 8 TB/s" in out
+
+
+def test_fd_trace_critical_path(tmp_path, capsys):
+    log = tmp_path / "fd.log"
+    lines = ["tip-fd-task task=0 n=10 levels=5 start_us=0.0 end_us=50.0",   # an earlier run: superseded
+             "tip-fd-task task=0 n=100 levels=10 start_us=0.0 end_us=200.0",
+             "tip-fd-task task=1 n=3000 levels=100 start_us=1.0 end_us=901.0",
+             "tip-fd-task task=2 n=40 levels=4 start_us=0.5 end_us=40.5"]
+    # the first line starts a run that the second (task 0 again) ends
+    log.write_text("\n".join(lines) + "\n")
+
+    class A:
+        workload, top, cmd, out = "wl", 2, "c", ""
+    A.log = str(log)
+    assert P.cmd_fdtrace(A) == 0
+    out = capsys.readouterr().out
+    assert "3 tasks" in out and "launch span 0.90 ms" in out and "at most 100 in one subset" in out
+    tops = [l for l in out.splitlines() if l.strip().startswith("task ") and "n_i" in l]
+    assert len(tops) == 2 and "n_i    3000" in tops[0] and "9.0 us/level" in tops[0]
