@@ -106,6 +106,17 @@ typedef struct {
  * entries held by peeled vertices.  Same results. */
 #define TIP_FLAG_DGM_PAPER 128
 
+/* TIP_FLAG_FD_WALK: every update of the fine-grained step walks the peeled
+ * vertex's wedges inside G_i (Alg. 4 as written) instead of reading its
+ * pair row.  By default, before peeling, each vertex u of a subset U_i gets
+ * the list of every w in U_i with c = |N(u) ∩ N(w)| >= 2 and C(c, 2): the
+ * update of u in Alg. 4, which does not change while U_i is peeled because
+ * the other side is never peeled.  The rows of a subset are built only if
+ * they fit the workspace's pair budget (tip_workspace_size includes it);
+ * other subsets, and every subset under TIP_FLAG_FD_DGM or tune[7], walk.
+ * Same results. */
+#define TIP_FLAG_FD_WALK 256
+
 /* Options.  Zero-initialised means defaults. */
 typedef struct {
     int32_t P;       /* number of tip-number ranges of the coarse-grained step
@@ -177,6 +188,8 @@ typedef struct {
     int64_t huc_rounds;    /* coarse-grained rounds that re-counted instead of peeling (tune[3]) */
     int64_t fd_huc_steps;  /* fine-grained steps that re-counted instead of peeling (tune[7]) */
     int64_t compactions;   /* list compactions: coarse-grained (low 32 bits) + fine-grained << 32 */
+    int64_t fd_pair_entries; /* entries of the fine-grained pair rows built (TIP_FLAG_FD_WALK) */
+    int64_t fd_pair_subsets; /* subsets peeled from pair rows; the others walked their wedges */
 } tip_stats;
 
 /* Per-vertex butterfly counts of both sides (Alg. 1, Section 2.1) and the

@@ -1,6 +1,9 @@
 // Fine-grained decomposition (Alg. 4) and output scatter.
 #include "kern_util.h"
 
+#include <cstdlib>
+#include <mutex>
+
 namespace tip {
 namespace {
 // ===========================================================================
@@ -211,6 +214,7 @@ struct FdLds {
     unsigned long long racc[kFdThreads / kWave];  // HUC re-count sums, per wave
     int64_t hx_off[kFdHeavyPre];  // row offset and degree of a level's heavy vertices
     int32_t hx_deg[kFdHeavyPre];
+    int32_t pn[kFdThreads / kWave + 1];  // pair-row build: entries of the row each wave (last: the workgroup) writes
 };
 
 // Next entry of the level's per-wave update list for the calling wavefront.
@@ -340,6 +344,7 @@ struct FdHbmState {
         const int64_t old = atomic_add_i64_ret(&sup[w], -d);
         if (old > level && old - d <= level) cx[atomicAdd(cxn, 1)] = w;
     }
+    static constexpr bool kMinLocal = false;
 };
 
 // HUC inside a subset (Section 4.1, last paragraph).  The support of a live
@@ -367,12 +372,100 @@ struct FdLdsState {
                                                (unsigned long long)(-d));
         atomicMin(&S->upd_min, (long long)(old - d));
     }
+    // the same, with the least support left folded in per wave by the caller
+    static constexpr bool kMinLocal = true;
+    __device__ inline int64_t dec_ret(int32_t w, int64_t d) const {
+        return (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&S->sup[w]), (unsigned long long)(-d)) - d;
+    }
+    __device__ inline void fold_min(int64_t mn) const { atomicMin(&S->upd_min, (long long)mn); }
 };
+
+// The pair-row build as the "state" of the update routines: instead of
+// decrementing w's support by C(c, 2), append (w, C(c, 2)) to the row of the
+// vertex being counted; n is the row's LDS entry counter.
+struct FdPairWriter {
+    const int32_t* vert;
+    int32_t* pw;
+    int64_t* pb;
+    int32_t* n;
+    __device__ inline bool live(int32_t) const { return true; }
+    __device__ inline int32_t vtx(int32_t x) const { return vert[x]; }
+    __device__ inline void dec(int32_t w, int64_t d) const {
+        const int32_t k = atomicAdd(n, 1);
+        pw[k] = w;
+        pb[k] = d;
+    }
+};
+
+// Updates of a step from pair rows: the rows of nq peeled vertices, row q
+// given by row(q, start, length).  Rows are cut into units of 64 entries;
+// every wave takes units round-robin over all rows, four at a time, so that
+// one long row spreads over the workgroup and short rows do not leave waves
+// idle.  A unit's row is found by a ballot over the units' prefix sums of
+// 64 rows at a time.  All threads call.
+template <class St, class RowF>
+__device__ inline void fd_pair_units(const FdBuffers& fb, int32_t nq, const RowF& row, const St& st,
+                                     unsigned long long& pairs) {
+    constexpr int NW = kFdThreads / kWave, R = 4;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    int64_t mn = INT64_MAX;
+    int32_t ub = 0;  // units of the rows before the current group of 64
+    for (int32_t g0 = 0; g0 < nq; g0 += kWave) {
+        const int gs = min(kWave, nq - g0);
+        int64_t off = 0;
+        int32_t len = 0;
+        if (lane < gs) row(g0 + lane, off, len);
+        const int32_t units = (len + kWave - 1) / kWave;
+        const int32_t incl = wave_incl_scan_i32(units);
+        const int32_t nu = __shfl(incl, kWave - 1, kWave);
+        const int32_t pre = incl - units;
+        // first unit of this group that falls to this wave
+        const int32_t k_first = (int32_t)(((wid - ub) % NW + NW) % NW);
+        for (int32_t k0 = k_first; k0 < nu; k0 += NW * R) {
+            int32_t ws[R];
+            int64_t bs[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int32_t k = k0 + r * NW;
+                ws[r] = -1;
+                bs[r] = 0;
+                if (k < nu) {
+                    const uint64_t le = __ballot(pre <= k);
+                    const int j = 63 - __clzll((long long)le);
+                    const int64_t oj = __shfl(off, j, kWave);
+                    const int32_t lj = __shfl(len, j, kWave), pj = __shfl(pre, j, kWave);
+                    const int32_t i = (k - pj) * kWave + lane;
+                    if (i < lj) {
+                        ws[r] = fb.prow_w[oj + i];
+                        bs[r] = fb.prow_b[oj + i];
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (ws[r] >= 0 && st.live(ws[r])) {
+                    if constexpr (St::kMinLocal) {
+                        const int64_t v = st.dec_ret(ws[r], bs[r]);
+                        mn = v < mn ? v : mn;
+                    } else {
+                        st.dec(ws[r], bs[r]);
+                    }
+                    ++pairs;
+                }
+            }
+        }
+        ub += nu;
+    }
+    if constexpr (St::kMinLocal) {
+        mn = wave_min_i64(mn);
+        if (lane == 0 && mn != INT64_MAX) st.fold_min(mn);
+    }
+}
 
 // Update of one light peeled vertex x (few wedges inside the subset) by one
 // wavefront with its private hash table of `slots` entries.
-template <class St>
-__device__ inline void fd_update_light(const DevGraph& g, const FdBuffers& fb, FdLds& L, unsigned long long* tab,
+template <class St, class Lds>
+__device__ inline void fd_update_light(const DevGraph& g, const FdBuffers& fb, Lds& L, unsigned long long* tab,
                                        int32_t x, uint32_t slots, const St& st, unsigned long long& wedges,
                                        unsigned long long& pairs) {
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -436,8 +529,8 @@ __device__ inline uint32_t ge2_bytes(uint32_t v) {
 // Update of one peeled vertex x of degree at most 255 in a subset of at most
 // kFdWaveKeys vertices by one wavefront: one 8-bit LDS counter per vertex of
 // the subset (c(x, w) <= d_x fits), scanned and cleared afterwards.
-template <class St>
-__device__ inline void fd_update_wave_dense(const DevGraph& g, const FdBuffers& fb, FdLds& L, uint32_t* cnt,
+template <class St, class Lds>
+__device__ inline void fd_update_wave_dense(const DevGraph& g, const FdBuffers& fb, Lds& L, uint32_t* cnt,
                                             int32_t x, int32_t n_i, const St& st, unsigned long long& wedges,
                                             unsigned long long& pairs) {
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -814,11 +907,13 @@ __device__ inline void fd_compact_runs(const DevGraph& g, const FdBuffers& fb, F
     __syncthreads();
 }
 
-// Level loop of a subset whose state lives in HBM.
+// Level loop of a subset whose state lives in HBM.  With pair rows (pr)
+// every peeled vertex is on the per-wave list and its row replaces the walk;
+// pair steps are not published on the help board.
 __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const int64_t* __restrict__ init,
                                    int64_t P0, int32_t n_i, FdLds& L, unsigned long long* tab, const Spill& sp,
                                    FdHelpSlot* hs, int32_t help_chunk, int32_t help_level_min, int32_t huc_pct,
-                                   int32_t sub, int32_t dgm, unsigned long long& wedges, unsigned long long& pairs,
+                                   int32_t sub, int32_t dgm, bool pr, unsigned long long& wedges, unsigned long long& pairs,
                                    unsigned long long& levels, unsigned long long& spills,
                                    unsigned long long& huc_steps, unsigned long long& compactions) {
     constexpr int NT = kFdThreads;
@@ -840,7 +935,7 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
         lc[j] = j;
         const int32_t v = vert[j];
         sup[j] = init[v];
-        alive[j] = kFdAlive | (fd_heavy(g, fb, P0, n_i, j) ? kFdHeavy : 0);
+        alive[j] = kFdAlive | (!pr && fd_heavy(g, fb, P0, n_i, j) ? kFdHeavy : 0);
         wsum += fw[j];
         if (dgm) esum += g.a_off[v + 1] - g.a_off[v];
     }
@@ -981,10 +1076,11 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
                 continue;
             }
         }
-        const bool publish = hs && n_light >= help_level_min;
+        const bool publish = !pr && hs && n_light >= help_level_min;
         // heavy updates are shared only when there are several and enough
         // wedges to outweigh the board's fences
-        const bool publish_heavy = hs && n_heavy >= kFdHelpHeavyMin && L.hw >= (unsigned long long)kFdHelpHeavyWedges;
+        const bool publish_heavy =
+            !pr && hs && n_heavy >= kFdHelpHeavyMin && L.hw >= (unsigned long long)kFdHelpHeavyWedges;
         // a small step (not published, so no helper decrements) tracks the
         // vertices it drops to the level
         const bool track = !publish && !publish_heavy && n_light + n_heavy <= kFdCascadeMax;
@@ -1010,6 +1106,25 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
                     __builtin_amdgcn_s_sleep(2);
             __syncthreads();
             __threadfence();
+        } else if (pr) {
+            // rows' starts and lengths for up to kFdHeavyPre peeled vertices
+            // at a time, then their entries
+            __syncthreads();
+            for (int32_t c0 = 0; c0 < n_light; c0 += kFdHeavyPre) {
+                const int32_t nq = min(kFdHeavyPre, n_light - c0);
+                for (int32_t q = tid; q < nq; q += NT) {
+                    const int32_t x = pl[c0 + q];
+                    L.hx_off[q] = fb.prow_off[P0 + x];
+                    L.hx_deg[q] = fb.prow_n[P0 + x];
+                }
+                __syncthreads();
+                const auto row = [&](int32_t q, int64_t& off, int32_t& len) {
+                    off = L.hx_off[q];
+                    len = L.hx_deg[q];
+                };
+                fd_pair_units(fb, nq, row, st, pairs);
+                __syncthreads();
+            }
         } else {
             __syncthreads();
             for (int32_t q = fd_next_wave_item(L); q < n_light; q = fd_next_wave_item(L)) {
@@ -1058,9 +1173,13 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
 // kept support.  The next level's minimum is the least of that and of the
 // supports the decrements leave behind: a kept vertex that no decrement
 // touched still has the support read in the pass.
+//
+// With pair rows (pr), the rows' starts (relative to the subset's first row)
+// and lengths are kept in the LDS of the update tables, which pair updates
+// do not use, and cleared at the end.
 __device__ inline void fd_peel_lds(const DevGraph& g, const FdBuffers& fb, const int64_t* __restrict__ init,
                                    int64_t P0, int32_t n_i, FdLds& L, FdSmall& S, unsigned long long* tab,
-                                   const Spill& sp, unsigned long long& wedges, unsigned long long& pairs,
+                                   const Spill& sp, bool pr, unsigned long long& wedges, unsigned long long& pairs,
                                    unsigned long long& levels, unsigned long long& spills) {
     constexpr int NT = kFdThreads;
     constexpr int NW = NT / kWave;
@@ -1068,15 +1187,23 @@ __device__ inline void fd_peel_lds(const DevGraph& g, const FdBuffers& fb, const
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     uint32_t* wcnt = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(&L.u) + (size_t)wid * kFdWaveKeys);
     const FdLdsState st{&S};
+    static_assert(sizeof(FdLds::Shared) >= (size_t)kFdLdsVerts * 6, "pair-row starts and lengths fit the union");
+    int32_t* roff = reinterpret_cast<int32_t*>(&L.u);
+    uint16_t* rn = reinterpret_cast<uint16_t*>(roff + kFdLdsVerts);
+    const int64_t rbase = pr ? fb.prow_off[P0] : 0;
     int64_t mn = INT64_MAX;
     for (int32_t j = tid; j < n_i; j += NT) {
         const int32_t v = fb.fd_vert[P0 + j];
         const int64_t s0 = init[v];
         S.vert[j] = v;
         S.sup[j] = s0;
-        S.flag[j] = kFdAlive | (fd_heavy(g, fb, P0, n_i, j) ? kFdHeavy : 0);
+        S.flag[j] = kFdAlive | (!pr && fd_heavy(g, fb, P0, n_i, j) ? kFdHeavy : 0);
         S.lc[j] = (uint16_t)j;
         mn = s0 < mn ? s0 : mn;
+        if (pr) {
+            roff[j] = (int32_t)(fb.prow_off[P0 + j] - rbase);
+            rn[j] = (uint16_t)fb.prow_n[P0 + j];
+        }
     }
     mn = fd_min<NT>(L, mn);
     uint16_t* lc = S.lc;
@@ -1136,16 +1263,33 @@ __device__ inline void fd_peel_lds(const DevGraph& g, const FdBuffers& fb, const
         }
         __syncthreads();
         levels += tid == 0;
-        for (int32_t q = fd_next_wave_item(L); q < n_light; q = fd_next_wave_item(L))
-            fd_update_wave_dense(g, fb, L, wcnt, (int32_t)S.pl[q], n_i, st, wedges, pairs);
-        __syncthreads();
-        fd_heavy_level(g, fb, L, sp, S.ph, n_heavy, n_i, st, wedges, pairs, spills);
+        if (pr) {
+            // every peeled vertex is on the light list (no heavy flags)
+            const auto row = [&](int32_t q, int64_t& off, int32_t& len) {
+                const int32_t x = (int32_t)S.pl[q];
+                off = rbase + (int64_t)roff[x];
+                len = (int32_t)rn[x];
+            };
+            fd_pair_units(fb, n_light, row, st, pairs);
+        } else {
+            for (int32_t q = fd_next_wave_item(L); q < n_light; q = fd_next_wave_item(L))
+                fd_update_wave_dense(g, fb, L, wcnt, (int32_t)S.pl[q], n_i, st, wedges, pairs);
+            __syncthreads();
+            fd_heavy_level(g, fb, L, sp, S.ph, n_heavy, n_i, st, wedges, pairs, spills);
+        }
         __syncthreads();
         mn = min<int64_t>(bmin, (int64_t)S.upd_min);
         uint16_t* tmp = lc;
         lc = ln;
         ln = tmp;
         n_live = n_keep;
+    }
+    if (pr) {
+        // the update tables are all zero between uses
+        uint32_t* z = reinterpret_cast<uint32_t*>(&L.u);
+        const int32_t words = kFdLdsVerts * 6 / 4;
+        for (int32_t i = tid; i < words; i += NT) z[i] = 0;
+        __syncthreads();
     }
 }
 
@@ -1187,12 +1331,15 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
         if (n_i == 0) continue;
         unsigned long long wedges = 0, pairs = 0, levels = 0, spills = 0, huc_steps = 0, compactions = 0;
         const unsigned long long t_start = jobs.trace ? wall_clock64() : 0ull;
+        // pair rows, when this subset's were built
+        const bool pr = fb.pairs_on && fb.prow_off[P0 + n_i] <= fb.pair_lim;
+        if (pr && tid == 0) atomicAdd(&J.ctl->fd_pair_tasks, 1ull);
         if (n_i <= kFdLdsVerts) {
-            fd_peel_lds(J.g, fb, J.init, P0, n_i, L, S, tab, sp, wedges, pairs, levels, spills);
+            fd_peel_lds(J.g, fb, J.init, P0, n_i, L, S, tab, sp, pr, wedges, pairs, levels, spills);
         } else {
             // a large subset opens a help-board slot for its per-wave updates
             FdHelpSlot* hs = nullptr;
-            if (n_i >= J.help_min) {
+            if (!pr && n_i >= J.help_min) {
                 if (tid == 0) {
                     const int32_t k = atomicAdd(&board->n_slots, 1);
                     L.flag = k;
@@ -1213,8 +1360,9 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
                 if (L.flag < kFdHelpSlots) hs = &board->slot[L.flag];
                 __syncthreads();
             }
-            fd_peel_hbm(J.g, fb, J.init, P0, n_i, L, tab, sp, hs, J.help_chunk, J.help_level_min, J.huc_pct, sub,
-                        J.dgm, wedges, pairs, levels, spills, huc_steps, compactions);
+            fd_peel_hbm(J.g, fb, J.init, P0, n_i, L, tab, sp, hs, J.help_chunk, J.help_level_min,
+                        pr ? 0 : J.huc_pct, sub, pr ? 0 : J.dgm, pr, wedges, pairs, levels, spills, huc_steps,
+                        compactions);
             if (hs && tid == 0) atomicExch(&hs->state, 2);
         }
         if (jobs.trace && tid == 0 && t < jobs.trace_max) {
@@ -1308,12 +1456,204 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
     }
 }
 
+// Pair rows (the fine-grained updates, precomputed).  Peeling u inside U_i
+// lowers the support of every w of U_i by C(c, 2), c = |N(u) ∩ N(w)| (the
+// update of Alg. 4 on G_i).  Only side A is peeled, so c never changes while
+// U_i is peeled, and u's update can be listed once, before any peeling,
+// with every vertex counted in parallel.  Row capacity of the vertex at
+// position p: min(n_i - 1, fd_w[p] / 2), since every listed w takes at least
+// two of u's induced wedges.  cap[n_a] = 0, so that an exclusive scan leaves
+// the total there.
+__global__ void k_fd_pair_cap(const int32_t* __restrict__ state, const int32_t* __restrict__ fd_vert,
+                              const int64_t* __restrict__ sub_off, const int64_t* __restrict__ fd_w, int32_t n_a,
+                              int64_t* cap) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > n_a) return;
+    int64_t c = 0;
+    if (p < n_a) {
+        const int32_t sub = state[fd_vert[p]];
+        const int64_t n_i = sub_off[sub + 1] - sub_off[sub];
+        c = min<int64_t>(n_i - 1, fd_w[p] / 2);
+    }
+    cap[p] = c;
+}
+
+// LDS of the per-wave pair-row build: per wave 8 KiB (8-bit counters of a
+// subset of at most kFdPairWaveKeys vertices, or a hash table of up to
+// kFdPairWaveSlots slots) and the staging of its neighbour runs.
+constexpr int kFdPairThreads = 256;
+constexpr int kFdPairWaves = kFdPairThreads / kWave;
+constexpr int kFdPairWaveKeys = 8192;
+constexpr int kFdPairWaveSlots = 1024;
+constexpr int64_t kFdPairHashMax = 448;     // hash path: at most this many wedges (table at most 7/16 full)
+constexpr int64_t kFdPairDenseMax = 4096;   // counter path: at most this many wedges for one wave
+struct FdPairLds {
+    union Shared {
+        uint32_t cnt[kFdPairWaves][kFdPairWaveKeys / 4];
+        unsigned long long wtab[kFdPairWaves][kFdPairWaveSlots];
+    } u;
+    int64_t wsbeg[kFdPairWaves][kWave];
+    int64_t wpre[kFdPairWaves][kWave + 1];
+    int32_t pn[kFdPairWaves];
+};
+
+// Pair rows of the light vertices, every wave on its own (no workgroup
+// barrier): a wave takes 64 positions at a time, strided over the whole
+// range so that the hubs at the front of each subset (ranks ascend inside a
+// subset) spread over many waves, classifies them in its lanes, counts each
+// light vertex's wedges inside its subset (8-bit
+// counters in a subset of at most kFdPairWaveKeys vertices, else a hash
+// table) and writes the pairs instead of decrementing.  The other vertices
+// go to the heavy list (one atomic per wave and chunk) for
+// k_fd_pair_rows_heavy.  Only subsets whose rows fit fb.pair_lim.
+__global__ void __launch_bounds__(kFdPairThreads)
+k_fd_pair_rows(DevGraph g, FdBuffers fb, const int32_t* __restrict__ state, int32_t* heavy, Ctl* ctl) {
+    __shared__ FdPairLds L;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int32_t n_a = g.n_a;
+    {
+        unsigned long long* mine = L.u.wtab[wid];
+        for (int i = lane; i < kFdPairWaveSlots; i += kWave) mine[i] = 0;
+        if (lane == 0) L.pn[wid] = 0;
+    }
+    wave_sync();
+    uint32_t* wcnt = L.u.cnt[wid];
+    unsigned long long* tab = L.u.wtab[wid];
+    unsigned long long wedges = 0, entries = 0, unused = 0;
+    // chunk c holds positions c + k * n_chunks, k < 64
+    const int32_t n_chunks = (int32_t)(((int64_t)n_a + kWave - 1) / kWave);
+    for (;;) {
+        int32_t c = 0;
+        if (lane == 0) c = atomicAdd(&fb.board->pair_head, 1);
+        c = __shfl(c, 0, kWave);
+        if (c >= n_chunks) break;
+        const int32_t p = (int32_t)min<int64_t>((int64_t)c + (int64_t)lane * n_chunks, (int64_t)n_a);
+        int kind = -1;  // 0: counters, 1: hash, 2: heavy
+        int64_t P0 = 0, w = 0;
+        int32_t n_i = 0;
+        if (p < n_a) {
+            const int32_t ux = fb.fd_vert[p];
+            const int32_t sub = state[ux];
+            P0 = fb.sub_off[sub];
+            n_i = (int32_t)(fb.sub_off[sub + 1] - P0);
+            w = fb.fd_w[p];
+            const int64_t d = g.a_off[ux + 1] - g.a_off[ux];
+            if (fb.prow_off[P0 + n_i] <= fb.pair_lim) {
+                if (w < 2) fb.prow_n[p] = 0;
+                else if (n_i <= kFdPairWaveKeys && d <= 255 && w <= kFdPairDenseMax) kind = 0;
+                else if (w <= kFdPairHashMax) kind = 1;
+                else kind = 2;
+            }
+        }
+        const uint64_t hm = __ballot(kind == 2);
+        if (hm) {
+            int32_t base = 0;
+            if (lane == 0) base = atomicAdd(&fb.board->pair_heavy, (int32_t)__popcll(hm));
+            base = __shfl(base, 0, kWave);
+            if (kind == 2) heavy[base + (int32_t)__popcll(hm & lanemask_lt())] = p;
+        }
+        uint64_t lm = __ballot(kind == 0 || kind == 1);
+        while (lm) {
+            const int t = __ffsll((unsigned long long)lm) - 1;
+            lm &= lm - 1;
+            const int32_t pt = __shfl(p, t, kWave);
+            const int64_t P0t = __shfl(P0, t, kWave), wt = __shfl(w, t, kWave);
+            const int32_t n_it = __shfl(n_i, t, kWave), kt = __shfl(kind, t, kWave);
+            const int64_t r0 = fb.prow_off[pt];
+            const FdPairWriter st{fb.fd_vert + P0t, fb.prow_w + r0, fb.prow_b + r0, &L.pn[wid]};
+            const int32_t j = (int32_t)(pt - P0t);
+            if (kt == 0) fd_update_wave_dense(g, fb, L, wcnt, j, n_it, st, wedges, unused);
+            else fd_update_light(g, fb, L, tab, j, min<uint32_t>(kFdPairWaveSlots, wave_slots(wt)), st, wedges, unused);
+            if (lane == 0) {
+                const int32_t n = L.pn[wid];
+                fb.prow_n[pt] = n;
+                entries += (unsigned long long)n;
+                L.pn[wid] = 0;
+            }
+            wave_sync();
+        }
+    }
+    if (lane == 0) {
+        if (wedges) atomicAdd(&ctl->wedges_fd, wedges);
+        if (entries) atomicAdd(&ctl->fd_pair_entries, entries);
+    }
+}
+
+// Pair rows of the heavy list: each workgroup takes one vertex at a time and
+// counts it with its LDS bitmap and repeat table (fd_update_heavy).
+__global__ void __launch_bounds__(kFdThreads)
+k_fd_pair_rows_heavy(DevGraph g, FdBuffers fb, const int32_t* __restrict__ state, const int32_t* __restrict__ heavy,
+                     Ctl* ctl, SpillArena spa) {
+    __shared__ FdLds L;
+    constexpr int NT = kFdThreads;
+    constexpr int NW = NT / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    {
+        unsigned long long* all = &L.u.wtab[0][0];
+        for (int i = tid; i < (int)(sizeof(L.u) / 8); i += NT) all[i] = 0;
+    }
+    if (tid == 0) {
+        L.spill_n = 0;
+        L.pn[NW] = 0;
+    }
+    const int32_t n_heavy = fb.board->pair_heavy;
+    if (blockIdx.x == 0 && tid == 0) ctl->fd_pair_heavy = (unsigned long long)n_heavy;
+    const Spill sp{spa.dense + (int64_t)blockIdx.x * spa.stride, spa.list + (int64_t)blockIdx.x * spa.stride};
+    unsigned long long wedges = 0, spills = 0, entries = 0, unused = 0;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) L.flag = atomicAdd(&fb.board->pair_head2, 1);
+        __syncthreads();
+        const int32_t q = L.flag;
+        if (q >= n_heavy) break;
+        const int32_t p = heavy[q];
+        const int32_t ux = fb.fd_vert[p];
+        const int32_t sub = state[ux];
+        const int64_t P0 = fb.sub_off[sub];
+        const int32_t n_i = (int32_t)(fb.sub_off[sub + 1] - P0);
+        const int64_t r0 = fb.prow_off[p];
+        const int64_t e0 = g.a_off[ux], d = g.a_off[ux + 1] - e0;
+        const FdPairWriter st{fb.fd_vert + P0, fb.prow_w + r0, fb.prow_b + r0, &L.pn[NW]};
+        fd_update_heavy(g, fb, L, sp, (int32_t)(p - P0), e0, d, n_i, st, wedges, unused, spills);
+        if (tid == 0) {
+            fb.prow_n[p] = L.pn[NW];
+            entries += (unsigned long long)L.pn[NW];
+            L.pn[NW] = 0;
+        }
+    }
+    wedges = (unsigned long long)wave_sum_i64((int64_t)wedges);
+    spills = (unsigned long long)wave_sum_i64((int64_t)spills);
+    entries = (unsigned long long)wave_sum_i64((int64_t)entries);
+    if (lane == 0) {
+        if (wedges) atomicAdd(&ctl->wedges_fd, wedges);
+        if (spills) atomicAdd(&ctl->spills, spills);
+        if (entries) atomicAdd(&ctl->fd_pair_entries, entries);
+    }
+}
+
 __global__ void k_scatter_i64(const int64_t* __restrict__ by_rank, const int32_t* __restrict__ orig, int32_t n,
                               int64_t* out) {
     GRID_STRIDE(r, (int64_t)n) out[orig[r]] = by_rank[r];
 }
 
 }  // namespace
+
+// Resident workgroups of the per-wave pair-row build on the current device.
+int pair_grid() {
+    static std::mutex mu;
+    static int cached_dev = -1, cached = 0;
+    int dev = 0;
+    TIP_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev != cached_dev) {
+        int cus = 0, n = 0;
+        TIP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        TIP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fd_pair_rows, kFdPairThreads, 0));
+        cached = std::max(1, cus) * std::max(1, n);
+        cached_dev = dev;
+    }
+    return cached;
+}
 
 int fd_occupancy() {
     int n = 0;
@@ -1386,12 +1726,40 @@ void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t 
     TIP_HIP_TRY(hipGetLastError());
 }
 
+void launch_fd_pairs(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, Ctl* ctl, const SpillArena& spill,
+                     int big_grid, int64_t* scan_tmp, bool on, hipStream_t s) {
+    fb.pairs_on = on && fb.pair_cap > 0 && g.n_a > 0 ? 1 : 0;
+    if (!fb.pairs_on) return;
+    // diagnostic: TIP_FD_PAIR_LIMIT=<entries> uses at most that many
+    // entries of the budget (subsets beyond it walk), for testing the mix
+    fb.pair_lim = fb.pair_cap;
+    if (const char* e = std::getenv("TIP_FD_PAIR_LIMIT")) {
+        const long long v = std::atoll(e);
+        if (v >= 0) fb.pair_lim = std::min<int64_t>(fb.pair_cap, v);
+    }
+    const int32_t n_a = g.n_a;
+    k_fd_pair_cap<<<grid1((int64_t)n_a + 1), kT, 0, s>>>(pb.state, fb.fd_vert, fb.sub_off, fb.fd_w, n_a, fb.prow_off);
+    TIP_HIP_TRY(hipGetLastError());
+    scan_exclusive_i64(fb.prow_off, fb.prow_off, (int64_t)n_a + 1, scan_tmp, s);
+    k_fd_reset_board<<<1, 256, 0, s>>>(fb.board);
+    TIP_HIP_TRY(hipGetLastError());
+    // the heavy list borrows the crossing list (written by the peeling
+    // before it is read)
+    int32_t* heavy = fb.lst[4];
+    k_fd_pair_rows<<<std::max(1, pair_grid()), kFdPairThreads, 0, s>>>(g, fb, pb.state, heavy, ctl);
+    TIP_HIP_TRY(hipGetLastError());
+    k_fd_pair_rows_heavy<<<std::max(1, big_grid), kFdThreads, 0, s>>>(g, fb, pb.state, heavy, ctl, spill);
+    TIP_HIP_TRY(hipGetLastError());
+}
+
 void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl, const Tune& tune,
                const SpillArena& spill, int big_grid, uint64_t* tmp_keys, int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp,
                uint64_t* keys_scratch, int32_t* vals_scratch, hipStream_t s, bool trace) {
     if (g.n_a <= 0) return;
     launch_fd_setup(g, pb, fb, S, tmp_keys, tmp_vals, hist, scan_tmp, keys_scratch, vals_scratch, s,
                     tune.fd_dgm && tune.fd_huc_pct == 0);
+    launch_fd_pairs(g, pb, fb, ctl, spill, big_grid, scan_tmp, !tune.fd_walk && !tune.fd_dgm && tune.fd_huc_pct == 0,
+                    s);
     k_fd_reset_board<<<1, 256, 0, s>>>(fb.board);
     TIP_HIP_TRY(hipGetLastError());
     FdJobs jobs{};

@@ -69,8 +69,9 @@ int resident_workgroups() {
 }
 
 // Allocates every buffer of one decomposition from the arena (or, with a
-// null arena base, only sums the sizes).
-void plan(Arena& ar, int32_t n_a, int32_t n_b, int64_t m, int32_t P, int slots, Work& w) {
+// null arena base, only sums the sizes); `pairs`: pair-row entries of the
+// fine-grained step (fd_pair_entries).
+void plan(Arena& ar, int32_t n_a, int32_t n_b, int64_t m, int32_t P, int slots, int64_t pairs, Work& w) {
     const int32_t S = P + 1;
     const int64_t na = std::max<int32_t>(n_a, 1), nb = std::max<int32_t>(n_b, 1), mm = std::max<int64_t>(m, 1);
     ingest_alloc(ar, n_a, n_b, m, w.ib);
@@ -120,6 +121,13 @@ void plan(Arena& ar, int32_t n_a, int32_t n_b, int64_t m, int32_t P, int slots, 
     w.fb.theta = ar.take<int64_t>(na);
     w.fb.board = ar.take<FdBoard>(1);
     w.fb.task_trace = ar.take<unsigned long long>(4 * kFdTraceTasks);
+    w.fb.pair_cap = pairs;
+    w.fb.pair_lim = 0;
+    w.fb.pairs_on = 0;
+    w.fb.prow_off = pairs > 0 ? ar.take<int64_t>(na + 1) : nullptr;
+    w.fb.prow_n = pairs > 0 ? ar.take<int32_t>(na) : nullptr;
+    w.fb.prow_w = pairs > 0 ? ar.take<int32_t>(pairs) : nullptr;
+    w.fb.prow_b = pairs > 0 ? ar.take<int64_t>(pairs) : nullptr;
     w.ctl = ar.take<Ctl>(1);
     w.total = ar.take<int64_t>(2);
     const int64_t keys = std::max<int64_t>(std::max(na, nb), 1);
@@ -430,10 +438,26 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
                         std::fprintf(stderr, "tip-fd-task task=%d n=%llu levels=%llu start_us=%.1f end_us=%.1f\n", t,
                                      h[4 * t], h[4 * t + 1], (double)(h[4 * t + 2] - t0) / 100.0,
                                      (double)(h[4 * t + 3] - t0) / 100.0);
+                if (w.fb.pairs_on) {
+                    int64_t cap_total = 0;
+                    unsigned long long entries = 0;
+                    TIP_HIP_TRY(hipMemcpyAsync(&cap_total, w.fb.prow_off + n_a, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+                    TIP_HIP_TRY(hipMemcpyAsync(&entries, &w.ctl->fd_pair_entries, sizeof(entries),
+                                               hipMemcpyDeviceToHost, s));
+                    unsigned long long n_heavy = 0;
+                    TIP_HIP_TRY(hipMemcpyAsync(&n_heavy, &w.ctl->fd_pair_heavy, sizeof(n_heavy),
+                                               hipMemcpyDeviceToHost, s));
+                    TIP_HIP_TRY(hipStreamSynchronize(s));
+                    std::fprintf(stderr, "tip-fd-pairs capacity=%lld budget=%lld entries=%llu heavy=%llu\n",
+                                 (long long)cap_total, (long long)w.fb.pair_lim, entries, n_heavy);
+                }
             }
         } else {
             launch_fd_setup(g, pb, w.fb, S, w.ib.keys2, w.ib.vals2, w.ib.hist, w.ib.scan_tmp, w.ib.keys, w.ib.vals, s,
                             tune.fd_dgm && tune.fd_huc_pct == 0);
+            if (S > 0)
+                launch_fd_pairs(g, pb, w.fb, w.ctl, w.spill, big_grid, w.ib.scan_tmp,
+                                !tune.fd_walk && !tune.fd_dgm && tune.fd_huc_pct == 0, s);
         }
     }
     return TIP_OK;
@@ -471,6 +495,8 @@ void run_back(Work& w, int32_t n_a, int32_t n_b, bool decompose, RunOut& out, Ru
         st->huc_rounds = (int64_t)cf.huc_rounds;
         st->fd_huc_steps = (int64_t)cf.fd_huc_steps;
         st->compactions = rs.cd_compactions + (int64_t)(cf.fd_compactions << 32);
+        st->fd_pair_entries = (int64_t)cf.fd_pair_entries;
+        st->fd_pair_subsets = (int64_t)cf.fd_pair_tasks;
         st->subsets = S;
         st->fd_levels = (int64_t)cf.fd_levels;
         st->spills = (int64_t)(cf.spills + spread_sum(cf, kScSpills));
@@ -535,7 +561,7 @@ void check_edges(const tip_edges* g) {
 
 constexpr int32_t kKnownFlags = TIP_FLAG_TIME_KERNELS | TIP_FLAG_NO_GRAPH | TIP_FLAG_BATCH_PLAIN | TIP_FLAG_NO_COMPACT |
                                 TIP_FLAG_OPTS_PER_GRAPH | TIP_FLAG_BATCH_STREAMS | TIP_FLAG_FD_DGM |
-                                TIP_FLAG_DGM_PAPER;
+                                TIP_FLAG_DGM_PAPER | TIP_FLAG_FD_WALK;
 
 int32_t check_opts(const tip_opts* opt, bool batch = false) {
     if (!opt) return kDefaultP;
@@ -562,6 +588,7 @@ Tune tune_of(const tip_opts* opt) {
     if (opt && (opt->flags & TIP_FLAG_NO_COMPACT)) t.compact_permille = 0;
     if (opt) t.fd_dgm = (opt->flags & TIP_FLAG_FD_DGM) != 0;
     if (opt) t.dgm_paper = (opt->flags & TIP_FLAG_DGM_PAPER) != 0;
+    if (opt) t.fd_walk = (opt->flags & TIP_FLAG_FD_WALK) != 0;
     return t;
 }
 
@@ -600,13 +627,13 @@ tip_status decompose_host(const tip_edges* g, int32_t side, int64_t* theta, int3
     Work w;
     const int slots = resident_workgroups();
     Arena sizer;
-    plan(sizer, n_a, n_b, m, P, slots, w);
+    plan(sizer, n_a, n_b, m, P, slots, fd_pair_entries(m, tune), w);
     const size_t extra = sizeof(int32_t) * (2 * (size_t)std::max<int64_t>(m, 1)) +
                          (sizeof(int64_t) * 2 + sizeof(int32_t)) * (size_t)std::max<int32_t>(n_a, 1) + 4096;
     DeviceBuffer buf;
     buf.alloc(sizer.off + extra);
     Arena ar{static_cast<char*>(buf.p), sizer.off + extra, 0};
-    plan(ar, n_a, n_b, m, P, slots, w);
+    plan(ar, n_a, n_b, m, P, slots, fd_pair_entries(m, tune), w);
     int32_t* d_a = ar.take<int32_t>(std::max<int64_t>(m, 1));
     int32_t* d_b = ar.take<int32_t>(std::max<int64_t>(m, 1));
     int64_t* d_theta = ar.take<int64_t>(std::max<int32_t>(n_a, 1));
@@ -702,12 +729,12 @@ tip_status decompose_batched(int32_t n, const tip_edges* gs, const int32_t* side
                 b.n_b = b.a_is_u ? g->n_v : g->n_u;
                 b.m = g->m;
                 Arena sizer;
-                plan(sizer, b.n_a, b.n_b, b.m, P, slots, b.w);
+                plan(sizer, b.n_a, b.n_b, b.m, P, slots, fd_pair_entries(b.m, b.tune), b.w);
                 const size_t extra = sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(b.m, 1) +
                                      sizeof(int64_t) * (size_t)std::max<int32_t>(b.n_a, 1) + 4096;
                 b.buf.alloc(sizer.off + extra);
                 Arena ar{static_cast<char*>(b.buf.p), sizer.off + extra, 0};
-                plan(ar, b.n_a, b.n_b, b.m, P, slots, b.w);
+                plan(ar, b.n_a, b.n_b, b.m, P, slots, fd_pair_entries(b.m, b.tune), b.w);
                 int32_t* d_a = ar.take<int32_t>(std::max<int64_t>(b.m, 1));
                 int32_t* d_b = ar.take<int32_t>(std::max<int64_t>(b.m, 1));
                 b.d_theta = ar.take<int64_t>(std::max<int32_t>(b.n_a, 1));
@@ -847,13 +874,13 @@ bool decompose_union(int32_t n, const tip_edges* gs, const int32_t* sides, int64
     Work w;
     const int slots = resident_workgroups();
     Arena sizer;
-    plan(sizer, n_a, n_b, m, P, slots, w);
+    plan(sizer, n_a, n_b, m, P, slots, fd_pair_entries(m, tune), w);
     const size_t extra = sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(m, 1) +
                          sizeof(int64_t) * (size_t)std::max<int32_t>(n_a, 1) + 4096;
     DeviceBuffer buf;
     buf.alloc(sizer.off + extra);
     Arena ar{static_cast<char*>(buf.p), sizer.off + extra, 0};
-    plan(ar, n_a, n_b, m, P, slots, w);
+    plan(ar, n_a, n_b, m, P, slots, fd_pair_entries(m, tune), w);
     int32_t* d_a = ar.take<int32_t>(std::max<int64_t>(m, 1));
     int32_t* d_b = ar.take<int32_t>(std::max<int64_t>(m, 1));
     int64_t* d_theta = ar.take<int64_t>(std::max<int32_t>(n_a, 1));
@@ -943,13 +970,13 @@ tip_status tip_count_butterflies(const tip_edges* g, int64_t* bfly_u, int64_t* b
         Work w;
         const int slots = resident_workgroups();
         Arena sizer;
-        plan(sizer, n_a, n_b, m, 1, slots, w);
+        plan(sizer, n_a, n_b, m, 1, slots, 0, w);
         const size_t extra = sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(m, 1) +
                              sizeof(int64_t) * ((size_t)std::max(n_a, 1) + std::max(n_b, 1)) + 4096;
         DeviceBuffer buf;
         buf.alloc(sizer.off + extra);
         Arena ar{static_cast<char*>(buf.p), sizer.off + extra, 0};
-        plan(ar, n_a, n_b, m, 1, slots, w);
+        plan(ar, n_a, n_b, m, 1, slots, 0, w);
         int32_t* d_a = ar.take<int32_t>(std::max<int64_t>(m, 1));
         int32_t* d_b = ar.take<int32_t>(std::max<int64_t>(m, 1));
         int64_t* d_bu = ar.take<int64_t>(std::max(n_a, 1));
@@ -1053,12 +1080,12 @@ tip_status tip_decompose_noalloc(const int32_t* d_eu, const int32_t* d_ev, int32
         w.no_alloc = true;
         Arena sizer;
         const int slots = resident_workgroups();
-        plan(sizer, n_a, n_b, m, P, slots, w);
+        plan(sizer, n_a, n_b, m, P, slots, 0, w);
         if (sizer.off > kNoAllocScratchBytes)
             throw AllocFailure("graph needs " + std::to_string(sizer.off) + " bytes of scratch; tip_decompose_noalloc "
                                "holds " + std::to_string(kNoAllocScratchBytes) + " (use tip_decompose_async)");
         Arena ar{static_cast<char*>(noalloc_scratch()), kNoAllocScratchBytes, 0};
-        plan(ar, n_a, n_b, m, P, slots, w);
+        plan(ar, n_a, n_b, m, P, slots, 0, w);
         const hipStream_t s = static_cast<hipStream_t>(stream);
         // the scratch keeps the previous call's contents: the repeat-count
         // spill area must start at zero (everything else is written before
@@ -1173,7 +1200,7 @@ tip_status tip_workspace_size(int32_t n_u, int32_t n_v, int64_t m, int32_t side,
         const int32_t n_a = side == TIP_SIDE_U ? n_u : n_v, n_b = side == TIP_SIDE_U ? n_v : n_u;
         Work w;
         Arena sizer;
-        plan(sizer, n_a, n_b, m, P, resident_workgroups(), w);
+        plan(sizer, n_a, n_b, m, P, resident_workgroups(), fd_pair_entries(m, tune_of(opt)), w);
         *bytes = sizer.off + 256;
         return TIP_OK;
     });
@@ -1194,10 +1221,10 @@ tip_status tip_decompose_async(const int32_t* d_eu, const int32_t* d_ev, int32_t
         Work w;
         Arena sizer;
         const int slots = resident_workgroups();
-        plan(sizer, n_a, n_b, m, P, slots, w);
+        plan(sizer, n_a, n_b, m, P, slots, fd_pair_entries(m, tune_of(opt)), w);
         if (ws_bytes < sizer.off) throw AllocFailure("workspace smaller than tip_workspace_size");
         Arena ar{static_cast<char*>(d_workspace), ws_bytes, 0};
-        plan(ar, n_a, n_b, m, P, slots, w);
+        plan(ar, n_a, n_b, m, P, slots, fd_pair_entries(m, tune_of(opt)), w);
         const hipStream_t s = static_cast<hipStream_t>(stream);
         TIP_HIP_TRY(hipMemsetAsync(w.spill.dense, 0, sizeof(int32_t) * w.spill.stride * w.spill.slots, s));
         RunOut out;

@@ -98,6 +98,8 @@ constexpr int kFdHelpLevelMin = 256;      // levels with fewer per-wave updates 
 constexpr int kFdPassUnroll = 8;          // live-list entries per thread in flight in a level's passes
 constexpr int kFdHelpHeavyMin = 2;        // levels with this many heavy updates of a large subset publish them,
 constexpr int64_t kFdHelpHeavyWedges = 1 << 18;  // ... when they hold at least this many induced wedges
+constexpr int64_t kFdPairsPerEdge = 16;   // pair-row entries a workspace holds per edge
+constexpr int kFdPairChunk = 64;          // vertex positions the pair-row build takes at once
 constexpr int kFdCascadeMax = 64;         // a step peeling at most this many vertices tracks the ones it drops to the level
 
 constexpr int32_t kLive = -1;              // subset id of a vertex not yet assigned

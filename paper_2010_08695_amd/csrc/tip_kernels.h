@@ -63,6 +63,9 @@ struct Ctl {
     unsigned long long huc_rounds;  // rounds that re-counted
     unsigned long long fd_huc_steps;  // fine-grained steps that re-counted
     unsigned long long cd_compactions, fd_compactions;
+    unsigned long long fd_pair_entries;  // entries written to the fine-grained pair rows
+    unsigned long long fd_pair_tasks;    // subsets peeled from pair rows
+    unsigned long long fd_pair_heavy;    // rows built by the workgroup-per-vertex kernel
 };
 
 __device__ inline void spread_add(Ctl* ctl, int c, unsigned long long v) {
@@ -132,6 +135,9 @@ struct FdHelpSlot {
 constexpr int kFdHelpSlots = 64;
 struct FdBoard {
     int32_t head;     // task queue head
+    int32_t pair_head;  // next vertex position of the pair-row build
+    int32_t pair_heavy; // vertices on the pair-row build's heavy list
+    int32_t pair_head2; // next entry of that list
     int32_t n_slots;  // slots handed out
     FdHelpSlot slot[kFdHelpSlots];
 };
@@ -159,6 +165,17 @@ struct FdBuffers {
     int64_t* theta;      // [n_a] by rank
     FdBoard* board;      // task queue and help board of the launch
     unsigned long long* task_trace;  // [4 * kFdTraceTasks] per-task timing (diagnostic)
+    // Pair rows: row p (the vertex at subset position p) holds every w of
+    // its subset with c(u, w) >= 2, as w's index inside the subset and
+    // C(c, 2).  A subset has rows iff pairs_on and its rows end within
+    // pair_cap entries.
+    int64_t* prow_off;   // [n_a + 1] row starts: exclusive scan of the row capacities
+    int32_t* prow_n;     // [n_a] entries of each row
+    int32_t* prow_w;     // [pair_cap]
+    int64_t* prow_b;     // [pair_cap]
+    int64_t pair_cap;    // entries allocated
+    int64_t pair_lim;    // entries this run may use (<= pair_cap)
+    int32_t pairs_on;    // set per run
 };
 
 // Update-kernel selection thresholds (tip_opts.tune[0], tune[1]).
@@ -174,7 +191,15 @@ struct Tune {
     int32_t fd_huc_pct = 0;  // tip_opts.tune[7]
     bool fd_dgm = false;     // TIP_FLAG_FD_DGM
     bool dgm_paper = false;  // TIP_FLAG_DGM_PAPER
+    bool fd_walk = false;    // TIP_FLAG_FD_WALK
 };
+
+// Pair-row entries a workspace holds for a graph of m edges (0: every
+// fine-grained update walks its wedges).
+inline int64_t fd_pair_entries(int64_t m, const Tune& t) {
+    if (t.fd_walk || t.fd_dgm || t.fd_huc_pct > 0) return 0;
+    return kFdPairsPerEdge * std::max<int64_t>(m, 1);
+}
 
 // counting
 void launch_count(const DevGraph& g, CountBuffers& cb, Ctl* ctl, const SpillArena& spill, int big_grid,
@@ -241,6 +266,10 @@ struct FdJobs {
 void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, uint64_t* tmp_keys,
                      int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp, uint64_t* keys_scratch,
                      int32_t* vals_scratch, hipStream_t s, bool runs);
+// Pair rows of every subset that fits fb.pair_cap (after launch_fd_setup);
+// off (fb.pairs_on = 0) when `on` is false.
+void launch_fd_pairs(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, Ctl* ctl, const SpillArena& spill,
+                     int big_grid, int64_t* scan_tmp, bool on, hipStream_t s);
 // Persistent peeling of the subsets of many graphs in one launch: tasks[t] =
 // job << 32 | subset, in the order they are to be taken; *head is the queue
 // head (reset here).

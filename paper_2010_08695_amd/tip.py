@@ -27,6 +27,7 @@ TIP_FLAG_OPTS_PER_GRAPH = 16
 TIP_FLAG_BATCH_STREAMS = 32
 TIP_FLAG_FD_DGM = 64
 TIP_FLAG_DGM_PAPER = 128
+TIP_FLAG_FD_WALK = 256
 SIDE_U, SIDE_V = 0, 1
 STATUS_NAMES = {0: "TIP_OK", -1: "TIP_EINVAL", -2: "TIP_ENOMEM", -3: "TIP_EDEVICE",
                 -4: "TIP_EOVERFLOW", -5: "TIP_EBUSY"}
@@ -60,7 +61,8 @@ class Stats(ctypes.Structure):
                  "peel_launches", "peel_wedges", "peel_edges", "peel_pairs")] + \
                [(n, ctypes.c_double) for n in
                 ("peel_ms", "t_ingest_ms", "t_count_ms", "t_cd_ms", "t_fd_ms", "t_total_ms")] + \
-               [("huc_rounds", ctypes.c_int64), ("fd_huc_steps", ctypes.c_int64), ("compactions", ctypes.c_int64)]
+               [("huc_rounds", ctypes.c_int64), ("fd_huc_steps", ctypes.c_int64), ("compactions", ctypes.c_int64),
+                ("fd_pair_entries", ctypes.c_int64), ("fd_pair_subsets", ctypes.c_int64)]
 
     def to_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -44,7 +44,7 @@ def test_missing_library_fails_loudly(tmp_path):
 def test_struct_sizes():
     assert ctypes.sizeof(tip.Edges) == 4 + 4 + 8 + 8 + 8
     assert ctypes.sizeof(tip.Opts) == 4 * 10
-    assert ctypes.sizeof(tip.Stats) == 14 * 8 + 6 * 8 + 3 * 8
+    assert ctypes.sizeof(tip.Stats) == 14 * 8 + 6 * 8 + 5 * 8
 
 
 def _edges(n_u, n_v, eu, ev, m=None):
@@ -91,7 +91,7 @@ def test_decompose_rejects_bad_arguments(lib):
     o.P = 70000
     _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
     o = tip.Opts()
-    o.flags = 256                                 # no such flag
+    o.flags = 512                                 # no such flag
     _expect_einval(lib, lib.tip_decompose(ctypes.byref(e), 0, tp, ctypes.byref(o), None))
     o = tip.Opts()
     o.tune[1] = -1

@@ -467,6 +467,45 @@ def test_fd_dgm_changes_nothing_but_work(gpu_lib):
     np.testing.assert_array_equal(got["theta"], th)
 
 
+def test_fd_pair_rows_change_nothing(gpu_lib, monkeypatch):
+    """The fine-grained step's pair rows (each vertex's update inside its
+    subset, listed before peeling; the default) against walking every
+    update's wedges (TIP_FLAG_FD_WALK, Alg. 4 as written): the same subsets,
+    initial supports, bounds, tip numbers, levels and support decrements,
+    with subsets kept in LDS and in HBM.  With the rows' budget cut
+    (TIP_FD_PAIR_LIMIT) some subsets read rows and the others walk, and the
+    results stay the same."""
+    g = gg.chung_lu(20000, 3000, 150000, 2.2, 2.0, seed=47)
+    th = oracle.bup(g, 0)[0]
+    keys = ("subset", "init", "bounds")
+    for P in (1, 3, 40):
+        ref = tip.decompose_ex(g, 0, P=P, flags=tip.TIP_FLAG_FD_WALK)
+        got = tip.decompose_ex(g, 0, P=P)
+        assert ref["stats"]["fd_pair_subsets"] == 0 and ref["stats"]["fd_pair_entries"] == 0
+        np.testing.assert_array_equal(ref["theta"], th)
+        np.testing.assert_array_equal(got["theta"], th)
+        for k in keys:
+            np.testing.assert_array_equal(got[k], ref[k])
+        assert got["stats"]["fd_levels"] == ref["stats"]["fd_levels"], P
+        assert got["stats"]["pair_updates"] == ref["stats"]["pair_updates"], P
+    assert got["stats"]["fd_pair_subsets"] > 0 and got["stats"]["fd_pair_entries"] > 0
+    mixed = False
+    for lim in (1 << 12, 1 << 14, 1 << 16, 1 << 18):
+        monkeypatch.setenv("TIP_FD_PAIR_LIMIT", str(lim))
+        cut = tip.decompose_ex(g, 0, P=40)
+        k = cut["stats"]["fd_pair_subsets"]
+        mixed = mixed or 0 < k < cut["stats"]["subsets"]
+        np.testing.assert_array_equal(cut["theta"], th)
+        assert cut["stats"]["pair_updates"] == got["stats"]["pair_updates"]
+    assert mixed
+    # side V, and the graph-replayed path with the rows on
+    th_v = oracle.bup(g, 1)[0]
+    monkeypatch.delenv("TIP_FD_PAIR_LIMIT")
+    out, st = tip.decompose(g, 1, P=20, with_stats=True)
+    assert st["fd_pair_subsets"] > 0
+    np.testing.assert_array_equal(out, th_v)
+
+
 def test_cd_dgm_paper_trigger_changes_nothing(gpu_lib):
     """Section 4.2's own trigger for the coarse-grained lists
     (TIP_FLAG_DGM_PAPER: compact once the wedges walked since the last
