@@ -250,7 +250,9 @@ tip_status tip_decompose_async(const int32_t* d_eu, const int32_t* d_ev, int32_t
 
 /* For callers that cannot allocate device memory (serving loops and
  * harnesses that forbid hipMalloc): tip_decompose_async without a workspace
- * argument.  The library's scratch is a static device array of 512 MiB per
+ * argument.  The scratch holds no pair rows, so the fine-grained step walks
+ * every update's wedges (as with TIP_FLAG_FD_WALK; same results).  The
+ * library's scratch is a static device array of 512 MiB per
  * device, created when the library's device code is loaded and held until
  * the process ends; the call itself allocates nothing (no device, pinned or
  * library memory, no HIP graph, no events).
@@ -261,8 +263,8 @@ tip_status tip_decompose_async(const int32_t* d_eu, const int32_t* d_ev, int32_t
  *               between rounds, so the call cannot be captured in a graph)
  *   opt, st     as for tip_decompose_async; TIP_FLAG_TIME_KERNELS is
  *               rejected and the t_*_ms times of st read 0
- * Graphs whose tip_workspace_size exceeds 512 MiB are refused with
- * TIP_ENOMEM before any device work.  Every call on one device shares that
+ * Graphs whose tip_workspace_size with TIP_FLAG_FD_WALK exceeds 512 MiB are
+ * refused with TIP_ENOMEM before any device work.  Every call on one device shares that
  * device's scratch and leaves its contents behind: calls that overlap on one
  * device (from several host threads or streams) race and must be
  * serialised by the caller. */

@@ -208,6 +208,7 @@ struct FdLds {
     int32_t spill_n;
     int32_t flag;
     int32_t wave_head;   // next per-wave update of the level
+    int32_t hn;          // entries of a claimed help-board chunk of pair rows
     int32_t lcnt[4];     // list lengths of a level's partition: kept, per-wave, heavy
     unsigned long long hw;  // induced wedges of a level's heavy vertices
     unsigned long long pw_all, pw_upd;  // induced wedges of a step's peeled vertices (all; with support left)
@@ -764,6 +765,44 @@ __device__ inline void fd_help_slot(const DevGraph& g, const FdBuffers& fb, FdLd
     }
 }
 
+// Pair-row updates taken from a help-board slot, kFdPairHelpChunk peeled
+// vertices at a time by the whole workgroup, until the published list is
+// exhausted; finished entries are counted in `done` after their decrements
+// are visible device-wide.  All threads call.
+template <class St>
+__device__ inline void fd_help_pairs(const FdBuffers& fb, FdLds& L, const int32_t* pl, int64_t P0, FdHelpSlot* hs,
+                                     const St& st, unsigned long long& pairs) {
+    static_assert(kFdPairHelpChunk <= kFdHeavyPre, "a chunk's rows are staged in hx_off / hx_deg");
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long wv = atomicAdd(&hs->word, (unsigned long long)kFdPairHelpChunk);
+            const uint32_t q0 = (uint32_t)wv, n = (uint32_t)(wv >> 32);
+            L.flag = q0 < n ? (int32_t)q0 : -1;
+            L.hn = q0 < n ? (int32_t)min<uint32_t>(kFdPairHelpChunk, n - q0) : 0;
+        }
+        __syncthreads();
+        const int32_t q0 = L.flag, nq = L.hn;
+        if (q0 < 0) break;
+        __threadfence();
+        for (int32_t q = threadIdx.x; q < nq; q += kFdThreads) {
+            const int32_t x = pl[q0 + q];
+            L.hx_off[q] = fb.prow_off[P0 + x];
+            L.hx_deg[q] = fb.prow_n[P0 + x];
+        }
+        __syncthreads();
+        const auto row = [&](int32_t q, int64_t& off, int32_t& len) {
+            off = L.hx_off[q];
+            len = L.hx_deg[q];
+        };
+        fd_pair_units(fb, nq, row, st, pairs);
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(&hs->done, nq);
+    }
+    __syncthreads();
+}
+
 // Which update a peeled vertex j of the subset takes.  In subsets of at most
 // kFdWaveKeys vertices every vertex of degree <= 255 with at most
 // kFdWaveDenseMax wedges inside the subset is updated by one wavefront with
@@ -1076,7 +1115,14 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
                 continue;
             }
         }
-        const bool publish = !pr && hs && n_light >= help_level_min;
+        bool publish = hs && n_light >= (pr ? kFdPairHelpMin : help_level_min);
+        if (publish && pr) {
+            // a pair step is shared only when its rows hold enough entries
+            // to outweigh the board's fences
+            int64_t e = 0;
+            for (int32_t q = tid; q < n_light; q += NT) e += fb.prow_n[P0 + pl[q]];
+            publish = fd_block_sum<NT>(L, e) >= kFdPairHelpEntries;
+        }
         // heavy updates are shared only when there are several and enough
         // wedges to outweigh the board's fences
         const bool publish_heavy =
@@ -1099,7 +1145,8 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
                 atomicExch(&hs->word, (unsigned long long)n_light << 32);
             }
             __syncthreads();
-            fd_help_slot(g, fb, L, tab, wcnt, pl, fw, n_i, hs, help_chunk, st, wedges, pairs);
+            if (pr) fd_help_pairs(fb, L, pl, P0, hs, st, pairs);
+            else fd_help_slot(g, fb, L, tab, wcnt, pl, fw, n_i, hs, help_chunk, st, wedges, pairs);
             __syncthreads();
             if (tid == 0)
                 while (__hip_atomic_load(&hs->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n_light)
@@ -1339,7 +1386,7 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
         } else {
             // a large subset opens a help-board slot for its per-wave updates
             FdHelpSlot* hs = nullptr;
-            if (!pr && n_i >= J.help_min) {
+            if (n_i >= J.help_min) {
                 if (tid == 0) {
                     const int32_t k = atomicAdd(&board->n_slots, 1);
                     L.flag = k;
@@ -1352,6 +1399,7 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
                         h.done = 0;
                         h.hword = 0;
                         h.hdone = 0;
+                        h.pairs = pr ? 1 : 0;
                         __threadfence();
                         atomicExch(&h.state, 1);
                     }
@@ -1441,8 +1489,9 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
             const FdHbmState st{fb.supp_fd + P0, fb.alive + P0, fb.fd_vert + P0};
             uint32_t* wcnt = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(&L.u) + (size_t)wid * kFdWaveKeys);
             unsigned long long wedges = 0, pairs = 0;
-            fd_help_slot(J.g, fb, L, tab, wcnt, fb.lst[2] + P0, fb.fd_w + P0, hs->n_i, hs, J.help_chunk, st, wedges,
-                         pairs);
+            if (hs->pairs) fd_help_pairs(fb, L, fb.lst[2] + P0, P0, hs, st, pairs);
+            else fd_help_slot(J.g, fb, L, tab, wcnt, fb.lst[2] + P0, fb.fd_w + P0, hs->n_i, hs, J.help_chunk, st,
+                              wedges, pairs);
             wedges = (unsigned long long)wave_sum_i64((int64_t)wedges);
             pairs = (unsigned long long)wave_sum_i64((int64_t)pairs);
             if (lane == 0) {

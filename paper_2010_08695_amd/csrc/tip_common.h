@@ -99,7 +99,9 @@ constexpr int kFdPassUnroll = 8;          // live-list entries per thread in fli
 constexpr int kFdHelpHeavyMin = 2;        // levels with this many heavy updates of a large subset publish them,
 constexpr int64_t kFdHelpHeavyWedges = 1 << 18;  // ... when they hold at least this many induced wedges
 constexpr int64_t kFdPairsPerEdge = 16;   // pair-row entries a workspace holds per edge
-constexpr int kFdPairChunk = 64;          // vertex positions the pair-row build takes at once
+constexpr int kFdPairHelpMin = 512;       // pair-row steps with this many peeled vertices ...
+constexpr int64_t kFdPairHelpEntries = 1 << 16;  // ... and this many row entries go on the help board
+constexpr int kFdPairHelpChunk = 256;     // peeled vertices (rows) a workgroup takes at once from the board
 constexpr int kFdCascadeMax = 64;         // a step peeling at most this many vertices tracks the ones it drops to the level
 
 constexpr int32_t kLive = -1;              // subset id of a vertex not yet assigned

@@ -128,6 +128,7 @@ struct FdHelpSlot {
     int32_t hdone;            // heavy entries of the published level finished
     unsigned long long hword; // heavy updates: (published << 32) | next to take
     int32_t state;            // 0 unused, 1 open, 2 closed
+    int32_t pairs;            // published entries are pair rows, taken kFdPairHelpChunk at a time
     int32_t job;              // index in the job list, -1 for the single job
     int32_t n_i;              // subset size
     int64_t P0;               // subset start (position)

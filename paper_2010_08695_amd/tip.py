@@ -236,10 +236,10 @@ def decompose_batch(graphs, sides=None, P: int = 0, with_stats: bool = False, fl
     return thetas
 
 
-def workspace_size(n_u: int, n_v: int, m: int, side: int = SIDE_U, P: int = 0) -> int:
+def workspace_size(n_u: int, n_v: int, m: int, side: int = SIDE_U, P: int = 0, flags: int = 0) -> int:
     lib = load()
     out = ctypes.c_size_t(0)
-    o = _opts(P)
+    o = _opts(P, flags)
     _check(lib, lib.tip_workspace_size(int(n_u), int(n_v), int(m), int(side), ctypes.byref(o), ctypes.byref(out)))
     return int(out.value)
 
@@ -274,9 +274,10 @@ NOALLOC_SCRATCH_BYTES = 512 << 20
 
 def decompose_noalloc(d_eu, d_ev, n_u: int, n_v: int, side: int, d_theta, stream=None, P: int = 0,
                       flags: int = 0, tune=None) -> dict:
-    """tip_decompose_noalloc: like decompose_async, with the library's static
-    device scratch instead of a workspace (graphs whose workspace exceeds
-    NOALLOC_SCRATCH_BYTES are refused with TIP_ENOMEM).  Returns the stats."""
+    """tip_decompose_noalloc: like decompose_async with TIP_FLAG_FD_WALK, with
+    the library's static device scratch instead of a workspace (graphs whose
+    workspace_size(..., flags=TIP_FLAG_FD_WALK) exceeds NOALLOC_SCRATCH_BYTES
+    are refused with TIP_ENOMEM).  Returns the stats."""
     lib = load()
     m = int(d_eu.numel())
     if int(d_ev.numel()) != m:
