@@ -770,8 +770,8 @@ __device__ inline void fd_help_slot(const DevGraph& g, const FdBuffers& fb, FdLd
 // exhausted; finished entries are counted in `done` after their decrements
 // are visible device-wide.  All threads call.
 template <class St>
-__device__ inline void fd_help_pairs(const FdBuffers& fb, FdLds& L, const int32_t* pl, int64_t P0, FdHelpSlot* hs,
-                                     const St& st, unsigned long long& pairs) {
+__device__ inline void fd_help_pairs(const FdBuffers& fb, FdLds& L, const int32_t* pl, int64_t P0, int64_t shift,
+                                     FdHelpSlot* hs, const St& st, unsigned long long& pairs) {
     static_assert(kFdPairHelpChunk <= kFdHeavyPre, "a chunk's rows are staged in hx_off / hx_deg");
     for (;;) {
         __syncthreads();
@@ -787,7 +787,7 @@ __device__ inline void fd_help_pairs(const FdBuffers& fb, FdLds& L, const int32_
         __threadfence();
         for (int32_t q = threadIdx.x; q < nq; q += kFdThreads) {
             const int32_t x = pl[q0 + q];
-            L.hx_off[q] = fb.prow_off[P0 + x];
+            L.hx_off[q] = fb.prow_off[P0 + x] + shift;
             L.hx_deg[q] = fb.prow_n[P0 + x];
         }
         __syncthreads();
@@ -952,7 +952,8 @@ __device__ inline void fd_compact_runs(const DevGraph& g, const FdBuffers& fb, F
 __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const int64_t* __restrict__ init,
                                    int64_t P0, int32_t n_i, FdLds& L, unsigned long long* tab, const Spill& sp,
                                    FdHelpSlot* hs, int32_t help_chunk, int32_t help_level_min, int32_t huc_pct,
-                                   int32_t sub, int32_t dgm, bool pr, unsigned long long& wedges, unsigned long long& pairs,
+                                   int32_t sub, int32_t dgm, bool pr, int64_t shift, unsigned long long& wedges,
+                                   unsigned long long& pairs,
                                    unsigned long long& levels, unsigned long long& spills,
                                    unsigned long long& huc_steps, unsigned long long& compactions) {
     constexpr int NT = kFdThreads;
@@ -1145,7 +1146,7 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
                 atomicExch(&hs->word, (unsigned long long)n_light << 32);
             }
             __syncthreads();
-            if (pr) fd_help_pairs(fb, L, pl, P0, hs, st, pairs);
+            if (pr) fd_help_pairs(fb, L, pl, P0, shift, hs, st, pairs);
             else fd_help_slot(g, fb, L, tab, wcnt, pl, fw, n_i, hs, help_chunk, st, wedges, pairs);
             __syncthreads();
             if (tid == 0)
@@ -1161,7 +1162,7 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
                 const int32_t nq = min(kFdHeavyPre, n_light - c0);
                 for (int32_t q = tid; q < nq; q += NT) {
                     const int32_t x = pl[c0 + q];
-                    L.hx_off[q] = fb.prow_off[P0 + x];
+                    L.hx_off[q] = fb.prow_off[P0 + x] + shift;
                     L.hx_deg[q] = fb.prow_n[P0 + x];
                 }
                 __syncthreads();
@@ -1226,7 +1227,8 @@ __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const
 // do not use, and cleared at the end.
 __device__ inline void fd_peel_lds(const DevGraph& g, const FdBuffers& fb, const int64_t* __restrict__ init,
                                    int64_t P0, int32_t n_i, FdLds& L, FdSmall& S, unsigned long long* tab,
-                                   const Spill& sp, bool pr, unsigned long long& wedges, unsigned long long& pairs,
+                                   const Spill& sp, bool pr, int64_t shift, unsigned long long& wedges,
+                                   unsigned long long& pairs,
                                    unsigned long long& levels, unsigned long long& spills) {
     constexpr int NT = kFdThreads;
     constexpr int NW = NT / kWave;
@@ -1237,7 +1239,7 @@ __device__ inline void fd_peel_lds(const DevGraph& g, const FdBuffers& fb, const
     static_assert(sizeof(FdLds::Shared) >= (size_t)kFdLdsVerts * 6, "pair-row starts and lengths fit the union");
     int32_t* roff = reinterpret_cast<int32_t*>(&L.u);
     uint16_t* rn = reinterpret_cast<uint16_t*>(roff + kFdLdsVerts);
-    const int64_t rbase = pr ? fb.prow_off[P0] : 0;
+    const int64_t rb0 = pr ? fb.prow_off[P0] : 0, rbase = rb0 + (pr ? shift : 0);
     int64_t mn = INT64_MAX;
     for (int32_t j = tid; j < n_i; j += NT) {
         const int32_t v = fb.fd_vert[P0 + j];
@@ -1248,7 +1250,7 @@ __device__ inline void fd_peel_lds(const DevGraph& g, const FdBuffers& fb, const
         S.lc[j] = (uint16_t)j;
         mn = s0 < mn ? s0 : mn;
         if (pr) {
-            roff[j] = (int32_t)(fb.prow_off[P0 + j] - rbase);
+            roff[j] = (int32_t)(fb.prow_off[P0 + j] - rb0);
             rn[j] = (uint16_t)fb.prow_n[P0 + j];
         }
     }
@@ -1379,10 +1381,11 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
         unsigned long long wedges = 0, pairs = 0, levels = 0, spills = 0, huc_steps = 0, compactions = 0;
         const unsigned long long t_start = jobs.trace ? wall_clock64() : 0ull;
         // pair rows, when this subset's were built
-        const bool pr = fb.pairs_on && fb.prow_off[P0 + n_i] <= fb.pair_lim;
+        const int64_t shift = fb.pairs_on ? fb.pshift[sub] : kNoRows;
+        const bool pr = shift != kNoRows;
         if (pr && tid == 0) atomicAdd(&J.ctl->fd_pair_tasks, 1ull);
         if (n_i <= kFdLdsVerts) {
-            fd_peel_lds(J.g, fb, J.init, P0, n_i, L, S, tab, sp, pr, wedges, pairs, levels, spills);
+            fd_peel_lds(J.g, fb, J.init, P0, n_i, L, S, tab, sp, pr, shift, wedges, pairs, levels, spills);
         } else {
             // a large subset opens a help-board slot for its per-wave updates
             FdHelpSlot* hs = nullptr;
@@ -1400,6 +1403,7 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
                         h.hword = 0;
                         h.hdone = 0;
                         h.pairs = pr ? 1 : 0;
+                        h.pshift = shift;
                         __threadfence();
                         atomicExch(&h.state, 1);
                     }
@@ -1409,7 +1413,7 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
                 __syncthreads();
             }
             fd_peel_hbm(J.g, fb, J.init, P0, n_i, L, tab, sp, hs, J.help_chunk, J.help_level_min,
-                        pr ? 0 : J.huc_pct, sub, pr ? 0 : J.dgm, pr, wedges, pairs, levels, spills, huc_steps,
+                        pr ? 0 : J.huc_pct, sub, pr ? 0 : J.dgm, pr, shift, wedges, pairs, levels, spills, huc_steps,
                         compactions);
             if (hs && tid == 0) atomicExch(&hs->state, 2);
         }
@@ -1489,7 +1493,7 @@ k_fd_peel(FdJobs jobs, const int64_t* __restrict__ tasks, int32_t n_tasks, FdBoa
             const FdHbmState st{fb.supp_fd + P0, fb.alive + P0, fb.fd_vert + P0};
             uint32_t* wcnt = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(&L.u) + (size_t)wid * kFdWaveKeys);
             unsigned long long wedges = 0, pairs = 0;
-            if (hs->pairs) fd_help_pairs(fb, L, fb.lst[2] + P0, P0, hs, st, pairs);
+            if (hs->pairs) fd_help_pairs(fb, L, fb.lst[2] + P0, P0, hs->pshift, hs, st, pairs);
             else fd_help_slot(J.g, fb, L, tab, wcnt, fb.lst[2] + P0, fb.fd_w + P0, hs->n_i, hs, J.help_chunk, st,
                               wedges, pairs);
             wedges = (unsigned long long)wave_sum_i64((int64_t)wedges);
@@ -1546,6 +1550,41 @@ struct FdPairLds {
     int32_t pn[kFdPairWaves];
 };
 
+// Row space in workload order (fb.order: most induced wedges first),
+// greedily: a subset whose rows (contiguous in position order) still fit the
+// budget gets the shift that moves them to the next free place; one that
+// does not fit gets kNoRows (it walks) and the next ones are still tried.
+// One workgroup of kT threads: each chunk of kT subsets' capacities is
+// loaded in parallel, then placed by one thread.
+__global__ void k_fd_pair_place(FdBuffers fb, int32_t S, int64_t lim) {
+    __shared__ int64_t cap[kT], lo[kT];
+    __shared__ int32_t sid[kT];
+    int64_t used = 0;  // thread 0
+    for (int32_t k0 = 0; k0 < S; k0 += kT) {
+        const int32_t k = k0 + threadIdx.x;
+        if (k < S) {
+            const int32_t s = fb.order[k];
+            const int64_t a = fb.prow_off[fb.sub_off[s]];
+            sid[threadIdx.x] = s;
+            lo[threadIdx.x] = a;
+            cap[threadIdx.x] = fb.prow_off[fb.sub_off[s + 1]] - a;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int32_t n = min(kT, S - k0);
+            for (int32_t i = 0; i < n; ++i) {
+                if (used + cap[i] <= lim) {
+                    fb.pshift[sid[i]] = used - lo[i];
+                    used += cap[i];
+                } else {
+                    fb.pshift[sid[i]] = kNoRows;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Pair rows of the light vertices, every wave on its own (no workgroup
 // barrier): a wave takes 64 positions at a time, strided over the whole
 // range so that the hubs at the front of each subset (ranks ascend inside a
@@ -1554,7 +1593,7 @@ struct FdPairLds {
 // counters in a subset of at most kFdPairWaveKeys vertices, else a hash
 // table) and writes the pairs instead of decrementing.  The other vertices
 // go to the heavy list (one atomic per wave and chunk) for
-// k_fd_pair_rows_heavy.  Only subsets whose rows fit fb.pair_lim.
+// k_fd_pair_rows_heavy.  Only subsets with row space.
 __global__ void __launch_bounds__(kFdPairThreads)
 k_fd_pair_rows(DevGraph g, FdBuffers fb, const int32_t* __restrict__ state, int32_t* heavy, Ctl* ctl) {
     __shared__ FdPairLds L;
@@ -1578,7 +1617,7 @@ k_fd_pair_rows(DevGraph g, FdBuffers fb, const int32_t* __restrict__ state, int3
         if (c >= n_chunks) break;
         const int32_t p = (int32_t)min<int64_t>((int64_t)c + (int64_t)lane * n_chunks, (int64_t)n_a);
         int kind = -1;  // 0: counters, 1: hash, 2: heavy
-        int64_t P0 = 0, w = 0;
+        int64_t P0 = 0, w = 0, shift = kNoRows;
         int32_t n_i = 0;
         if (p < n_a) {
             const int32_t ux = fb.fd_vert[p];
@@ -1586,8 +1625,9 @@ k_fd_pair_rows(DevGraph g, FdBuffers fb, const int32_t* __restrict__ state, int3
             P0 = fb.sub_off[sub];
             n_i = (int32_t)(fb.sub_off[sub + 1] - P0);
             w = fb.fd_w[p];
+            shift = fb.pshift[sub];
             const int64_t d = g.a_off[ux + 1] - g.a_off[ux];
-            if (fb.prow_off[P0 + n_i] <= fb.pair_lim) {
+            if (shift != kNoRows) {
                 if (w < 2) fb.prow_n[p] = 0;
                 else if (n_i <= kFdPairWaveKeys && d <= 255 && w <= kFdPairDenseMax) kind = 0;
                 else if (w <= kFdPairHashMax) kind = 1;
@@ -1608,7 +1648,7 @@ k_fd_pair_rows(DevGraph g, FdBuffers fb, const int32_t* __restrict__ state, int3
             const int32_t pt = __shfl(p, t, kWave);
             const int64_t P0t = __shfl(P0, t, kWave), wt = __shfl(w, t, kWave);
             const int32_t n_it = __shfl(n_i, t, kWave), kt = __shfl(kind, t, kWave);
-            const int64_t r0 = fb.prow_off[pt];
+            const int64_t r0 = fb.prow_off[pt] + __shfl(shift, t, kWave);
             const FdPairWriter st{fb.fd_vert + P0t, fb.prow_w + r0, fb.prow_b + r0, &L.pn[wid]};
             const int32_t j = (int32_t)(pt - P0t);
             if (kt == 0) fd_update_wave_dense(g, fb, L, wcnt, j, n_it, st, wedges, unused);
@@ -1660,7 +1700,7 @@ k_fd_pair_rows_heavy(DevGraph g, FdBuffers fb, const int32_t* __restrict__ state
         const int32_t sub = state[ux];
         const int64_t P0 = fb.sub_off[sub];
         const int32_t n_i = (int32_t)(fb.sub_off[sub + 1] - P0);
-        const int64_t r0 = fb.prow_off[p];
+        const int64_t r0 = fb.prow_off[p] + fb.pshift[sub];
         const int64_t e0 = g.a_off[ux], d = g.a_off[ux + 1] - e0;
         const FdPairWriter st{fb.fd_vert + P0, fb.prow_w + r0, fb.prow_b + r0, &L.pn[NW]};
         fd_update_heavy(g, fb, L, sp, (int32_t)(p - P0), e0, d, n_i, st, wedges, unused, spills);
@@ -1775,8 +1815,8 @@ void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t 
     TIP_HIP_TRY(hipGetLastError());
 }
 
-void launch_fd_pairs(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, Ctl* ctl, const SpillArena& spill,
-                     int big_grid, int64_t* scan_tmp, bool on, hipStream_t s) {
+void launch_fd_pairs(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl,
+                     const SpillArena& spill, int big_grid, int64_t* scan_tmp, bool on, hipStream_t s) {
     fb.pairs_on = on && fb.pair_cap > 0 && g.n_a > 0 ? 1 : 0;
     if (!fb.pairs_on) return;
     // diagnostic: TIP_FD_PAIR_LIMIT=<entries> uses at most that many
@@ -1790,6 +1830,8 @@ void launch_fd_pairs(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, Ctl* ctl
     k_fd_pair_cap<<<grid1((int64_t)n_a + 1), kT, 0, s>>>(pb.state, fb.fd_vert, fb.sub_off, fb.fd_w, n_a, fb.prow_off);
     TIP_HIP_TRY(hipGetLastError());
     scan_exclusive_i64(fb.prow_off, fb.prow_off, (int64_t)n_a + 1, scan_tmp, s);
+    k_fd_pair_place<<<1, kT, 0, s>>>(fb, S, fb.pair_lim);
+    TIP_HIP_TRY(hipGetLastError());
     k_fd_reset_board<<<1, 256, 0, s>>>(fb.board);
     TIP_HIP_TRY(hipGetLastError());
     // the heavy list borrows the crossing list (written by the peeling
@@ -1807,8 +1849,8 @@ void launch_fd(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl
     if (g.n_a <= 0) return;
     launch_fd_setup(g, pb, fb, S, tmp_keys, tmp_vals, hist, scan_tmp, keys_scratch, vals_scratch, s,
                     tune.fd_dgm && tune.fd_huc_pct == 0);
-    launch_fd_pairs(g, pb, fb, ctl, spill, big_grid, scan_tmp, !tune.fd_walk && !tune.fd_dgm && tune.fd_huc_pct == 0,
-                    s);
+    launch_fd_pairs(g, pb, fb, S, ctl, spill, big_grid, scan_tmp,
+                    !tune.fd_walk && !tune.fd_dgm && tune.fd_huc_pct == 0, s);
     k_fd_reset_board<<<1, 256, 0, s>>>(fb.board);
     TIP_HIP_TRY(hipGetLastError());
     FdJobs jobs{};

@@ -125,6 +125,7 @@ void plan(Arena& ar, int32_t n_a, int32_t n_b, int64_t m, int32_t P, int slots, 
     w.fb.pair_lim = 0;
     w.fb.pairs_on = 0;
     w.fb.prow_off = pairs > 0 ? ar.take<int64_t>(na + 1) : nullptr;
+    w.fb.pshift = pairs > 0 ? ar.take<int64_t>(S) : nullptr;
     w.fb.prow_n = pairs > 0 ? ar.take<int32_t>(na) : nullptr;
     w.fb.prow_w = pairs > 0 ? ar.take<int32_t>(pairs) : nullptr;
     w.fb.prow_b = pairs > 0 ? ar.take<int64_t>(pairs) : nullptr;
@@ -456,7 +457,7 @@ tip_status run_front(Work& w, const int32_t* d_a, const int32_t* d_b, int32_t n_
             launch_fd_setup(g, pb, w.fb, S, w.ib.keys2, w.ib.vals2, w.ib.hist, w.ib.scan_tmp, w.ib.keys, w.ib.vals, s,
                             tune.fd_dgm && tune.fd_huc_pct == 0);
             if (S > 0)
-                launch_fd_pairs(g, pb, w.fb, w.ctl, w.spill, big_grid, w.ib.scan_tmp,
+                launch_fd_pairs(g, pb, w.fb, S, w.ctl, w.spill, big_grid, w.ib.scan_tmp,
                                 !tune.fd_walk && !tune.fd_dgm && tune.fd_huc_pct == 0, s);
         }
     }

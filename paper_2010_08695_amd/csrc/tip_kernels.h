@@ -129,6 +129,7 @@ struct FdHelpSlot {
     unsigned long long hword; // heavy updates: (published << 32) | next to take
     int32_t state;            // 0 unused, 1 open, 2 closed
     int32_t pairs;            // published entries are pair rows, taken kFdPairHelpChunk at a time
+    int64_t pshift;           // the subset's row shift (pair rows)
     int32_t job;              // index in the job list, -1 for the single job
     int32_t n_i;              // subset size
     int64_t P0;               // subset start (position)
@@ -168,9 +169,11 @@ struct FdBuffers {
     unsigned long long* task_trace;  // [4 * kFdTraceTasks] per-task timing (diagnostic)
     // Pair rows: row p (the vertex at subset position p) holds every w of
     // its subset with c(u, w) >= 2, as w's index inside the subset and
-    // C(c, 2).  A subset has rows iff pairs_on and its rows end within
-    // pair_cap entries.
-    int64_t* prow_off;   // [n_a + 1] row starts: exclusive scan of the row capacities
+    // C(c, 2).  Row space goes to the subsets in workload order, each that
+    // still fits the budget; row p starts at prow_off[p] + pshift[s] for its
+    // subset s, and a subset without rows has pshift kNoRows.
+    int64_t* prow_off;   // [n_a + 1] exclusive scan of the row capacities in position order
+    int64_t* pshift;     // [S]
     int32_t* prow_n;     // [n_a] entries of each row
     int32_t* prow_w;     // [pair_cap]
     int64_t* prow_b;     // [pair_cap]
@@ -267,10 +270,10 @@ struct FdJobs {
 void launch_fd_setup(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, uint64_t* tmp_keys,
                      int32_t* tmp_vals, int64_t* hist, int64_t* scan_tmp, uint64_t* keys_scratch,
                      int32_t* vals_scratch, hipStream_t s, bool runs);
-// Pair rows of every subset that fits fb.pair_cap (after launch_fd_setup);
-// off (fb.pairs_on = 0) when `on` is false.
-void launch_fd_pairs(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, Ctl* ctl, const SpillArena& spill,
-                     int big_grid, int64_t* scan_tmp, bool on, hipStream_t s);
+// Pair rows of the subsets that fit fb.pair_lim, taken in workload order
+// (after launch_fd_setup); off (fb.pairs_on = 0) when `on` is false.
+void launch_fd_pairs(const DevGraph& g, PeelBuffers& pb, FdBuffers& fb, int32_t S, Ctl* ctl,
+                     const SpillArena& spill, int big_grid, int64_t* scan_tmp, bool on, hipStream_t s);
 // Persistent peeling of the subsets of many graphs in one launch: tasks[t] =
 // job << 32 | subset, in the order they are to be taken; *head is the queue
 // head (reset here).
