@@ -307,10 +307,14 @@ __device__ inline void fd_rep_insert(FdLds& L, const Spill& sp, uint32_t k) {
 // kFdLdsVerts vertices keep supports, liveness, heavy flags and the vertex
 // lists in LDS for the whole task (the supports take LDS atomics, and the
 // next level's minimum is tracked on the fly); larger ones keep them in HBM.
+//
+// sup[x] of a peeled vertex holds its tip number (the level it was peeled
+// at; no update reads a peeled vertex's support), written out at the end of
+// the task.  A level's peeled vertices are listed in pl: per-wave ones from
+// the front, heavy ones after them.
 struct FdSmall {
     int64_t sup[kFdLdsVerts];
-    int32_t vert[kFdLdsVerts];
-    uint16_t lc[kFdLdsVerts], ln[kFdLdsVerts], pl[kFdLdsVerts], ph[kFdLdsVerts];
+    uint16_t lc[kFdLdsVerts], ln[kFdLdsVerts], pl[kFdLdsVerts];
     uint8_t flag[kFdLdsVerts];     // bit 0: alive, bit 1: heavy
     long long upd_min;             // least support left by this level's decrements
     int64_t red_min[kFdThreads / kWave];
@@ -366,8 +370,9 @@ struct FdRecountState {
 
 struct FdLdsState {
     FdSmall* S;
+    const int32_t* vert;  // the subset's vertices (HBM)
     __device__ inline bool live(int32_t w) const { return (S->flag[w] & kFdAlive) != 0; }
-    __device__ inline int32_t vtx(int32_t x) const { return S->vert[x]; }
+    __device__ inline int32_t vtx(int32_t x) const { return vert[x]; }
     __device__ inline void dec(int32_t w, int64_t d) const {
         const int64_t old = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&S->sup[w]),
                                                (unsigned long long)(-d));
@@ -1235,7 +1240,7 @@ __device__ inline void fd_peel_lds(const DevGraph& g, const FdBuffers& fb, const
     constexpr int kSh = kFdPack;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     uint32_t* wcnt = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(&L.u) + (size_t)wid * kFdWaveKeys);
-    const FdLdsState st{&S};
+    const FdLdsState st{&S, fb.fd_vert + P0};
     static_assert(sizeof(FdLds::Shared) >= (size_t)kFdLdsVerts * 6, "pair-row starts and lengths fit the union");
     int32_t* roff = reinterpret_cast<int32_t*>(&L.u);
     uint16_t* rn = reinterpret_cast<uint16_t*>(roff + kFdLdsVerts);
@@ -1244,7 +1249,6 @@ __device__ inline void fd_peel_lds(const DevGraph& g, const FdBuffers& fb, const
     for (int32_t j = tid; j < n_i; j += NT) {
         const int32_t v = fb.fd_vert[P0 + j];
         const int64_t s0 = init[v];
-        S.vert[j] = v;
         S.sup[j] = s0;
         S.flag[j] = kFdAlive | (!pr && fd_heavy(g, fb, P0, n_i, j) ? kFdHeavy : 0);
         S.lc[j] = (uint16_t)j;
@@ -1303,9 +1307,9 @@ __device__ inline void fd_peel_lds(const DevGraph& g, const FdBuffers& fb, const
                 ln[ok++] = (uint16_t)x;
             } else {
                 S.flag[x] &= (uint8_t)~kFdAlive;
-                fb.theta[S.vert[x]] = level;
+                S.sup[x] = level;
                 if (sx > 0) {
-                    if (S.flag[x] & kFdHeavy) S.ph[oh++] = (uint16_t)x;
+                    if (S.flag[x] & kFdHeavy) S.pl[n_light + oh++] = (uint16_t)x;
                     else S.pl[ol++] = (uint16_t)x;
                 }
             }
@@ -1324,7 +1328,7 @@ __device__ inline void fd_peel_lds(const DevGraph& g, const FdBuffers& fb, const
             for (int32_t q = fd_next_wave_item(L); q < n_light; q = fd_next_wave_item(L))
                 fd_update_wave_dense(g, fb, L, wcnt, (int32_t)S.pl[q], n_i, st, wedges, pairs);
             __syncthreads();
-            fd_heavy_level(g, fb, L, sp, S.ph, n_heavy, n_i, st, wedges, pairs, spills);
+            fd_heavy_level(g, fb, L, sp, S.pl + n_light, n_heavy, n_i, st, wedges, pairs, spills);
         }
         __syncthreads();
         mn = min<int64_t>(bmin, (int64_t)S.upd_min);
@@ -1333,6 +1337,8 @@ __device__ inline void fd_peel_lds(const DevGraph& g, const FdBuffers& fb, const
         ln = tmp;
         n_live = n_keep;
     }
+    // tip numbers, kept in sup since each vertex was peeled
+    for (int32_t j = tid; j < n_i; j += NT) fb.theta[fb.fd_vert[P0 + j]] = S.sup[j];
     if (pr) {
         // the update tables are all zero between uses
         uint32_t* z = reinterpret_cast<uint32_t*>(&L.u);

@@ -89,7 +89,7 @@ constexpr int kFdWaveSlots = 512;          // per-wave hash slots for light peel
 constexpr int64_t kFdWaveMax = 224;        // light: at most this many wedges inside the subset
 constexpr int kFdHistMax = 16384;          // subsets counted in LDS per workgroup at the fine-grained set-up
 constexpr int kFdTraceTasks = 4096;        // fine-grained tasks a diagnostic trace records
-constexpr int kFdLdsVerts = 2560;         // subsets up to this size keep their peeling state in LDS
+constexpr int kFdLdsVerts = 3584;         // subsets up to this size keep their peeling state in LDS
 constexpr int kFdWaveKeys = 10240;        // subsets up to this size: per-wave 8-bit counters per vertex
 constexpr int64_t kFdWaveDenseMax = 1024;  // ... for peeled vertices with at most this many wedges
 constexpr int kFdHelpMin = 4096;          // subsets from this size let idle workgroups take their per-wave updates
