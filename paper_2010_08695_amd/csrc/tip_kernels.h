@@ -2,6 +2,7 @@
 #pragma once
 
 #include "agg.h"
+#include "fd_tune.h"
 
 namespace tip {
 
