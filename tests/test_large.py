@@ -61,14 +61,18 @@ def _sample(theta, count, seed):
     return np.unique(np.concatenate(parts)).astype(np.int32)
 
 
-def test_large_skewed_both_sides(gpu_lib):
+def test_large_skewed_both_sides(gpu_lib, capsys):
     t0 = time.time()
 
     def log(msg):
-        print(f"[{time.time() - t0:6.1f}s] {msg}", flush=True)
+        # progress goes past pytest's capture: the steps below run for
+        # minutes without another test finishing
+        with capsys.disabled():
+            print(f"[{time.time() - t0:6.1f}s] {msg}", flush=True)
 
     with open(GOLDEN) as f:
         gold = json.load(f)
+    log("generating cl-100m-skew")
     g = gg.config_graph("cl-100m-skew")
     assert gg.graph_sha256(g) == gold["graph_sha256"]
     du = np.bincount(g.eu, minlength=g.n_u).astype(np.int64)
