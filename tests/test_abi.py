@@ -47,6 +47,35 @@ def test_struct_sizes():
     assert ctypes.sizeof(tip.Stats) == 14 * 8 + 6 * 8 + 5 * 8
 
 
+def _header_without_comments():
+    return re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+
+
+def test_binding_constants_match_the_header():
+    """Every TIP_FLAG_* and status value the header defines has the same value
+    in the binding, and the binding defines no flag the header lacks."""
+    src = _header_without_comments()
+    flags = {n: int(v) for n, v in re.findall(r"#define\s+(TIP_FLAG_[A-Z_]+)\s+(\d+)", src)}
+    assert flags and flags == {n: getattr(tip, n) for n in dir(tip) if n.startswith("TIP_FLAG_")}
+    assert len(set(flags.values())) == len(flags)
+    assert all(v & (v - 1) == 0 for v in flags.values())   # one bit each
+    status = dict(re.findall(r"\b(TIP_[A-Z]+)\s*=\s*(-?\d+)", src))
+    for name in ("TIP_OK", "TIP_EINVAL", "TIP_ENOMEM", "TIP_EDEVICE", "TIP_EOVERFLOW", "TIP_EBUSY"):
+        assert int(status[name]) == getattr(tip, name), name
+
+
+def test_stats_fields_match_the_header():
+    """tip.Stats lists tip_stats' fields in the header's order with the same
+    C types, so every field lands at its offset."""
+    body = re.search(r"typedef struct \{([^{}]*)\} tip_stats;", _header_without_comments()).group(1)
+    fields = []
+    for decl in filter(None, (d.strip() for d in body.split(";"))):
+        ctype, names = decl.split(None, 1)
+        fields += [(n.strip(), ctype) for n in names.split(",")]
+    want = {"int64_t": ctypes.c_int64, "double": ctypes.c_double}
+    assert [(n, want[t]) for n, t in fields] == list(tip.Stats._fields_)
+
+
 def _edges(n_u, n_v, eu, ev, m=None):
     eu = np.asarray(eu, np.int32)
     ev = np.asarray(ev, np.int32)
