@@ -953,7 +953,8 @@ __device__ inline void fd_compact_runs(const DevGraph& g, const FdBuffers& fb, F
 
 // Level loop of a subset whose state lives in HBM.  With pair rows (pr)
 // every peeled vertex is on the per-wave list and its row replaces the walk;
-// pair steps are not published on the help board.
+// a pair step with many peeled vertices and row entries is published on the
+// help board and taken kFdPairHelpChunk rows at a time.
 __device__ inline void fd_peel_hbm(const DevGraph& g, const FdBuffers& fb, const int64_t* __restrict__ init,
                                    int64_t P0, int32_t n_i, FdLds& L, unsigned long long* tab, const Spill& sp,
                                    FdHelpSlot* hs, int32_t help_chunk, int32_t help_level_min, int32_t huc_pct,
