@@ -323,17 +323,17 @@ __global__ void k_ctl_select_init(Ctl* ctl, long long tgt) {
     ctl->sel_tgt = tgt;
 }
 
-// findHi as a weighted radix select: one 8-bit digit per pass, most
+// findHi as a weighted radix select: one kSelBits-bit digit per pass, most
 // significant first.  The histogram adds w[u] over live u whose support
-// matches the prefix chosen so far.
+// matches the prefix chosen so far.  kT threads.
 __global__ void k_select_hist(const int32_t* __restrict__ live, int32_t n_live, const int64_t* __restrict__ supp,
                               const int64_t* __restrict__ wprox, int shift, const Ctl* ctl, int64_t* hist) {
     if (!ctl->sel_found) return;
-    __shared__ unsigned long long h[256];
-    h[threadIdx.x] = 0;
+    __shared__ unsigned long long h[kSelBins];
+    for (int i = threadIdx.x; i < kSelBins; i += blockDim.x) h[i] = 0;
     __syncthreads();
     const uint64_t prefix = ctl->sel_prefix;
-    const int hs = shift + 8;
+    const int hs = shift + kSelBits;
     const int lane = threadIdx.x & (kWave - 1);
     // the supports of a range cluster, so a wave's keys often share the
     // digit: then one LDS atomic adds the wave's sum
@@ -347,7 +347,7 @@ __global__ void k_select_hist(const int32_t* __restrict__ live, int32_t n_live, 
             const uint64_t key = (uint64_t)supp[u];
             if (hs >= 64 || (key >> hs) == (prefix >> hs)) {
                 ok = true;
-                dg = (uint32_t)((key >> shift) & 255);
+                dg = (uint32_t)((key >> shift) & (kSelBins - 1));
                 w = (unsigned long long)wprox[u];
             }
         }
@@ -363,29 +363,57 @@ __global__ void k_select_hist(const int32_t* __restrict__ live, int32_t n_live, 
         }
     }
     __syncthreads();
-    if (h[threadIdx.x]) atomicAdd(reinterpret_cast<unsigned long long*>(&hist[threadIdx.x]), h[threadIdx.x]);
+    for (int i = threadIdx.x; i < kSelBins; i += blockDim.x)
+        if (h[i]) atomicAdd(reinterpret_cast<unsigned long long*>(&hist[i]), h[i]);
 }
 
+// The digit of this pass: the first d with sel_cum + hist[0..d] >= target.
+// Thread t holds bins [t * PER, (t + 1) * PER); a block scan of their sums
+// finds the one thread whose bins cross the target, which walks them.  The
+// histogram is left zero for the next pass.  kT threads.
 __global__ void k_select_pick(int shift, Ctl* ctl, int64_t* hist) {
-    __shared__ long long hh[256];
-    hh[threadIdx.x] = hist[threadIdx.x];
-    hist[threadIdx.x] = 0;
+    constexpr int PER = kSelBins / kT;
+    static_assert(PER * kT == kSelBins, "bins split evenly over the threads");
+    __shared__ long long wsum[kT / kWave];
+    __shared__ int chosen;
+    __shared__ long long chosen_run;
+    const int t = threadIdx.x, lane = t & (kWave - 1), wid = t / kWave;
+    long long v[PER], s = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        v[i] = hist[t * PER + i];
+        hist[t * PER + i] = 0;
+        s += v[i];
+    }
+    const long long inc = wave_incl_scan_i64<kT>(s);
+    if (lane == kWave - 1) wsum[wid] = inc;
+    if (t == 0) chosen = -1;
     __syncthreads();
-    if (threadIdx.x == 0 && ctl->sel_found) {
-        long long run = ctl->sel_cum;
+    const bool found = ctl->sel_found != 0;
+    if (found) {
         const long long tgt = ctl->sel_tgt;
-        int chosen = -1;
-        for (int d = 0; d < 256; ++d) {
-            if (run + hh[d] >= tgt) {
-                chosen = d;
-                break;
+        long long before = ctl->sel_cum + inc - s;
+        for (int w = 0; w < wid; ++w) before += wsum[w];
+        // prefix sums never decrease, so one thread crosses (thread 0 also
+        // when sel_cum alone reaches the target)
+        if ((t == 0 || before < tgt) && before + s >= tgt) {
+            long long run = before;
+            for (int i = 0; i < PER; ++i) {
+                if (run + v[i] >= tgt) {
+                    chosen = t * PER + i;
+                    chosen_run = run;
+                    break;
+                }
+                run += v[i];
             }
-            run += hh[d];
         }
+    }
+    __syncthreads();
+    if (t == 0 && found) {
         if (chosen < 0) {
             ctl->sel_found = 0;
         } else {
-            ctl->sel_cum = run;
+            ctl->sel_cum = chosen_run;
             ctl->sel_prefix |= (unsigned long long)chosen << shift;
         }
     }
@@ -1260,7 +1288,7 @@ void launch_peel_setup(const DevGraph& g, const int32_t* deg_b_rank, PeelBuffers
                        hipStream_t s) {
     fill_i64(pb.wprox, 0, g.n_a, s);
     // the select histogram is cleared after every use, so it starts cleared
-    fill_i64(pb.sel_hist, 0, 256, s);
+    fill_i64(pb.sel_hist, 0, kSelBins, s);
     if (g.m > 0) {
         k_wproxy<<<grid1(g.m), kT, 0, s>>>(g, deg_b_rank, pb.wprox);
         TIP_HIP_TRY(hipGetLastError());
@@ -1339,13 +1367,13 @@ void launch_select(PeelBuffers& pb, int cur_live, int32_t n_live, uint64_t max_s
     k_ctl_select_init<<<1, 1, 0, s>>>(ctl, (long long)tgt);
     TIP_HIP_TRY(hipGetLastError());
     const int bits = bits_for(max_supp);
-    const int passes = (bits + 7) / 8;
+    const int passes = (bits + kSelBits - 1) / kSelBits;
     for (int p = passes - 1; p >= 0; --p) {
-        const int shift = 8 * p;
+        const int shift = kSelBits * p;
         k_select_hist<<<grid1(n_live, 256), kT, 0, s>>>(pb.live[cur_live], n_live, pb.supp, pb.wprox, shift, ctl,
                                                           pb.sel_hist);
         TIP_HIP_TRY(hipGetLastError());
-        k_select_pick<<<1, 256, 0, s>>>(shift, ctl, pb.sel_hist);
+        k_select_pick<<<1, kT, 0, s>>>(shift, ctl, pb.sel_hist);
         TIP_HIP_TRY(hipGetLastError());
     }
 }

@@ -88,7 +88,7 @@ void plan(Arena& ar, int32_t n_a, int32_t n_b, int64_t m, int32_t P, int slots, 
     for (int i = 0; i < 2; ++i) w.pb.live[i] = ar.take<int32_t>(na);
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < kBins; ++j) w.pb.front[i][j] = ar.take<int32_t>(na);
-    w.pb.sel_hist = ar.take<int64_t>(256);
+    w.pb.sel_hist = ar.take<int64_t>(kSelBins);
     w.pb.bin = ar.take<uint8_t>(na);
     w.pb.tk = dense_tile_keys(na);
     // the bitmap path walks whole table tiles of at most kBmTile keys

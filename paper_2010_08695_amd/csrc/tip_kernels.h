@@ -87,6 +87,10 @@ struct CountBuffers {
     int32_t* items_big;
 };
 
+// findHi's radix select: digit width and histogram bins.
+constexpr int kSelBits = 11;
+constexpr int kSelBins = 1 << kSelBits;
+
 struct PeelBuffers {
     int64_t* supp;       // [n_a] raw supports (= bfly_a)
     int64_t* wprox;      // [n_a] wedges of u in the original graph
@@ -94,7 +98,7 @@ struct PeelBuffers {
     int64_t* init;       // [n_a] support at the start of u's range
     int32_t* live[2];    // [n_a] live lists (ping-pong)
     int32_t* front[2][kBins];  // [buffer][bin] frontier lists
-    int64_t* sel_hist;   // [256]
+    int64_t* sel_hist;   // [kSelBins]
     uint8_t* bin;        // [n_a] update kernel of each vertex
     int32_t* tb;         // [n_b * (ntt + 1)] tile bounds of every CD list
     int32_t tk;          // keys per tile (dense_tile_keys(n_a))
