@@ -112,7 +112,8 @@ typedef struct {
  * the list of every w in U_i with c = |N(u) ∩ N(w)| >= 2 and C(c, 2): the
  * update of u in Alg. 4, which does not change while U_i is peeled because
  * the other side is never peeled.  The rows of a subset are built only if
- * they fit the workspace's pair budget (tip_workspace_size includes it);
+ * they fit the workspace's pair budget (16 entries of 12 bytes per edge, at
+ * most 2^31 entries; tip_workspace_size includes it);
  * other subsets, and every subset under TIP_FLAG_FD_DGM or tune[7], walk.
  * Same results. */
 #define TIP_FLAG_FD_WALK 256

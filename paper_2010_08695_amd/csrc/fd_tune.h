@@ -23,7 +23,8 @@ constexpr int kFdPassUnroll = 8;          // live-list entries per thread in fli
 constexpr int kFdHelpHeavyMin = 2;        // levels with this many heavy updates of a large subset publish them,
 constexpr int64_t kFdHelpHeavyWedges = 1 << 18;  // ... when they hold at least this many induced wedges
 constexpr int64_t kNoRows = INT64_MIN;     // row shift of a subset without pair rows
-constexpr int64_t kFdPairsPerEdge = 16;   // pair-row entries a workspace holds per edge
+constexpr int64_t kFdPairsPerEdge = 16;   // pair-row entries a workspace holds per edge,
+constexpr int64_t kFdPairsMax = int64_t(1) << 31;  // ... and at most this many (24 GiB)
 constexpr int kFdPairHelpMin = 512;       // pair-row steps with this many peeled vertices ...
 constexpr int64_t kFdPairHelpEntries = 1 << 16;  // ... and this many row entries go on the help board
 constexpr int kFdPairHelpChunk = 256;     // peeled vertices (rows) a workgroup takes at once from the board

@@ -207,7 +207,7 @@ struct Tune {
 // fine-grained update walks its wedges).
 inline int64_t fd_pair_entries(int64_t m, const Tune& t) {
     if (t.fd_walk || t.fd_dgm || t.fd_huc_pct > 0) return 0;
-    return kFdPairsPerEdge * std::max<int64_t>(m, 1);
+    return std::min(kFdPairsMax, kFdPairsPerEdge * std::max<int64_t>(m, 1));
 }
 
 // counting
