@@ -157,3 +157,10 @@ def test_fd_trace_critical_path(tmp_path, capsys):
     assert "3 tasks" in out and "launch span 0.90 ms" in out and "at most 100 in one subset" in out
     tops = [l for l in out.splitlines() if l.strip().startswith("task ") and "n_i" in l]
     assert len(tops) == 2 and "n_i    3000" in tops[0] and "9.0 us/level" in tops[0]
+
+
+def test_traffic_record_matches_the_dense_kernel_source():
+    """The committed HBM-traffic record of the dominant kernel was taken with
+    its current source (otherwise the bench line reports traffic null): after
+    a change to that kernel the counter runs must be repeated."""
+    assert bench.load_traffic("cl-10m") is not None, bench.kernel_source_sha()
